@@ -1,0 +1,359 @@
+/*
+ * aiwc.h -- C ABI of libaiwc, an MI355X (gfx950) implementation of the
+ * data-parallel reduction at the heart of AIWC (Architecture-Independent
+ * Workload Characterization, Johnston & Milthorpe, arXiv 1805.04207).
+ *
+ * A *trace* is the stream of events that an interpreted OpenCL kernel emits
+ * to the AIWC plugin (paper, Section "Implementation": instructionExecuted,
+ * workItemBegin, memoryLoad/Store/AtomicLoad/AtomicStore, barrier events).
+ * libaiwc takes that stream as structure-of-arrays already resident in HBM
+ * and reduces it, entirely in HIP kernels, to the metrics of the paper's
+ * Table I ("Metrics collected by the AIWC tool ordered by type").
+ *
+ * Conventions for every entry point:
+ *   - Every call returns an aiwc_status.  On anything but AIWC_OK no
+ *     out-parameter is written; aiwc_last_error(ctx) holds a message.
+ *   - "device pointer" = memory allocated on the context's HIP device
+ *     (hipMalloc, a torch CUDA tensor, ...).  It is BORROWED: the caller keeps
+ *     it alive and unmodified until the work that reads it has completed
+ *     (aiwc_metrics_read returned, or the stream was synchronized).
+ *   - "host pointer" = ordinary process memory; it is read (copied) during the
+ *     call and may be released when the call returns.
+ *   - A stream argument is a hipStream_t passed as void*; NULL = the null stream.
+ *   - One context per host thread.  Traces and metrics belong to the context
+ *     that created them and must not outlive it.
+ */
+#ifndef AIWC_H
+#define AIWC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ status */
+typedef enum aiwc_status {
+  AIWC_OK = 0,
+  AIWC_ERR_INVALID_ARG = 1,   /* bad pointer, size, flag, or trace content   */
+  AIWC_ERR_INCONSISTENT = 2,  /* opcode kinds disagree with stream lengths   */
+  AIWC_ERR_OUT_OF_MEMORY = 3, /* device allocation failed / over the cap     */
+  AIWC_ERR_HIP = 4,           /* a HIP runtime call failed                   */
+  AIWC_ERR_UNSUPPORTED = 5    /* valid request this build does not handle    */
+} aiwc_status;
+
+/* ------------------------------------------------------------- opcode kinds
+ * The role an opcode plays in the event stream.  COMPUTE/OTHER only feed the
+ * opcode and SIMD metrics; LOAD/STORE/ATOMIC_RMW announce memory events;
+ * BRANCH_COND announces one branch event; BARRIER closes an
+ * instructions-to-barrier segment (Table I, Parallelism rows).              */
+enum {
+  AIWC_KIND_COMPUTE = 0,
+  AIWC_KIND_LOAD = 1,
+  AIWC_KIND_STORE = 2,
+  AIWC_KIND_ATOMIC_RMW = 3,  /* one instruction = a read and a write event  */
+  AIWC_KIND_BRANCH_COND = 4,
+  AIWC_KIND_BARRIER = 5,
+  AIWC_KIND_OTHER = 6
+};
+
+/* mem_kind bits of one memory event.  Bit 0: the event is a write (store, or
+ * the store half of an atomic).  Bit 1: the address is in the local (work-group
+ * shared) address space; clear = global.  All other bits must be zero.      */
+enum { AIWC_MEM_WRITE = 1u, AIWC_MEM_LOCAL = 2u };
+
+/* Per-opcode-id description, indexed by the u16 opcode id of the stream.
+ * op_class groups ids into the "unique opcodes" of Table I: the paper counts
+ * LLVM opcode *names* (Implementation section, opcode map), so ids that are
+ * width variants of one name share a class.  simd_width is the number of
+ * data items the instruction's result holds (Implementation section, SIMD
+ * paragraph); scalar and void results use 1.                               */
+typedef struct aiwc_opcode_info {
+  uint16_t op_class;   /* < 65535                                           */
+  uint8_t simd_width;  /* >= 1                                              */
+  uint8_t kind;        /* AIWC_KIND_*                                       */
+} aiwc_opcode_info;
+
+/* trace flags */
+enum {
+  AIWC_VALIDATE_ON_DEVICE = 1u  /* aiwc_trace_create runs a validation kernel
+                                   over every array and synchronizes        */
+};
+
+/* One kernel launch's event trace (structure of arrays).
+ *
+ *   opcode[n_events]          device, u16 ids; work-item w's instructions are
+ *                             opcode[wi_offsets[w] .. wi_offsets[w+1]) in
+ *                             execution order.
+ *   wi_offsets[n_workitems+1] device, non-decreasing, [0] = 0,
+ *                             [n_workitems] = n_events.
+ *   addr[n_mem], mem_kind[n_mem]
+ *                             device; the byte address of each memory event
+ *                             (its start address) and AIWC_MEM_* bits.  Order
+ *                             is free: memory metrics are order independent.
+ *                             addr == UINT64_MAX is reserved (rejected).
+ *   br_site[n_branch], br_taken[n_branch]
+ *                             device; each conditional-branch event's static
+ *                             site id (< n_sites) and outcome (0/1), in the
+ *                             order the branches executed.  Only the relative
+ *                             order of events of the same site matters.
+ *   opcode_table[n_opcode_ids] HOST; copied at create time.
+ *   history_len               branch history length m, 1..32 (the paper fixes
+ *                             16: Metrics section, branch paragraph).
+ *   max_lsb_skip              must be 10 (skips 0..10: Table I memory entropy
+ *                             rows and the LMAE paragraph of Metrics).
+ * Per-trace limits: n_mem < 2^32, n_branch < 2^32, n_sites < 2^31.          */
+typedef struct aiwc_trace_desc {
+  uint32_t struct_size;   /* = sizeof(aiwc_trace_desc)                       */
+  uint32_t flags;         /* AIWC_VALIDATE_ON_DEVICE, ...                    */
+  uint64_t n_events;
+  const uint16_t *opcode;
+  uint64_t n_workitems;
+  const uint64_t *wi_offsets;
+  uint32_t wg_size;       /* work-group size (informational, sizing feature) */
+  uint32_t n_opcode_ids;
+  const aiwc_opcode_info *opcode_table;
+  uint64_t n_mem;
+  const uint64_t *addr;
+  const uint8_t *mem_kind;
+  uint64_t n_branch;
+  const uint32_t *br_site;
+  const uint8_t *br_taken;
+  uint32_t n_sites;
+  uint32_t history_len;
+  uint32_t max_lsb_skip;
+  uint32_t reserved;
+} aiwc_trace_desc;
+
+#define AIWC_NSKIP 11        /* LSB skips 0..10                            */
+#define AIWC_SPACE_GLOBAL 0
+#define AIWC_SPACE_LOCAL 1
+
+/* Memory metrics of one address space (Table I, Memory rows).  The paper's
+ * named scalars refer to the global space; the same set is reported for the
+ * local space.  distinct[k] / entropy[k] are taken over the addresses with
+ * their k least significant bits dropped (a >> k): k = 0 is the global
+ * memory address entropy, k = 1..10 the local (spatial-locality) entropy
+ * curve of the Metrics section.  Entropy is Shannon's, base 2, plug-in.    */
+typedef struct aiwc_space_metrics {
+  uint64_t total_accesses;          /* reads + writes                        */
+  uint64_t total_reads;
+  uint64_t total_writes;
+  uint64_t unique_reads;            /* distinct addresses read               */
+  uint64_t unique_writes;           /* distinct addresses written            */
+  uint64_t footprint;               /* distinct addresses (= distinct[0])    */
+  uint64_t footprint_90;            /* fewest addresses covering 90% of
+                                       accesses, most-accessed first          */
+  uint64_t distinct[AIWC_NSKIP];
+  double entropy[AIWC_NSKIP];
+  double unique_rw_ratio;           /* unique_reads / unique_writes          */
+  double reread_ratio;              /* unique_reads / total_reads            */
+  double rewrite_ratio;             /* unique_writes / total_writes          */
+} aiwc_space_metrics;
+
+/* All metrics of one trace.  Ratios are IEEE double divisions of the exact
+ * integers (x/0 = +inf, 0/0 = NaN).  Medians of an even count are the mean
+ * of the two middle values.                                                 */
+typedef struct aiwc_metrics_host {
+  uint32_t struct_size;             /* filled by aiwc_metrics_read           */
+  uint32_t history_len;
+  /* compute (Table I, Compute rows) */
+  uint64_t total_instructions;
+  uint32_t unique_opcodes;          /* classes executed at least once        */
+  uint32_t opcodes_90;              /* fewest classes covering 90% of
+                                       dynamic instructions                  */
+  uint64_t simd_max;
+  uint64_t simd_sum;                /* S1 = sum of widths (exact)            */
+  uint64_t simd_sumsq_lo;           /* S2 = sum of squared widths, 128-bit   */
+  uint64_t simd_sumsq_hi;
+  double simd_mean;                 /* S1 / N                                */
+  double simd_sd;                   /* population SD = sqrt(N*S2 - S1^2) / N */
+  /* parallelism (Table I, Parallelism rows) */
+  uint64_t work_items;
+  uint64_t barriers_hit;            /* explicit barrier events               */
+  uint64_t itb_count;               /* segments = barriers_hit + work_items  */
+  uint64_t itb_sum;                 /* = total_instructions                  */
+  uint64_t itb_min, itb_max;
+  double itb_median;
+  uint64_t ipt_min, ipt_max;
+  double ipt_median;
+  /* memory */
+  aiwc_space_metrics space[2];      /* [AIWC_SPACE_GLOBAL], [AIWC_SPACE_LOCAL] */
+  /* control (Table I, Control rows) */
+  uint64_t total_branches;
+  uint64_t unique_branches;         /* sites executed at least once          */
+  uint64_t branches_90;             /* fewest sites covering 90% of branches */
+  uint64_t n_windows;               /* history windows: sum_s max(0, n_s - m) */
+  uint64_t albe_min_sum;            /* sum over (site, history) of min(n0,n1) */
+  double yokota_entropy;            /* H(outcome | site, history), in [0,1]  */
+  double linear_branch_entropy;     /* 2 * albe_min_sum / n_windows          */
+  /* bookkeeping */
+  uint32_t overflow_redos;          /* on-chip table overflows redone        */
+  uint32_t partitions;              /* memory partitions used (both spaces)  */
+} aiwc_metrics_host;
+
+typedef struct aiwc_ctx aiwc_ctx;
+typedef struct aiwc_trace aiwc_trace;
+typedef struct aiwc_metrics aiwc_metrics;
+
+/* --------------------------------------------------------------- contexts */
+
+/* Create a context on HIP device `hip_device`.  Owns scratch memory, the
+ * tuning cache and the sizing network.  Errors: INVALID_ARG (null out, bad
+ * device), HIP.                                                            */
+aiwc_status aiwc_context_create(int hip_device, aiwc_ctx **out);
+/* Destroy a context; waits for its outstanding work.  NULL is a no-op.     */
+aiwc_status aiwc_context_destroy(aiwc_ctx *ctx);
+/* Last error message of the context ("" if none).  Never NULL.  Valid until
+ * the next call on the context.  ctx may be NULL (then: messages of calls
+ * that had no context).                                                     */
+const char *aiwc_last_error(const aiwc_ctx *ctx);
+
+/* ----------------------------------------------------------------- traces */
+
+/* Describe a trace.  Checks the descriptor on the host (null pointers with
+ * non-zero sizes, history_len in 1..32, max_lsb_skip == 10, n_sites >= 1 when
+ * n_branch > 0, limits above, opcode table entries) and copies opcode_table
+ * to the device.  With AIWC_VALIDATE_ON_DEVICE it also checks the arrays
+ * (offsets non-decreasing with [0] = 0 and [n_workitems] = n_events;
+ * mem_kind bits; br_taken in {0,1}; br_site < n_sites; addr != UINT64_MAX;
+ * opcode ids < n_opcode_ids) and returns INVALID_ARG on the first violation
+ * class found, or INCONSISTENT when #LOAD + #STORE + 2 #ATOMIC_RMW != n_mem
+ * or #BRANCH_COND != n_branch.  Without the flag those content errors are
+ * the caller's responsibility (the consistency check still runs at
+ * characterize time).                                                       */
+aiwc_status aiwc_trace_create(aiwc_ctx *ctx, const aiwc_trace_desc *desc,
+                              aiwc_trace **out);
+aiwc_status aiwc_trace_destroy(aiwc_trace *trace);
+
+/* ----------------------------------------------------------- characterize */
+
+/* Enqueue the full reduction of one trace on `stream` (the paper's kernelEnd
+ * statistics, Implementation section) and return a metrics handle at once.
+ * All arithmetic runs in HIP kernels; nothing is copied to the host until
+ * aiwc_metrics_read.  On-chip table overflow is never an error: the kernels
+ * redo the affected partition with more rounds (results stay exact).
+ * Errors: INVALID_ARG, OUT_OF_MEMORY, HIP.                                   */
+aiwc_status aiwc_characterize(aiwc_ctx *ctx, const aiwc_trace *trace,
+                              void *stream, aiwc_metrics **out);
+
+/* Sizing policy for the memory partitions and on-chip tables.             */
+typedef enum aiwc_sizing {
+  AIWC_SIZING_BOUND = 0,      /* distinct <= accesses: never undersized     */
+  AIWC_SIZING_HEURISTIC = 1,  /* extrapolate distinct counts of a prefix    */
+  AIWC_SIZING_LEARNED = 2     /* the context's sizing network (MLP)        */
+} aiwc_sizing;
+
+typedef enum aiwc_autotune {
+  AIWC_AUTOTUNE_OFF = 0,      /* built-in launch shapes                     */
+  AIWC_AUTOTUNE_CACHED = 1,   /* use the tuning cache, defaults on a miss   */
+  AIWC_AUTOTUNE_SEARCH = 2    /* time candidates on a miss, then cache      */
+} aiwc_autotune;
+
+typedef struct aiwc_batch_opts {
+  uint32_t struct_size;             /* = sizeof(aiwc_batch_opts)             */
+  uint32_t sizing;                  /* aiwc_sizing                           */
+  uint32_t autotune;                /* aiwc_autotune                         */
+  uint32_t use_graph;               /* capture the batch in a hipGraph       */
+  uint64_t admission_cap_bytes;     /* scratch budget per wave; 0 = 200 GiB  */
+  uint32_t force_partition_log2;    /* debug: force global partitions 2^x
+                                       (undersize => redo path), 0 = off     */
+  uint32_t reserved;
+} aiwc_batch_opts;
+
+/* Characterize n traces as one batch: the traces are bin-packed into waves
+ * whose scratch fits admission_cap_bytes, and each wave's stages run as
+ * batch-wide persistent launches over a longest-first work list (optionally
+ * replayed from a captured hipGraph).  out[i] receives trace i's metrics.
+ * Results are bit-identical to aiwc_characterize on each trace.
+ * Errors: INVALID_ARG, OUT_OF_MEMORY (one trace alone exceeds the cap), HIP. */
+aiwc_status aiwc_characterize_batch(aiwc_ctx *ctx,
+                                    const aiwc_trace *const *traces, size_t n,
+                                    const aiwc_batch_opts *opts, void *stream,
+                                    aiwc_metrics **out);
+
+/* Statistics of the last aiwc_characterize_batch call of the context.     */
+typedef struct aiwc_batch_stats {
+  uint32_t struct_size;
+  uint32_t waves;                   /* admission waves launched              */
+  uint64_t reserved_bytes;          /* peak scratch reserved by a wave       */
+  uint64_t redo_partitions;         /* partitions redone after overflow      */
+  uint64_t total_partitions;
+  double plan_ms;                   /* host planning time                    */
+} aiwc_batch_stats;
+aiwc_status aiwc_batch_last_stats(const aiwc_ctx *ctx, aiwc_batch_stats *out);
+
+/* Wait for the metrics' work and copy the result to the host (one D2H copy).
+ * Errors: INVALID_ARG (null), INCONSISTENT (see aiwc_trace_create), HIP.    */
+aiwc_status aiwc_metrics_read(aiwc_metrics *m, aiwc_metrics_host *out);
+/* Per-class instruction counts (index = op_class), len entries (host).     */
+aiwc_status aiwc_metrics_class_hist(aiwc_metrics *m, uint64_t *out, size_t len);
+/* Count-of-counts spectrum of one space at LSB skip 0: pairs (f, m_f) =
+ * "m_f distinct addresses were accessed exactly f times", ascending f.
+ * Writes at most cap pairs (host arrays) and the total number of pairs to
+ * *n_out.                                                                   */
+aiwc_status aiwc_metrics_spectrum(aiwc_metrics *m, int space, uint64_t *f,
+                                  uint64_t *mf, size_t cap, size_t *n_out);
+aiwc_status aiwc_metrics_destroy(aiwc_metrics *m);
+
+/* ----------------------------------------------------- learned sizing (MLP)
+ * A 40 -> 64 -> 64 -> 64 -> 11 perceptron (exact-erf GELU, bf16 weights,
+ * fp32 accumulation) predicts log2 of the global-space distinct counts at
+ * skips 0..10 from features of a 65,536-event prefix.  The predictions size
+ * the memory partitions; overflow is redone, so results never depend on them.
+ */
+#define AIWC_N_FEATURES 40
+#define AIWC_N_TARGETS 11
+#define AIWC_MLP_HIDDEN 64
+
+/* Features of n traces into dev_out[n][40] (device, fp32, raw = not yet
+ * normalized).                                                              */
+aiwc_status aiwc_sizer_features(aiwc_ctx *ctx, const aiwc_trace *const *traces,
+                                size_t n, void *stream, float *dev_out);
+
+typedef struct aiwc_train_opts {
+  uint32_t struct_size;
+  uint32_t epochs;
+  uint32_t batch;
+  uint32_t seed;
+  float lr;
+  float beta1, beta2, eps;
+  uint32_t reserved;
+} aiwc_train_opts;
+
+/* Train the context's network on (dev_x[n][40] raw features, dev_y[n][11]
+ * log2 targets), device fp32.  Feature/target normalization statistics are
+ * taken from this training set.  *loss_out (host, nullable) receives the
+ * final epoch's mean squared error (normalized units).                      */
+aiwc_status aiwc_sizer_train(aiwc_ctx *ctx, const float *dev_x,
+                             const float *dev_y, size_t n,
+                             const aiwc_train_opts *opts, void *stream,
+                             float *loss_out);
+/* Predict log2 distinct counts dev_y[n][11] from raw features dev_x[n][40]. */
+aiwc_status aiwc_sizer_predict(aiwc_ctx *ctx, const float *dev_x, size_t n,
+                               void *stream, float *dev_y);
+/* One forward + backward pass on normalized inputs (device fp32
+ * dev_xn[n][40], dev_yn[n][11]) with the current weights; writes the mean
+ * squared error to *loss (host) and the gradients of every parameter, in
+ * aiwc_sizer_get_params order, to host_grad (fp32, count from
+ * aiwc_sizer_num_params).                                                   */
+aiwc_status aiwc_sizer_grad(aiwc_ctx *ctx, const float *dev_xn,
+                            const float *dev_yn, size_t n, void *stream,
+                            float *loss, float *host_grad);
+size_t aiwc_sizer_num_params(void);
+/* Parameters as fp32 values of the bf16 weights: W1[64][40], b1[64],
+ * W2[64][64], b2[64], W3[64][64], b3[64], W4[11][64], b4[11]; then the
+ * normalization: x_mean[40], x_std[40], y_mean[11], y_std[11].  set_params
+ * rounds weights to bf16 (nearest-even).                                   */
+aiwc_status aiwc_sizer_get_params(const aiwc_ctx *ctx, float *host_params);
+aiwc_status aiwc_sizer_set_params(aiwc_ctx *ctx, const float *host_params);
+aiwc_status aiwc_sizer_save(const aiwc_ctx *ctx, const char *path);
+aiwc_status aiwc_sizer_load(aiwc_ctx *ctx, const char *path);
+/* Margin (in log2 units) added to predictions before sizing.               */
+aiwc_status aiwc_sizer_set_margin(aiwc_ctx *ctx, float margin_log2);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AIWC_H */

@@ -1,0 +1,172 @@
+"""CPU oracle for the AIWC metrics -- TEST INFRASTRUCTURE ONLY.
+
+``liboracle.so`` (aiwc_oracle.c) is a plain restatement of the paper's
+Table I definitions (arXiv 1805.04207); ``brute.py`` restates them once more
+in pure Python with 50-digit mpmath arithmetic for tiny inputs.  Only the
+tests, ``__graft_entry__.smoke()`` and the CPU-baseline leg of ``bench.py``
+may import this package; the product path never does.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Dict
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB = os.path.join(HERE, "liboracle.so")
+
+
+def build() -> str:
+    """Compile the C oracle (gcc, host only)."""
+    cmd = ["gcc", "-O2", "-std=gnu11", "-Wall", "-Wextra", "-fPIC", "-shared",
+           os.path.join(HERE, "aiwc_oracle.c"), "-o", LIB, "-lm"]
+    subprocess.run(cmd, check=True)
+    return LIB
+
+
+class OrcOpinfo(ctypes.Structure):
+    _fields_ = [("op_class", ctypes.c_uint16), ("simd_width", ctypes.c_uint8),
+                ("kind", ctypes.c_uint8)]
+
+
+class OrcTrace(ctypes.Structure):
+    _fields_ = [("n_events", ctypes.c_uint64), ("opcode", ctypes.c_void_p),
+                ("n_wi", ctypes.c_uint64), ("wi_offsets", ctypes.c_void_p),
+                ("n_ids", ctypes.c_uint32), ("n_sites", ctypes.c_uint32),
+                ("table", ctypes.c_void_p), ("n_mem", ctypes.c_uint64),
+                ("addr", ctypes.c_void_p), ("mem_kind", ctypes.c_void_p),
+                ("n_branch", ctypes.c_uint64), ("br_site", ctypes.c_void_p),
+                ("br_taken", ctypes.c_void_p), ("history_len", ctypes.c_uint32),
+                ("pad", ctypes.c_uint32)]
+
+
+class OrcSpace(ctypes.Structure):
+    _fields_ = [("total_accesses", ctypes.c_uint64), ("total_reads", ctypes.c_uint64),
+                ("total_writes", ctypes.c_uint64), ("unique_reads", ctypes.c_uint64),
+                ("unique_writes", ctypes.c_uint64), ("footprint", ctypes.c_uint64),
+                ("footprint_90", ctypes.c_uint64), ("distinct", ctypes.c_uint64 * 11),
+                ("entropy", ctypes.c_double * 11), ("unique_rw_ratio", ctypes.c_double),
+                ("reread_ratio", ctypes.c_double), ("rewrite_ratio", ctypes.c_double)]
+
+
+class OrcResult(ctypes.Structure):
+    _fields_ = [("total_instructions", ctypes.c_uint64), ("unique_opcodes", ctypes.c_uint64),
+                ("opcodes_90", ctypes.c_uint64), ("simd_max", ctypes.c_uint64),
+                ("simd_sum", ctypes.c_uint64), ("simd_sumsq_lo", ctypes.c_uint64),
+                ("simd_sumsq_hi", ctypes.c_uint64), ("simd_mean", ctypes.c_double),
+                ("simd_sd", ctypes.c_double), ("work_items", ctypes.c_uint64),
+                ("barriers_hit", ctypes.c_uint64), ("itb_count", ctypes.c_uint64),
+                ("itb_sum", ctypes.c_uint64), ("itb_min", ctypes.c_uint64),
+                ("itb_max", ctypes.c_uint64), ("itb_median", ctypes.c_double),
+                ("ipt_min", ctypes.c_uint64), ("ipt_max", ctypes.c_uint64),
+                ("ipt_median", ctypes.c_double), ("space", OrcSpace * 2),
+                ("total_branches", ctypes.c_uint64), ("unique_branches", ctypes.c_uint64),
+                ("branches_90", ctypes.c_uint64), ("n_windows", ctypes.c_uint64),
+                ("albe_min_sum", ctypes.c_uint64), ("yokota_entropy", ctypes.c_double),
+                ("linear_branch_entropy", ctypes.c_double)]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build()
+        L = ctypes.CDLL(LIB)
+        L.orc_characterize.argtypes = [ctypes.POINTER(OrcTrace), ctypes.POINTER(OrcResult)]
+        L.orc_class_hist.argtypes = [ctypes.POINTER(OrcTrace), ctypes.c_void_p, ctypes.c_size_t]
+        L.orc_spectrum.argtypes = [ctypes.POINTER(OrcTrace), ctypes.c_int, ctypes.c_int,
+                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                   ctypes.POINTER(ctypes.c_size_t)]
+        _lib = L
+    return _lib
+
+
+def _as(a, dt):
+    return np.ascontiguousarray(np.asarray(a, dtype=dt))
+
+
+class _Bound:
+    """Keeps numpy buffers alive while the C struct points at them."""
+
+    def __init__(self, tr):
+        tab = np.asarray(tr.table)
+        self.opcode = _as(tr.opcode, np.uint16)
+        self.off = _as(tr.wi_offsets, np.uint64)
+        self.tab = np.zeros(len(tab), dtype=[("op_class", "<u2"), ("simd_width", "u1"), ("kind", "u1")])
+        self.tab["op_class"] = tab["op_class"]
+        self.tab["simd_width"] = tab["simd_width"]
+        self.tab["kind"] = tab["kind"]
+        self.addr = _as(tr.addr, np.uint64)
+        self.kind = _as(tr.mem_kind, np.uint8)
+        self.site = _as(tr.br_site, np.uint32)
+        self.taken = _as(tr.br_taken, np.uint8)
+        t = OrcTrace()
+        t.n_events = self.opcode.size
+        t.opcode = self.opcode.ctypes.data
+        t.n_wi = self.off.size - 1
+        t.wi_offsets = self.off.ctypes.data
+        t.n_ids = len(self.tab)
+        t.n_sites = int(tr.n_sites)
+        t.table = self.tab.ctypes.data
+        t.n_mem = self.addr.size
+        t.addr = self.addr.ctypes.data
+        t.mem_kind = self.kind.ctypes.data
+        t.n_branch = self.site.size
+        t.br_site = self.site.ctypes.data
+        t.br_taken = self.taken.ctypes.data
+        t.history_len = int(tr.history_len)
+        self.t = t
+
+
+def _struct_to_dict(s) -> Dict:
+    out = {}
+    for name, _ in s._fields_:
+        v = getattr(s, name)
+        if isinstance(v, ctypes.Array):
+            if len(v) and isinstance(v[0], ctypes.Structure):
+                out[name] = [_struct_to_dict(x) for x in v]
+            else:
+                out[name] = list(v)
+        else:
+            out[name] = v
+    return out
+
+
+def characterize(tr) -> Dict:
+    """Metrics of a host trace (any object with the HostTrace attributes)."""
+    L = _load()
+    b = _Bound(tr)
+    r = OrcResult()
+    rc = L.orc_characterize(ctypes.byref(b.t), ctypes.byref(r))
+    if rc != 0:
+        raise ValueError(f"oracle rejected the trace (rc={rc})")
+    return _struct_to_dict(r)
+
+
+def class_hist(tr, n_classes: int) -> np.ndarray:
+    L = _load()
+    b = _Bound(tr)
+    out = np.zeros(n_classes, dtype=np.uint64)
+    if L.orc_class_hist(ctypes.byref(b.t), out.ctypes.data, n_classes) != 0:
+        raise ValueError("oracle rejected the trace")
+    return out
+
+
+def spectrum(tr, space: int, k: int = 0):
+    """Count-of-counts [(f, m_f)] ascending in f."""
+    L = _load()
+    b = _Bound(tr)
+    n = ctypes.c_size_t()
+    L.orc_spectrum(ctypes.byref(b.t), space, k, None, None, 0, ctypes.byref(n))
+    f = np.zeros(max(1, n.value), dtype=np.uint64)
+    m = np.zeros(max(1, n.value), dtype=np.uint64)
+    if L.orc_spectrum(ctypes.byref(b.t), space, k, f.ctypes.data, m.ctypes.data, n.value,
+                      ctypes.byref(n)) != 0:
+        raise ValueError("oracle rejected the trace")
+    return [(int(a), int(c)) for a, c in zip(f[:n.value], m[:n.value])]

@@ -1,0 +1,84 @@
+"""Small trace builders shared by the tests (input construction only)."""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Optional, Sequence
+
+import numpy as np
+
+OPDT = np.dtype([("op_class", "<u2"), ("simd_width", "u1"), ("kind", "u1")])
+COMPUTE, LOAD, STORE, ATOMIC, BRANCH, BARRIER, OTHER = range(7)
+
+
+def table(entries: Sequence[tuple]) -> np.ndarray:
+    t = np.zeros(len(entries), dtype=OPDT)
+    for i, e in enumerate(entries):
+        t[i] = e
+    return t
+
+
+# a default table: id 0..3 compute (classes 0..3, width 1), 4 load, 5 store,
+# 6 cond branch, 7 barrier, 8 ret
+DEFAULT_TABLE = table([(0, 1, COMPUTE), (1, 1, COMPUTE), (2, 1, COMPUTE), (3, 1, COMPUTE),
+                       (4, 1, LOAD), (5, 1, STORE), (6, 1, BRANCH), (7, 1, BARRIER),
+                       (8, 1, OTHER)])
+ID_LOAD, ID_STORE, ID_BRANCH, ID_BARRIER, ID_RET = 4, 5, 6, 7, 8
+
+
+@dataclass
+class Trace:
+    opcode: np.ndarray
+    wi_offsets: np.ndarray
+    addr: np.ndarray
+    mem_kind: np.ndarray
+    br_site: np.ndarray
+    br_taken: np.ndarray
+    n_sites: int = 1
+    history_len: int = 16
+    table: np.ndarray = field(default_factory=lambda: DEFAULT_TABLE.copy())
+
+
+def mk(opcode=(), wi_lengths: Optional[Sequence[int]] = None, addr=(), mem_kind=None,
+       br_site=(), br_taken=(), n_sites: int = 1, m: int = 16, tab=None) -> Trace:
+    op = np.asarray(opcode, dtype=np.uint16)
+    if wi_lengths is None:
+        wi_lengths = [op.size]
+    off = np.zeros(len(wi_lengths) + 1, dtype=np.uint64)
+    off[1:] = np.cumsum(np.asarray(wi_lengths, dtype=np.uint64))
+    assert int(off[-1]) == op.size
+    a = np.asarray(addr, dtype=np.uint64)
+    k = np.zeros(a.size, dtype=np.uint8) if mem_kind is None else np.asarray(mem_kind, dtype=np.uint8)
+    return Trace(op, off, a, k, np.asarray(br_site, dtype=np.uint32),
+                 np.asarray(br_taken, dtype=np.uint8), n_sites=max(1, n_sites), history_len=m,
+                 table=DEFAULT_TABLE.copy() if tab is None else tab)
+
+
+def mem_trace(addr, kinds=None) -> Trace:
+    """A trace whose only events are loads/stores of the given addresses."""
+    a = np.asarray(addr, dtype=np.uint64)
+    k = np.zeros(a.size, dtype=np.uint8) if kinds is None else np.asarray(kinds, dtype=np.uint8)
+    op = np.where(k & 1, ID_STORE, ID_LOAD).astype(np.uint16)
+    return mk(op, [op.size], a, k)
+
+
+def branch_trace(sites, outcomes, n_sites: int, m: int) -> Trace:
+    s = np.asarray(sites, dtype=np.uint32)
+    op = np.full(s.size, ID_BRANCH, dtype=np.uint16)
+    return mk(op, [op.size], br_site=s, br_taken=outcomes, n_sites=n_sites, m=m)
+
+
+def random_trace(rng: np.random.Generator, n_wi: int, max_len: int, n_sites: int, m: int,
+                 addr_bits: int = 12, p_local: float = 0.3) -> Trace:
+    """Random small trace with consistent kinds (for brute-force checks)."""
+    lens = rng.integers(0, max_len + 1, size=n_wi)
+    n = int(lens.sum())
+    ids = rng.integers(0, 9, size=n).astype(np.uint16)
+    is_mem = np.isin(ids, [ID_LOAD, ID_STORE])
+    nm = int(is_mem.sum())
+    kinds = (ids[is_mem] == ID_STORE).astype(np.uint8)
+    kinds |= (rng.random(nm) < p_local).astype(np.uint8) << 1
+    addr = rng.integers(0, 1 << addr_bits, size=nm, dtype=np.uint64)
+    nb = int((ids == ID_BRANCH).sum())
+    sites = rng.integers(0, n_sites, size=nb).astype(np.uint32)
+    taken = (rng.random(nb) < rng.random()).astype(np.uint8)
+    return mk(ids, list(lens), addr, kinds, sites, taken, n_sites=n_sites, m=m)
