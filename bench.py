@@ -1,0 +1,132 @@
+"""Benchmark: trace events per second of the full characterization on one
+MI355X, with the dominant kernel's roofline and the CPU oracle beside it.
+
+A step = one complete characterization (aiwc_characterize + aiwc_metrics_read)
+of one synthetic trace already resident in HBM.  Default workload: the large
+plain trace (2^20 work-items in work-groups of 256, ~1.07e9 events, config2
+recipe of tracegen).  Prints ONE JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "trace events/sec and % HBM peak, batched+learned-sizing vs plain, bit-exact"
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_bytes(name: str, n_ev: int, n_wi: int, n_mem: int, n_br: int, passes: int) -> float:
+    """Bytes each kernel must move for one trace (documented in the design doc)."""
+    return {
+        "k_ops": 2.0 * n_ev + 8.0 * (n_wi + 1),
+        "k_mem_hist": 9.0 * n_mem,
+        "k_mem_scatter": 17.0 * n_mem,
+        "k_mem_bucket": 8.0 * n_mem,
+        "k_br_pack": 9.0 * n_br,
+        "k_br_sort": 12.0 * n_br * passes,
+        "k_br_segments": 4.0 * n_br,
+        "k_br_windows": 4.0 * n_br,
+    }.get(name, 0.0)
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n-wi-log2", type=int, default=20, help="work-items = 2^x (config2 recipe)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-wi-log2", type=int, default=15)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; the multi-GPU sharding "
+                                   "is a design (see DESIGN.md), not a launched path"}))
+        return 2
+
+    import numpy as np
+    import torch
+    import tracegen as tg
+    import paper_1805_04207_amd as aiwc
+
+    spec = tg.config2(n_wi=1 << args.n_wi_log2)
+    t0 = time.time()
+    dev = tg.generate_device(spec, 0)
+    torch.cuda.synchronize()
+    gen_s = time.time() - t0
+    n_ev, n_mem, n_br, n_wi = dev["n_events"], dev["n_mem"], dev["n_branch"], spec.n_wi
+    print(f"# generated {spec.label}: events={n_ev} mem={n_mem} branch={n_br} in {gen_s:.1f}s",
+          file=sys.stderr, flush=True)
+    ctx = aiwc.Context(0)
+    tr = aiwc.device_trace(ctx, dev, tg.opcode_table(), spec.n_sites, spec.history_len,
+                           spec.wg_size)
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        r = ctx.characterize(tr, stream).read()
+    print(f"# warmup done: H0={r['space'][0]['entropy'][0]:.6f} redos={r['overflow_redos']}",
+          file=sys.stderr, flush=True)
+
+    ctx.profile_enable(True)
+    per_kernel = {}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        m = ctx.characterize(tr, stream)
+        r = m.read()
+        for name, ms in ctx.profile_read():
+            per_kernel.setdefault(name, []).append(ms)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ctx.profile_enable(False)
+    ms_step = 1000.0 * dt / args.steps
+    value = n_ev * args.steps / dt
+    passes = (max(1, spec.n_sites - 1).bit_length() + 7) // 8 if spec.n_sites > 1 else 0
+    avg = {k: float(np.mean(v)) for k, v in per_kernel.items()}
+    dom = max(avg, key=avg.get)
+    ach = algorithmic_bytes(dom, n_ev, n_wi, n_mem, n_br, passes) / (avg[dom] * 1e-3) / 1e9
+    compulsory = 2.0 * n_ev + 9.0 * n_mem + 5.0 * n_br + 8.0 * (n_wi + 1)
+    comp_gbs = compulsory / (ms_step * 1e-3) / 1e9
+    print("# per-kernel ms: " + ", ".join(f"{k}={v:.3f}" for k, v in avg.items()),
+          file=sys.stderr, flush=True)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        sspec = tg.config2(n_wi=1 << args.cpu_sample_wi_log2)
+        h = tg.generate_host(sspec)
+        t0 = time.perf_counter()
+        oracle.characterize(h)
+        cdt = time.perf_counter() - t0
+        cpu = {"value": h.opcode.size / cdt, "unit": "events/s", "cores": 1, "kind": "oracle",
+               "sample": f"config2 recipe with 2^{args.cpu_sample_wi_log2} work-items "
+                         f"({h.opcode.size} events, {h.addr.size} memory, {h.br_site.size} branch"
+                         f" events), single-threaded C oracle, {cdt:.1f} s"}
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "events/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": f"plain large trace (config2 recipe): 2^{args.n_wi_log2} work-items "
+                               f"in work-groups of 256, {n_ev} events, {n_mem} memory events "
+                               f"(10% local; global 60/30/10 sweep/stencil/gather), {n_br} "
+                               f"branch events at 4096 sites, history 16",
+                   "path": "plain per-trace aiwc_characterize", "n_events": n_ev,
+                   "compulsory_bytes": compulsory, "compulsory_gbps": comp_gbs,
+                   "compulsory_hbm_frac": comp_gbs / HBM_PEAK_GBS,
+                   "kernel_ms": avg, "partitions": r["partitions"],
+                   "overflow_redos": r["overflow_redos"]},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -297,6 +297,16 @@ aiwc_status aiwc_metrics_spectrum(aiwc_metrics *m, int space, uint64_t *f,
                                   uint64_t *mf, size_t cap, size_t *n_out);
 aiwc_status aiwc_metrics_destroy(aiwc_metrics *m);
 
+/* ---------------------------------------------------------- instrumentation
+ * When enabled, every characterization records a hipEvent on its stream after
+ * each kernel launch.  aiwc_profile_read waits for the last one and returns,
+ * for the most recent characterization of the context, the per-kernel
+ * durations in milliseconds (ms[i] = time from the previous mark to mark i)
+ * and their kernel names as one comma-separated string (host buffers).      */
+aiwc_status aiwc_profile_enable(aiwc_ctx *ctx, int on);
+aiwc_status aiwc_profile_read(aiwc_ctx *ctx, char *names, size_t names_cap,
+                              double *ms, size_t max_stages, size_t *n_out);
+
 /* ----------------------------------------------------- learned sizing (MLP)
  * A 40 -> 64 -> 64 -> 64 -> 11 perceptron (exact-erf GELU, bf16 weights,
  * fp32 accumulation) predicts log2 of the global-space distinct counts at

@@ -1,0 +1,519 @@
+// abi.hip -- the C ABI of libaiwc: contexts, trace descriptors, the
+// per-trace planner (scratch layout and launch shapes) and metrics handles.
+// All metric arithmetic runs in the kernels of k_*.hip; this file only
+// validates arguments, sizes buffers and enqueues launches.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "abi_internal.h"
+
+namespace aiwc_kernels {
+u64 scan_tmp_elems(u64 n);
+u64 br_tiles_for(u64 n);
+u64 br_blocks_for(u64 n);
+}
+
+static thread_local std::string g_noctx_err;
+
+void ctx_error(aiwc_ctx *ctx, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (ctx) ctx->err = buf; else g_noctx_err = buf;
+}
+
+#define HIP_OR(ctx, call)                                                       \
+  do {                                                                          \
+    hipError_t e__ = (call);                                                    \
+    if (e__ != hipSuccess) {                                                    \
+      ctx_error(ctx, "%s failed: %s", #call, hipGetErrorString(e__));           \
+      return AIWC_ERR_HIP;                                                      \
+    }                                                                           \
+  } while (0)
+
+static inline u64 align_up(u64 x, u64 a) { return (x + a - 1) / a * a; }
+static inline u32 ceil_log2(u64 x) {
+  u32 b = 0;
+  while ((1ull << b) < x) ++b;
+  return b;
+}
+
+// ------------------------------------------------------------------ plan
+// Scratch layout of one trace: a zero region (cleared by a kernel) followed
+// by buffers that every stage fully writes before reading.
+void plan_trace(const aiwc_trace *t, u32 pbits, TracePlan &p) {
+  const aiwc_trace_desc &d = t->d;
+  p = TracePlan();
+  p.pbits = d.n_mem ? pbits : 4;
+  const u64 P = 1ull << p.pbits;
+  // memory: histogram blocks = one per CU at most, >= 16K records each
+  u64 nb = (d.n_mem + 16383) / 16384;
+  nb = std::max<u64>(1, std::min<u64>(nb, 256));
+  p.n_hist_blocks = (u32)nb;
+  p.hist_chunk = align_up((d.n_mem + nb - 1) / nb, 4);
+  if (p.hist_chunk == 0) p.hist_chunk = 4;
+  u64 r = (u64)std::sqrt((double)(2 * d.n_mem)) + 2;
+  p.sp_cap = (u32)std::max<u64>(64, 1ull << ceil_log2(2 * r));
+  // branches
+  p.br_passes = 0;
+  if (d.n_sites > 1) p.br_passes = (ceil_log2(d.n_sites) + 7) / 8;
+  p.br_tiles = aiwc_kernels::br_tiles_for(d.n_branch);
+  p.br_blocks = aiwc_kernels::br_blocks_for(d.n_branch);
+  // ops
+  p.large_cap = d.n_events / 65536 + 1;
+  u64 E = std::max<u64>(4096, (d.n_events + 16383) / 16384);
+  p.ops_task = align_up(E, 512);
+  p.ops_tasks = std::max<u64>(1, (d.n_events + p.ops_task - 1) / p.ops_task);
+
+  u64 o = 0;
+  auto take = [&](u64 bytes) { u64 at = o; o += align_up(bytes, 256); return at; };
+  p.o_acc = take(sizeof(DevAccum));
+  p.o_id_hist = take(8ull * d.n_opcode_ids);
+  p.o_class_hist = take(8ull * t->n_classes);
+  p.o_itb_hist = take(8ull * VAL_DENSE);
+  p.o_ipt_hist = take(8ull * VAL_DENSE);
+  p.o_sp_f = take(8ull * 2 * p.sp_cap);
+  p.o_sp_m = take(8ull * 2 * p.sp_cap);
+  p.o_seg_start = take(4ull * std::max<u32>(1, d.n_sites));
+  p.o_seg_end = take(4ull * std::max<u32>(1, d.n_sites));
+  p.zero_bytes = o;
+  p.o_itb_large = take(8ull * p.large_cap);
+  p.o_ipt_large = take(8ull * p.large_cap);
+  p.o_part_hist = take(4ull * p.n_hist_blocks * P);
+  p.o_part_off = take(4ull * (P + 1));
+  p.o_part_rec = take(8ull * std::max<u64>(1, d.n_mem));
+  p.o_br_a = take(4ull * std::max<u64>(1, d.n_branch));
+  p.o_br_b = take(4ull * std::max<u64>(1, d.n_branch));
+  p.o_br_cnt = take(4ull * 256 * std::max<u64>(1, p.br_tiles));
+  p.o_scan_tmp = take(4ull * aiwc_kernels::scan_tmp_elems(256 * std::max<u64>(1, p.br_tiles)));
+  p.scratch_bytes = o;
+  p.spec_export_cap = std::min<u32>(p.sp_cap, 65536);
+  // result buffer: metrics, 4 status words, class histogram, spectrum pairs
+  u64 rb = 0;
+  p.r_metrics = rb; rb += align_up(sizeof(aiwc_metrics_host) + 32, 256);
+  p.r_class = rb; rb += align_up(8ull * t->n_classes, 256);
+  p.r_spec = rb; rb += align_up(8ull * 2 * 2 * p.spec_export_cap, 256);
+  p.result_bytes = rb;
+}
+
+u32 bound_pbits(u64 n_mem) {
+  // distinct <= accesses: aim at <= 4096 distinct addresses per partition
+  u64 want = (n_mem + 4095) / 4096;
+  u32 b = ceil_log2(std::max<u64>(want, 1));
+  return std::min<u32>(15, std::max<u32>(4, b));
+}
+
+void fill_args(const aiwc_trace *t, const TracePlan &p, char *scratch, char *result,
+               TraceArgs &a) {
+  const aiwc_trace_desc &d = t->d;
+  memset(&a, 0, sizeof a);
+  a.opcode = d.opcode;
+  a.wi_off = (const u64 *)d.wi_offsets;
+  a.addr = (const u64 *)d.addr;
+  a.mem_kind = d.mem_kind;
+  a.br_site = d.br_site;
+  a.br_taken = d.br_taken;
+  a.op_info = t->dev_info;
+  a.n_events = d.n_events;
+  a.n_wi = d.n_workitems;
+  a.n_mem = d.n_mem;
+  a.n_branch = d.n_branch;
+  a.n_ids = d.n_opcode_ids;
+  a.n_classes = t->n_classes;
+  a.n_sites = d.n_sites;
+  a.m = d.history_len;
+  a.pbits = p.pbits;
+  a.n_hist_blocks = p.n_hist_blocks;
+  a.hist_chunk = p.hist_chunk;
+  a.sp_cap = p.sp_cap;
+  a.br_passes = p.br_passes;
+  a.br_tiles = p.br_tiles;
+  a.br_blocks = p.br_blocks;
+  a.large_cap = p.large_cap;
+  a.ops_task = p.ops_task;
+  a.ops_tasks = p.ops_tasks;
+  a.acc = (DevAccum *)(scratch + p.o_acc);
+  a.id_hist = (u64 *)(scratch + p.o_id_hist);
+  a.class_hist = (u64 *)(scratch + p.o_class_hist);
+  a.itb_hist = (u64 *)(scratch + p.o_itb_hist);
+  a.ipt_hist = (u64 *)(scratch + p.o_ipt_hist);
+  a.itb_large = (u64 *)(scratch + p.o_itb_large);
+  a.ipt_large = (u64 *)(scratch + p.o_ipt_large);
+  a.sp_f = (u64 *)(scratch + p.o_sp_f);
+  a.sp_m = (u64 *)(scratch + p.o_sp_m);
+  a.seg_start = (u32 *)(scratch + p.o_seg_start);
+  a.seg_end = (u32 *)(scratch + p.o_seg_end);
+  a.part_hist = (u32 *)(scratch + p.o_part_hist);
+  a.part_off = (u32 *)(scratch + p.o_part_off);
+  a.part_rec = (u64 *)(scratch + p.o_part_rec);
+  a.br_a = (u32 *)(scratch + p.o_br_a);
+  a.br_b = (u32 *)(scratch + p.o_br_b);
+  a.br_cnt = (u32 *)(scratch + p.o_br_cnt);
+  a.scan_tmp = (u32 *)(scratch + p.o_scan_tmp);
+  a.out = (aiwc_metrics_host *)(result + p.r_metrics);
+  a.out_class_hist = (u64 *)(result + p.r_class);
+  a.out_spec = (u64 *)(result + p.r_spec);
+  a.spec_export_cap = p.spec_export_cap;
+}
+
+hipError_t enqueue_trace(const TraceArgs &a, const TracePlan &p, char *scratch,
+                         hipStream_t s, StageMarks *pm) {
+  hipError_t e = aiwc_kernels::launch_zero(scratch, p.zero_bytes, s);
+  AIWC_MARK(pm, "k_zero", s);
+  if (e == hipSuccess) e = aiwc_kernels::launch_ops(a, s, pm);
+  if (e == hipSuccess) e = aiwc_kernels::launch_mem(a, s, pm);
+  if (e == hipSuccess) e = aiwc_kernels::launch_branch(a, s, pm);
+  if (e == hipSuccess) e = aiwc_kernels::launch_finalize(a, s, pm);
+  return e;
+}
+
+// ------------------------------------------------------------ profiling
+void Profiler::begin(hipStream_t s) {
+  used = 0;
+  marks.clear();
+  if (!start) hipEventCreate(&start);
+  hipEventRecord(start, s);
+}
+
+void Profiler::mark(const char *name, hipStream_t s) {
+  if (used == pool.size()) {
+    hipEvent_t e;
+    hipEventCreate(&e);
+    pool.push_back(e);
+  }
+  hipEvent_t e = pool[used++];
+  hipEventRecord(e, s);
+  marks.emplace_back(name, e);
+}
+
+void Profiler::release() {
+  if (start) hipEventDestroy(start);
+  for (hipEvent_t e : pool) hipEventDestroy(e);
+  pool.clear();
+  marks.clear();
+  start = nullptr;
+}
+
+extern "C" aiwc_status aiwc_profile_enable(aiwc_ctx *ctx, int on) {
+  if (!ctx) { ctx_error(nullptr, "aiwc_profile_enable: NULL context"); return AIWC_ERR_INVALID_ARG; }
+  ctx->prof.on = on != 0;
+  return AIWC_OK;
+}
+
+extern "C" aiwc_status aiwc_profile_read(aiwc_ctx *ctx, char *names, size_t names_cap,
+                                         double *ms, size_t max_stages, size_t *n_out) {
+  if (!ctx || !n_out) { ctx_error(ctx, "aiwc_profile_read: NULL argument"); return AIWC_ERR_INVALID_ARG; }
+  Profiler &P = ctx->prof;
+  std::string csv;
+  size_t n = 0;
+  if (P.start && !P.marks.empty()) {
+    HIP_OR(ctx, hipEventSynchronize(P.marks.back().second));
+    hipEvent_t prev = P.start;
+    for (auto &m : P.marks) {
+      float t = 0.f;
+      HIP_OR(ctx, hipEventElapsedTime(&t, prev, m.second));
+      if (n < max_stages && ms) ms[n] = t;
+      if (!csv.empty()) csv += ",";
+      csv += m.first;
+      prev = m.second;
+      ++n;
+    }
+  }
+  if (names && names_cap) {
+    size_t c = std::min(names_cap - 1, csv.size());
+    memcpy(names, csv.data(), c);
+    names[c] = 0;
+  }
+  *n_out = n;
+  return AIWC_OK;
+}
+
+// --------------------------------------------------------------- context
+extern "C" aiwc_status aiwc_context_create(int hip_device, aiwc_ctx **out) {
+  if (!out) { ctx_error(nullptr, "aiwc_context_create: out is NULL"); return AIWC_ERR_INVALID_ARG; }
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || hip_device < 0 || hip_device >= n) {
+    ctx_error(nullptr, "aiwc_context_create: no HIP device %d (%d visible)", hip_device, n);
+    return AIWC_ERR_INVALID_ARG;
+  }
+  aiwc_ctx *c = new aiwc_ctx();
+  c->device = hip_device;
+  if (hipSetDevice(hip_device) != hipSuccess) {
+    delete c;
+    ctx_error(nullptr, "aiwc_context_create: hipSetDevice(%d) failed", hip_device);
+    return AIWC_ERR_HIP;
+  }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, hip_device) == hipSuccess) {
+    c->n_cu = prop.multiProcessorCount;
+    c->arch = prop.gcnArchName;
+  }
+  sizer_init(c);
+  *out = c;
+  return AIWC_OK;
+}
+
+extern "C" aiwc_status aiwc_context_destroy(aiwc_ctx *ctx) {
+  if (!ctx) return AIWC_OK;
+  hipSetDevice(ctx->device);
+  hipDeviceSynchronize();
+  if (ctx->arena) hipFree(ctx->arena);
+  if (ctx->last_done) hipEventDestroy(ctx->last_done);
+  ctx->prof.release();
+  sizer_free(ctx);
+  batch_free(ctx);
+  delete ctx;
+  return AIWC_OK;
+}
+
+extern "C" const char *aiwc_last_error(const aiwc_ctx *ctx) {
+  return ctx ? ctx->err.c_str() : g_noctx_err.c_str();
+}
+
+// Grow the context's scratch arena (waiting for work that may still use it).
+aiwc_status ensure_arena(aiwc_ctx *ctx, u64 bytes) {
+  if (ctx->arena_bytes >= bytes) return AIWC_OK;
+  if (ctx->arena) {
+    if (ctx->last_done) hipEventSynchronize(ctx->last_done);
+    hipFree(ctx->arena);
+    ctx->arena = nullptr;
+    ctx->arena_bytes = 0;
+  }
+  u64 want = std::max<u64>(bytes, 1ull << 20);
+  void *p = nullptr;
+  if (hipMalloc(&p, want) != hipSuccess) {
+    hipGetLastError();
+    ctx_error(ctx, "out of device memory: scratch of %llu bytes", (unsigned long long)want);
+    return AIWC_ERR_OUT_OF_MEMORY;
+  }
+  ctx->arena = (char *)p;
+  ctx->arena_bytes = want;
+  return AIWC_OK;
+}
+
+// ------------------------------------------------------------------ trace
+extern "C" aiwc_status aiwc_trace_create(aiwc_ctx *ctx, const aiwc_trace_desc *d,
+                                         aiwc_trace **out) {
+  if (!ctx || !d || !out) { ctx_error(ctx, "aiwc_trace_create: NULL argument"); return AIWC_ERR_INVALID_ARG; }
+  if (d->struct_size != sizeof(aiwc_trace_desc)) {
+    ctx_error(ctx, "aiwc_trace_create: struct_size %u != %zu", d->struct_size, sizeof(aiwc_trace_desc));
+    return AIWC_ERR_INVALID_ARG;
+  }
+  if (d->history_len < 1 || d->history_len > 32) {
+    ctx_error(ctx, "history_len %u outside 1..32", d->history_len);
+    return AIWC_ERR_INVALID_ARG;
+  }
+  if (d->max_lsb_skip != 10) {
+    ctx_error(ctx, "max_lsb_skip must be 10 (got %u)", d->max_lsb_skip);
+    return AIWC_ERR_INVALID_ARG;
+  }
+  if (!d->wi_offsets || (d->n_events && !d->opcode) || (d->n_mem && (!d->addr || !d->mem_kind)) ||
+      (d->n_branch && (!d->br_site || !d->br_taken))) {
+    ctx_error(ctx, "NULL array with a non-zero length");
+    return AIWC_ERR_INVALID_ARG;
+  }
+  if (d->n_branch && d->n_sites == 0) { ctx_error(ctx, "n_branch > 0 needs n_sites >= 1"); return AIWC_ERR_INVALID_ARG; }
+  if (d->n_sites >= (1u << 31)) { ctx_error(ctx, "n_sites must be < 2^31"); return AIWC_ERR_INVALID_ARG; }
+  if (d->n_mem >= (1ull << 32) || d->n_branch >= (1ull << 32)) {
+    ctx_error(ctx, "n_mem and n_branch must be < 2^32 per trace");
+    return AIWC_ERR_INVALID_ARG;
+  }
+  if (d->n_opcode_ids == 0 || d->n_opcode_ids > 65536 || !d->opcode_table) {
+    ctx_error(ctx, "opcode table needs 1..65536 entries");
+    return AIWC_ERR_INVALID_ARG;
+  }
+  u32 ncls = 0;
+  std::vector<u32> info(d->n_opcode_ids);
+  for (u32 i = 0; i < d->n_opcode_ids; ++i) {
+    const aiwc_opcode_info &e = d->opcode_table[i];
+    if (e.kind > AIWC_KIND_OTHER || e.simd_width == 0 || e.op_class == 0xFFFF) {
+      ctx_error(ctx, "opcode table entry %u is invalid", i);
+      return AIWC_ERR_INVALID_ARG;
+    }
+    ncls = std::max<u32>(ncls, (u32)e.op_class + 1);
+    info[i] = (u32)e.kind | ((u32)e.simd_width << 8) | ((u32)e.op_class << 16);
+  }
+  HIP_OR(ctx, hipSetDevice(ctx->device));
+  aiwc_trace *t = new aiwc_trace();
+  t->ctx = ctx;
+  t->d = *d;
+  t->d.opcode_table = nullptr;
+  t->n_classes = ncls;
+  t->host_info = info;
+  if (hipMalloc(&t->dev_info, 4ull * info.size()) != hipSuccess) {
+    hipGetLastError();
+    delete t;
+    ctx_error(ctx, "out of device memory for the opcode table");
+    return AIWC_ERR_OUT_OF_MEMORY;
+  }
+  if (hipMemcpy(t->dev_info, info.data(), 4ull * info.size(), hipMemcpyHostToDevice) != hipSuccess) {
+    hipFree(t->dev_info);
+    delete t;
+    ctx_error(ctx, "copying the opcode table failed");
+    return AIWC_ERR_HIP;
+  }
+  if (d->flags & AIWC_VALIDATE_ON_DEVICE) {
+    aiwc_status st = validate_on_device(ctx, t);
+    if (st != AIWC_OK) { hipFree(t->dev_info); delete t; return st; }
+  }
+  *out = t;
+  return AIWC_OK;
+}
+
+extern "C" aiwc_status aiwc_trace_destroy(aiwc_trace *t) {
+  if (!t) return AIWC_OK;
+  if (t->dev_info) hipFree(t->dev_info);
+  delete t;
+  return AIWC_OK;
+}
+
+// ------------------------------------------------------------ characterize
+aiwc_status new_metrics(aiwc_ctx *ctx, const aiwc_trace *t, const TracePlan &p,
+                        aiwc_metrics **out) {
+  aiwc_metrics *m = new aiwc_metrics();
+  m->ctx = ctx;
+  m->plan = p;
+  m->n_classes = t->n_classes;
+  if (hipMalloc(&m->buf, p.result_bytes) != hipSuccess) {
+    hipGetLastError();
+    delete m;
+    ctx_error(ctx, "out of device memory for a result buffer");
+    return AIWC_ERR_OUT_OF_MEMORY;
+  }
+  if (hipEventCreateWithFlags(&m->done, hipEventDisableTiming) != hipSuccess) {
+    hipFree(m->buf);
+    delete m;
+    ctx_error(ctx, "hipEventCreate failed");
+    return AIWC_ERR_HIP;
+  }
+  *out = m;
+  return AIWC_OK;
+}
+
+aiwc_status characterize_planned(aiwc_ctx *ctx, const aiwc_trace *t, u32 pbits,
+                                 hipStream_t s, aiwc_metrics **out) {
+  TracePlan p;
+  plan_trace(t, pbits, p);
+  aiwc_status st = ensure_arena(ctx, p.scratch_bytes);
+  if (st != AIWC_OK) return st;
+  aiwc_metrics *m = nullptr;
+  st = new_metrics(ctx, t, p, &m);
+  if (st != AIWC_OK) return st;
+  if (ctx->last_done) HIP_OR(ctx, hipStreamWaitEvent(s, ctx->last_done, 0));
+  TraceArgs a;
+  fill_args(t, p, ctx->arena, (char *)m->buf, a);
+  StageMarks *pm = nullptr;
+  if (ctx->prof.on) { ctx->prof.begin(s); pm = &ctx->prof; }
+  hipError_t e = enqueue_trace(a, p, ctx->arena, s, pm);
+  if (e != hipSuccess) {
+    ctx_error(ctx, "kernel launch failed: %s", hipGetErrorString(e));
+    aiwc_metrics_destroy(m);
+    return AIWC_ERR_HIP;
+  }
+  HIP_OR(ctx, hipEventRecord(m->done, s));
+  if (!ctx->last_done) HIP_OR(ctx, hipEventCreateWithFlags(&ctx->last_done, hipEventDisableTiming));
+  HIP_OR(ctx, hipEventRecord(ctx->last_done, s));
+  *out = m;
+  return AIWC_OK;
+}
+
+extern "C" aiwc_status aiwc_characterize(aiwc_ctx *ctx, const aiwc_trace *t, void *stream,
+                                         aiwc_metrics **out) {
+  if (!ctx || !t || !out) { ctx_error(ctx, "aiwc_characterize: NULL argument"); return AIWC_ERR_INVALID_ARG; }
+  if (t->ctx != ctx) { ctx_error(ctx, "trace belongs to another context"); return AIWC_ERR_INVALID_ARG; }
+  HIP_OR(ctx, hipSetDevice(ctx->device));
+  u32 pbits = bound_pbits(t->d.n_mem);
+  // debug knob: force the partition count (undersizing exercises the
+  // overflow -> split -> redo path; results must not change)
+  if (const char *e = getenv("AIWC_FORCE_PARTITION_LOG2")) {
+    int v = atoi(e);
+    if (v >= 4 && v <= 15) pbits = (u32)v;
+  }
+  return characterize_planned(ctx, t, pbits, (hipStream_t)stream, out);
+}
+
+// ------------------------------------------------------------------ metrics
+extern "C" aiwc_status aiwc_metrics_read(aiwc_metrics *m, aiwc_metrics_host *out) {
+  if (!m || !out) { ctx_error(m ? m->ctx : nullptr, "aiwc_metrics_read: NULL argument"); return AIWC_ERR_INVALID_ARG; }
+  aiwc_ctx *ctx = m->ctx;
+  HIP_OR(ctx, hipEventSynchronize(m->done));
+  std::vector<char> h(m->plan.r_metrics + sizeof(aiwc_metrics_host) + 32);
+  HIP_OR(ctx, hipMemcpy(h.data(), (char *)m->buf + m->plan.r_metrics,
+                        sizeof(aiwc_metrics_host) + 32, hipMemcpyDeviceToHost));
+  aiwc_metrics_host r;
+  memcpy(&r, h.data(), sizeof r);
+  u64 status[4];
+  memcpy(status, h.data() + sizeof(aiwc_metrics_host), sizeof status);
+  m->spec_pairs[0] = (u32)(status[2] & 0xFFFFFFFFu);
+  m->spec_pairs[1] = (u32)(status[2] >> 32);
+  if (status[0]) {
+    ctx_error(ctx, "trace content is invalid (%llu bad opcode ids / sites / outcomes)",
+              (unsigned long long)status[0]);
+    return AIWC_ERR_INVALID_ARG;
+  }
+  if (status[1]) {
+    ctx_error(ctx, "opcode kinds disagree with the memory / branch stream lengths");
+    return AIWC_ERR_INCONSISTENT;
+  }
+  *out = r;
+  return AIWC_OK;
+}
+
+extern "C" aiwc_status aiwc_metrics_class_hist(aiwc_metrics *m, uint64_t *out, size_t len) {
+  if (!m || (!out && len)) { ctx_error(m ? m->ctx : nullptr, "aiwc_metrics_class_hist: NULL argument"); return AIWC_ERR_INVALID_ARG; }
+  aiwc_ctx *ctx = m->ctx;
+  HIP_OR(ctx, hipEventSynchronize(m->done));
+  std::vector<uint64_t> h(m->n_classes);
+  if (m->n_classes)
+    HIP_OR(ctx, hipMemcpy(h.data(), (char *)m->buf + m->plan.r_class, 8ull * m->n_classes,
+                          hipMemcpyDeviceToHost));
+  for (size_t i = 0; i < len; ++i) out[i] = i < h.size() ? h[i] : 0;
+  return AIWC_OK;
+}
+
+extern "C" aiwc_status aiwc_metrics_spectrum(aiwc_metrics *m, int space, uint64_t *f,
+                                             uint64_t *mf, size_t cap, size_t *n_out) {
+  if (!m || !n_out || space < 0 || space > 1 || (cap && (!f || !mf))) {
+    ctx_error(m ? m->ctx : nullptr, "aiwc_metrics_spectrum: invalid argument");
+    return AIWC_ERR_INVALID_ARG;
+  }
+  aiwc_ctx *ctx = m->ctx;
+  HIP_OR(ctx, hipEventSynchronize(m->done));
+  u64 status[4];
+  HIP_OR(ctx, hipMemcpy(status, (char *)m->buf + m->plan.r_metrics + sizeof(aiwc_metrics_host),
+                        sizeof status, hipMemcpyDeviceToHost));
+  u64 n = space ? (status[2] >> 32) : (status[2] & 0xFFFFFFFFu);
+  if (n > m->plan.spec_export_cap) {
+    ctx_error(ctx, "spectrum has %llu pairs, more than the %u exported",
+              (unsigned long long)n, m->plan.spec_export_cap);
+    return AIWC_ERR_UNSUPPORTED;
+  }
+  std::vector<uint64_t> pairs(2 * n);
+  if (n)
+    HIP_OR(ctx, hipMemcpy(pairs.data(),
+                          (char *)m->buf + m->plan.r_spec + 16ull * space * m->plan.spec_export_cap,
+                          16 * n, hipMemcpyDeviceToHost));
+  std::vector<std::pair<uint64_t, uint64_t>> v(n);
+  for (u64 i = 0; i < n; ++i) v[i] = {pairs[2 * i], pairs[2 * i + 1]};
+  std::sort(v.begin(), v.end());
+  for (u64 i = 0; i < n && i < cap; ++i) { f[i] = v[i].first; mf[i] = v[i].second; }
+  *n_out = n;
+  return AIWC_OK;
+}
+
+extern "C" aiwc_status aiwc_metrics_destroy(aiwc_metrics *m) {
+  if (!m) return AIWC_OK;
+  if (m->done) { hipEventSynchronize(m->done); hipEventDestroy(m->done); }
+  if (m->buf) hipFree(m->buf);
+  delete m;
+  return AIWC_OK;
+}

@@ -1,0 +1,92 @@
+// abi_internal.h -- host-side objects behind the opaque handles of aiwc.h.
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+struct TracePlan {
+  u32 pbits = 4;
+  u32 n_hist_blocks = 1;
+  u64 hist_chunk = 4;
+  u32 sp_cap = 64;
+  u32 br_passes = 0;
+  u64 br_tiles = 0, br_blocks = 0;
+  u64 large_cap = 1;
+  u64 ops_task = 4096, ops_tasks = 1;
+  // scratch offsets (bytes)
+  u64 o_acc = 0, o_id_hist = 0, o_class_hist = 0, o_itb_hist = 0, o_ipt_hist = 0;
+  u64 o_sp_f = 0, o_sp_m = 0, o_seg_start = 0, o_seg_end = 0;
+  u64 zero_bytes = 0;
+  u64 o_itb_large = 0, o_ipt_large = 0, o_part_hist = 0, o_part_off = 0, o_part_rec = 0;
+  u64 o_br_a = 0, o_br_b = 0, o_br_cnt = 0, o_scan_tmp = 0;
+  u64 scratch_bytes = 0;
+  // result buffer offsets (bytes)
+  u64 r_metrics = 0, r_class = 0, r_spec = 0, result_bytes = 0;
+  u32 spec_export_cap = 0;
+};
+
+struct SizerState;
+struct BatchState;
+
+// Per-context stage timer (instrumentation; see aiwc_profile_*).
+struct Profiler : StageMarks {
+  bool on = false;
+  hipEvent_t start = nullptr;
+  std::vector<std::pair<std::string, hipEvent_t>> marks;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  void begin(hipStream_t s);
+  void mark(const char *name, hipStream_t s) override;
+  void release();
+};
+
+struct aiwc_ctx {
+  int device = 0;
+  int n_cu = 256;
+  std::string arch;
+  std::string err;
+  char *arena = nullptr;
+  u64 arena_bytes = 0;
+  hipEvent_t last_done = nullptr;
+  SizerState *sizer = nullptr;
+  BatchState *batch = nullptr;
+  aiwc_batch_stats last_stats{};
+  Profiler prof;
+};
+
+struct aiwc_trace {
+  aiwc_ctx *ctx = nullptr;
+  aiwc_trace_desc d{};
+  u32 n_classes = 0;
+  std::vector<u32> host_info;
+  u32 *dev_info = nullptr;
+};
+
+struct aiwc_metrics {
+  aiwc_ctx *ctx = nullptr;
+  TracePlan plan;
+  u32 n_classes = 0;
+  void *buf = nullptr;
+  hipEvent_t done = nullptr;
+  u32 spec_pairs[2] = {0, 0};
+};
+
+void ctx_error(aiwc_ctx *ctx, const char *fmt, ...);
+void plan_trace(const aiwc_trace *t, u32 pbits, TracePlan &p);
+u32 bound_pbits(u64 n_mem);
+void fill_args(const aiwc_trace *t, const TracePlan &p, char *scratch, char *result,
+               TraceArgs &a);
+hipError_t enqueue_trace(const TraceArgs &a, const TracePlan &p, char *scratch, hipStream_t s,
+                         StageMarks *pm);
+aiwc_status ensure_arena(aiwc_ctx *ctx, u64 bytes);
+aiwc_status new_metrics(aiwc_ctx *ctx, const aiwc_trace *t, const TracePlan &p,
+                        aiwc_metrics **out);
+aiwc_status characterize_planned(aiwc_ctx *ctx, const aiwc_trace *t, u32 pbits,
+                                 hipStream_t s, aiwc_metrics **out);
+aiwc_status validate_on_device(aiwc_ctx *ctx, const aiwc_trace *t);
+
+void sizer_init(aiwc_ctx *ctx);
+void sizer_free(aiwc_ctx *ctx);
+void batch_free(aiwc_ctx *ctx);

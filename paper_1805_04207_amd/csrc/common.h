@@ -1,0 +1,171 @@
+// common.h -- types and device helpers shared by the libaiwc kernels (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "aiwc.h"
+
+typedef unsigned long long u64;
+typedef unsigned int u32;
+
+#define AIWC_WAVE 64
+
+// ---------------------------------------------------------------- layout
+// Accumulators written by the stage kernels and read by the finalize kernel.
+// They live at the start of the per-trace zero region (cleared by a fill
+// kernel at the start of every characterization).
+#define SPEC_DENSE 256       // level-0 spectrum kept densely for f < 256
+#define VAL_DENSE 65536      // ITB / IPT value histograms are dense below this
+struct DevAccum {
+  u64 itb_min_inv, itb_max, itb_cnt, itb_sum;   // min stored as max of ~v
+  u64 ipt_min_inv, ipt_max, ipt_cnt, ipt_sum;
+  u64 barriers, bad_ids;
+  u64 itb_large_n, ipt_large_n;
+  u64 sp_reads[2], sp_writes[2];
+  u64 distinct[2][AIWC_NSKIP];
+  u64 ent_lo[2][AIWC_NSKIP], ent_hi[2][AIWC_NSKIP];  // fixed point, 2^-64 units
+  u64 uniq_r[2], uniq_w[2];
+  u64 spec_dense[2][SPEC_DENSE];
+  u64 redos;
+  u64 mem_queue;
+  u64 br_windows, br_minsum, yok_lo, yok_hi;
+  u64 br_queue;
+  u64 bad_mem;
+  u64 pad[4];
+};
+
+// Everything a kernel needs to know about one trace and its scratch.
+struct TraceArgs {
+  // inputs (device)
+  const uint16_t *opcode;
+  const u64 *wi_off;
+  const u64 *addr;
+  const uint8_t *mem_kind;
+  const u32 *br_site;
+  const uint8_t *br_taken;
+  const u32 *op_info;        // per id: kind | width << 8 | class << 16
+  u64 n_events, n_wi, n_mem, n_branch;
+  u32 n_ids, n_classes, n_sites, m;
+  // planning
+  u32 pbits;                 // memory partitions P = 2^pbits
+  u32 n_hist_blocks;         // blocks of the partition histogram / scatter
+  u64 hist_chunk;            // records per histogram block (multiple of 4)
+  u32 sp_cap;                // sparse spectrum capacity per space (pow2)
+  u32 br_passes;             // radix passes of 8 bits over the site ids
+  u64 br_tiles;              // 4096-element tiles of the branch stream
+  u64 br_blocks;             // windows work blocks
+  u64 large_cap;             // capacity of the ITB / IPT large-value lists
+  u64 ops_task;              // events per ops task
+  u64 ops_tasks;
+  // scratch (device)
+  DevAccum *acc;
+  u64 *id_hist;              // [n_ids]
+  u64 *class_hist;           // [n_classes]
+  u64 *itb_hist, *ipt_hist;  // [VAL_DENSE]
+  u64 *itb_large, *ipt_large;// [large_cap]
+  u64 *sp_f, *sp_m;          // [2][sp_cap] sparse level-0 spectrum (f >= 256)
+  u32 *seg_start, *seg_end;  // [n_sites]
+  u32 *part_hist;            // [n_hist_blocks][P]
+  u32 *part_off;             // [P + 1]
+  u64 *part_rec;             // [n_mem]
+  u32 *br_a, *br_b;          // [n_branch] radix ping-pong
+  u32 *br_cnt;               // [256 * br_tiles]
+  u32 *scan_tmp;             // block sums for the generic scan
+  // result (device)
+  aiwc_metrics_host *out;
+  u64 *out_class_hist;       // [n_classes]
+  u64 *out_spec;             // [2][SPEC_DENSE] then sparse export
+  u32 spec_export_cap;       // sparse pairs exported per space
+  u32 pad0;
+};
+
+// ------------------------------------------------------------ device math
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ u64 wave_sum_u64(u64 v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ void wave_sum_u128(u64 &lo, u64 &hi) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    u64 ol = __shfl_xor(lo, o, 64), oh = __shfl_xor(hi, o, 64);
+    u64 nl = lo + ol;
+    hi = hi + oh + (nl < lo ? 1ull : 0ull);
+    lo = nl;
+  }
+}
+
+// Exact 128-bit accumulation into a pair of u64 words (global or LDS).
+__device__ __forceinline__ void atomic_add_u128(u64 *lo, u64 *hi, u64 vlo, u64 vhi) {
+  if (vlo == 0 && vhi == 0) return;
+  u64 old = atomicAdd(lo, vlo);
+  u64 carry = (old + vlo < old) ? 1ull : 0ull;
+  if (vhi + carry) atomicAdd(hi, vhi + carry);
+}
+
+// Non-negative double -> unsigned fixed point with 64 fraction bits, as a
+// (lo, hi) pair.  Exact for every double below 2^63; bits below 2^-64 are
+// truncated.
+__device__ __forceinline__ void to_fx64(double d, u64 &lo, u64 &hi) {
+  lo = hi = 0;
+  if (!(d > 0.0)) return;
+  int e;
+  double mant = frexp(d, &e);                 // d = mant * 2^e, mant in [0.5,1)
+  u64 m53 = (u64)ldexp(mant, 53);             // exact
+  int sh = e - 53 + 64;                       // value * 2^64 = m53 * 2^sh
+  if (sh >= 128) { lo = hi = ~0ull; return; }
+  if (sh >= 64) { hi = m53 << (sh - 64); lo = 0; }
+  else if (sh > 0) { lo = m53 << sh; hi = m53 >> (64 - sh); }
+  else if (sh == 0) { lo = m53; }
+  else if (sh > -64) { lo = m53 >> (-sh); }
+}
+
+__host__ __device__ __forceinline__ double fx64_to_double(u64 lo, u64 hi) {
+  return ((double)hi * 18446744073709551616.0 + (double)lo) * 5.421010862427522170e-20;
+}
+
+// A bijection of the 54-bit page numbers (address >> 10): multiply by odd
+// constants and xor-shift inside 54 bits.  Spreads pages over partitions.
+#define PAGE_BITS 54
+__device__ __forceinline__ u64 mix54(u64 x) {
+  const u64 M = (1ull << PAGE_BITS) - 1ull;
+  x &= M;
+  x = (x * 0x2545F4914F6CDD1Dull) & M;
+  x ^= x >> 27;
+  x = (x * 0x1D8E4E27C47D124Full) & M;
+  x ^= x >> 25;
+  x = (x * 0x3C79AC492BA7B653ull) & M;
+  x ^= x >> 29;
+  return x;
+}
+
+__device__ __forceinline__ u32 hash_slot(u64 key, u32 cap) {
+  u64 h = key * 0x9E3779B97F4A7C15ull;
+  h ^= h >> 31;
+  h *= 0xBF58476D1CE4E5B9ull;
+  u32 x = (u32)(h >> 32);
+  return (u32)(((u64)x * cap) >> 32);
+}
+
+// ---------------------------------------------------------- host helpers
+// Optional instrumentation: when set, a hipEvent is recorded on the stream
+// after every kernel launch, tagged with the kernel's name.
+struct StageMarks {
+  virtual void mark(const char *name, hipStream_t s) = 0;
+  virtual ~StageMarks() {}
+};
+
+namespace aiwc_kernels {
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);
+hipError_t launch_ops(const TraceArgs &a, hipStream_t s, StageMarks *pm);
+hipError_t launch_mem(const TraceArgs &a, hipStream_t s, StageMarks *pm);
+hipError_t launch_branch(const TraceArgs &a, hipStream_t s, StageMarks *pm);
+hipError_t launch_finalize(const TraceArgs &a, hipStream_t s, StageMarks *pm);
+}  // namespace aiwc_kernels
+
+#define AIWC_MARK(pm, name, s) \
+  do { if (pm) (pm)->mark(name, s); } while (0)

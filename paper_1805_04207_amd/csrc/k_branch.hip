@@ -1,0 +1,394 @@
+// k_branch.hip -- control metrics (Table I, Control rows).
+//
+// Reading of the paper's branch metrics (Implementation section: a
+// per-site vector of outcomes; Metrics section: histories of 16 outcomes):
+// every site keeps the history of its own previous m outcomes; an execution
+// forms a window only once m earlier outcomes of its site exist.  For each
+// key (site, history) with n0 / n1 following outcomes,
+//   Yokota entropy  = sum [n0 log2(n/n0) + n1 log2(n/n1)] / N_w
+//   linear entropy  = 2 sum min(n0, n1) / N_w.
+//
+// GPU plan:
+//  1. k_br_pack     : (site, taken) -> u32 (site << 1 | taken), validated.
+//  2. stable LSD radix sort by site, 8 bits per pass: per-tile digit counts
+//     (k_br_upsweep), one exclusive scan, and a stable scatter whose ranks
+//     come from wavefront ballots (k_br_downsweep).  After it every site's
+//     outcomes are contiguous and in stream order.
+//  3. k_br_segments : start / end of every site segment.
+//  4. k_br_windows  : work blocks of whole segments; each element's history
+//     is m bits cut out of two 64-bit outcome ballots with funnel shifts;
+//     (site, history) keys are counted in an LDS open-addressing table; the
+//     table's entries give min(n0, n1) (exact integers) and the Yokota terms
+//     (exact 128-bit fixed point sums, so the result is order independent).
+//     A block whose distinct keys overflow the table is split by key hash
+//     bits and redone.
+#include "common.h"
+
+namespace {
+
+constexpr int BR_BLOCK = 256;
+constexpr int BR_TILE = 4096;                 // elements per radix tile
+constexpr int BR_ROUNDS = BR_TILE / BR_BLOCK; // 16
+constexpr int WIN_BLOCK = 1024;
+constexpr u64 WIN_T = 4096;                   // windows work-block size
+constexpr u32 WT_C = 8192;                    // LDS table slots
+constexpr u32 WT_CAP = 6656;
+constexpr u64 EMPTY = ~0ull;
+
+// ------------------------------------------------------------------ pack
+__global__ void k_br_pack(TraceArgs A, u32 *out) {
+  u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+  const u64 stride = (u64)gridDim.x * blockDim.x;
+  u32 bad = 0;
+  for (; i < A.n_branch; i += stride) {
+    const u32 s = A.br_site[i];
+    const u32 y = A.br_taken[i];
+    if (s >= A.n_sites || y > 1u) { bad += 1; out[i] = 0; continue; }
+    out[i] = (s << 1) | y;
+  }
+  u64 b = wave_sum_u64(bad);
+  if (lane_id() == 0 && b) atomicAdd(&A.acc->bad_mem, b);
+}
+
+// -------------------------------------------------------------- radix sort
+__global__ void __launch_bounds__(BR_BLOCK) k_br_upsweep(const u32 *in, u64 n, u32 shift,
+                                                        u32 *cnt, u64 n_tiles) {
+  __shared__ u32 h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const u64 t = blockIdx.x;
+  const u64 base = t * BR_TILE;
+  for (int r = 0; r < BR_ROUNDS; ++r) {
+    const u64 i = base + (u64)r * BR_BLOCK + threadIdx.x;
+    if (i < n) atomicAdd(&h[(in[i] >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  cnt[(u64)threadIdx.x * n_tiles + t] = h[threadIdx.x];
+}
+
+__global__ void __launch_bounds__(BR_BLOCK) k_br_downsweep(const u32 *in, u32 *out, u64 n,
+                                                          u32 shift, const u32 *ofs,
+                                                          u64 n_tiles) {
+  __shared__ u32 gofs[256];
+  __shared__ u32 running[256];
+  __shared__ u32 wcnt[BR_BLOCK / AIWC_WAVE][256];
+  const int tid = threadIdx.x, lane = lane_id(), wave = tid / AIWC_WAVE;
+  const u64 t = blockIdx.x;
+  gofs[tid] = ofs[(u64)tid * n_tiles + t];
+  running[tid] = 0;
+  const u64 base = t * BR_TILE;
+  const u64 lt = (1ull << lane) - 1ull;
+  for (int r = 0; r < BR_ROUNDS; ++r) {
+#pragma unroll
+    for (int w = 0; w < BR_BLOCK / AIWC_WAVE; ++w) wcnt[w][tid] = 0;
+    __syncthreads();
+    const u64 i = base + (u64)r * BR_BLOCK + tid;
+    const bool valid = i < n;
+    const u32 v = valid ? in[i] : 0u;
+    const u32 d = (v >> shift) & 255u;
+    u64 peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const u64 m = __ballot((d >> b) & 1u);
+      peers &= ((d >> b) & 1u) ? m : ~m;
+    }
+    const u32 rank = (u32)__builtin_popcountll(peers & lt);
+    if (valid && rank == 0) wcnt[wave][d] = (u32)__builtin_popcountll(peers);
+    __syncthreads();
+    if (valid) {
+      u32 before = running[d];
+      for (int w = 0; w < wave; ++w) before += wcnt[w][d];
+      out[gofs[d] + before + rank] = v;
+    }
+    __syncthreads();
+    u32 add = 0;
+#pragma unroll
+    for (int w = 0; w < BR_BLOCK / AIWC_WAVE; ++w) add += wcnt[w][tid];
+    running[tid] += add;
+  }
+}
+
+// Generic exclusive scan of u32 values (totals < 2^32): block sums, a scan of
+// the sums in one block, then per-block scans with the carried offset.
+constexpr int SCAN_BLOCK = 1024;
+constexpr int SCAN_PER = 8;
+constexpr u64 SCAN_TILE = (u64)SCAN_BLOCK * SCAN_PER;
+
+__device__ u32 block_exclusive_scan(u32 v, u32 *wsum, u32 &total) {
+  u32 x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    u32 y = __shfl_up(x, o, 64);
+    if (lane_id() >= o) x += y;
+  }
+  if (lane_id() == 63) wsum[threadIdx.x / 64] = x;
+  __syncthreads();
+  u32 before = 0, tot = 0;
+  for (u32 w = 0; w < blockDim.x / 64; ++w) {
+    if (w < threadIdx.x / 64) before += wsum[w];
+    tot += wsum[w];
+  }
+  __syncthreads();
+  total = tot;
+  return before + x - v;
+}
+
+__global__ void __launch_bounds__(SCAN_BLOCK) k_scan_reduce(const u32 *in, u64 n, u32 *sums) {
+  __shared__ u32 wsum[16];
+  const u64 base = (u64)blockIdx.x * SCAN_TILE;
+  u32 s = 0;
+  for (int j = 0; j < SCAN_PER; ++j) {
+    const u64 i = base + (u64)j * SCAN_BLOCK + threadIdx.x;
+    if (i < n) s += in[i];
+  }
+  u32 tot;
+  block_exclusive_scan(s, wsum, tot);
+  if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+__global__ void __launch_bounds__(SCAN_BLOCK) k_scan_sums(u32 *sums, u64 nb) {
+  __shared__ u32 wsum[16];
+  __shared__ u32 carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (u64 b = 0; b < nb; b += SCAN_BLOCK) {
+    const u64 i = b + threadIdx.x;
+    const u32 v = i < nb ? sums[i] : 0u;
+    u32 tot;
+    const u32 ex = block_exclusive_scan(v, wsum, tot);
+    const u32 c = carry;
+    if (i < nb) sums[i] = c + ex;
+    __syncthreads();
+    if (threadIdx.x == 0) carry = c + tot;
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(SCAN_BLOCK) k_scan_apply(u32 *data, u64 n, const u32 *sums) {
+  __shared__ u32 wsum[16];
+  const u64 base = (u64)blockIdx.x * SCAN_TILE;
+  // each thread owns SCAN_PER consecutive elements
+  u32 v[SCAN_PER];
+  u32 s = 0;
+  const u64 mine = base + (u64)threadIdx.x * SCAN_PER;
+#pragma unroll
+  for (int j = 0; j < SCAN_PER; ++j) {
+    v[j] = (mine + j < n) ? data[mine + j] : 0u;
+    s += v[j];
+  }
+  u32 tot;
+  u32 ex = block_exclusive_scan(s, wsum, tot) + sums[blockIdx.x];
+#pragma unroll
+  for (int j = 0; j < SCAN_PER; ++j) {
+    if (mine + j < n) data[mine + j] = ex;
+    ex += v[j];
+  }
+}
+
+// ------------------------------------------------------------- segments
+__global__ void k_br_segments(TraceArgs A, const u32 *sorted) {
+  u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+  const u64 stride = (u64)gridDim.x * blockDim.x;
+  const u64 n = A.n_branch;
+  for (; i < n; i += stride) {
+    const u32 s = sorted[i] >> 1;
+    if (i == 0 || (sorted[i - 1] >> 1) != s) A.seg_start[s] = (u32)i;
+    if (i + 1 == n || (sorted[i + 1] >> 1) != s) A.seg_end[s] = (u32)(i + 1);
+  }
+}
+
+// --------------------------------------------------------------- windows
+struct WinShared {
+  u64 key[WT_C];
+  u32 n0[WT_C], n1[WT_C];
+  uint16_t live[WT_C];
+  u64 tlo[256], thi[256];     // Yokota terms for n0, n1 < 16
+  u64 minsum, windows, ylo, yhi;
+  u32 live_n, overflow, work;
+  u32 stack_m[64], stack_c[64];
+  u32 sp_top;
+};
+
+// n0 log2(n / n0) + n1 log2(n / n1), 2^-64 fixed point
+__device__ __forceinline__ void yterm(u32 a, u32 b, u64 &lo, u64 &hi) {
+  if (a == 0 || b == 0) { lo = hi = 0; return; }
+  const double da = (double)a, db = (double)b;
+  const double d = (da * log1p(db / da) + db * log1p(da / db)) * 1.4426950408889634074;
+  to_fx64(d, lo, hi);
+}
+
+__device__ __forceinline__ u64 range_begin(const TraceArgs &A, const u32 *sorted, u64 b) {
+  const u64 x = b * WIN_T;
+  if (x == 0) return 0;
+  if (x >= A.n_branch) return A.n_branch;
+  const u32 s = sorted[x] >> 1;
+  if ((sorted[x - 1] >> 1) != s) return x;
+  return A.seg_end[s];
+}
+
+__device__ __forceinline__ bool win_insert(WinShared &S, u64 key, u32 y) {
+  u32 slot = hash_slot(key, WT_C);
+  while (true) {
+    u64 w = S.key[slot];
+    if (w == EMPTY) {
+      if (S.live_n >= WT_CAP) { S.overflow = 1; return false; }
+      u64 old = atomicCAS(&S.key[slot], EMPTY, key);
+      if (old == EMPTY) {
+        u32 idx = atomicAdd(&S.live_n, 1u);
+        if (idx < WT_C) S.live[idx] = (uint16_t)slot;
+        w = key;
+      } else {
+        w = old;
+      }
+    }
+    if (w == key) {
+      atomicAdd(y ? &S.n1[slot] : &S.n0[slot], 1u);
+      return true;
+    }
+    slot = (slot + 1 == WT_C) ? 0 : slot + 1;
+  }
+}
+
+__global__ void __launch_bounds__(WIN_BLOCK) k_br_windows(TraceArgs A, const u32 *sorted) {
+  __shared__ WinShared S;
+  const int tid = threadIdx.x, lane = lane_id(), wave = tid / AIWC_WAVE;
+  const u32 m = A.m;
+  const u64 hmask = (m >= 64) ? ~0ull : ((1ull << m) - 1ull);
+  for (u32 i = tid; i < WT_C; i += WIN_BLOCK) { S.key[i] = EMPTY; S.n0[i] = 0; S.n1[i] = 0; }
+  if (tid < 256) yterm(tid >> 4, tid & 15, S.tlo[tid], S.thi[tid]);
+  if (tid == 0) { S.minsum = S.windows = S.ylo = S.yhi = 0; S.live_n = 0; S.overflow = 0; }
+  __syncthreads();
+  while (true) {
+    if (tid == 0) S.work = (u32)atomicAdd(&A.acc->br_queue, 1ull);
+    __syncthreads();
+    const u64 b = S.work;
+    if (b >= A.br_blocks) break;
+    const u64 r0 = range_begin(A, sorted, b), r1 = range_begin(A, sorted, b + 1);
+    if (r1 <= r0) { __syncthreads(); continue; }
+    if (tid == 0) { S.sp_top = 1; S.stack_m[0] = 1; S.stack_c[0] = 0; }
+    __syncthreads();
+    while (S.sp_top > 0) {
+      __syncthreads();
+      const u32 M = S.stack_m[S.sp_top - 1], C = S.stack_c[S.sp_top - 1];
+      __syncthreads();
+      if (tid == 0) S.sp_top -= 1;
+      bool stop = false;
+      for (u64 cb = r0 + (u64)wave * AIWC_WAVE; cb < r1; cb += (u64)WIN_BLOCK) {
+        const u64 i = cb + lane;
+        const bool valid = i < r1;
+        const u32 v = valid ? sorted[i] : 0u;
+        const u64 ip = i - AIWC_WAVE;                 // same lane, previous chunk
+        const u32 vp = (cb >= AIWC_WAVE) ? sorted[ip] : 0u;
+        const u64 B = __ballot(valid && (v & 1u));
+        const u64 Bp = __ballot((cb >= AIWC_WAVE) && (vp & 1u));
+        if (!valid || stop) continue;
+        const u32 s = v >> 1;
+        if (i - A.seg_start[s] < m) continue;
+        const u32 sh = 64u + (u32)lane - m;           // in [32, 127]
+        u64 E;
+        if (sh >= 64) E = B >> (sh - 64);
+        else E = (Bp >> sh) | (B << (64 - sh));
+        E &= hmask;
+        const u64 key = ((u64)s << m) | E;
+        if (M > 1 && (((u32)((key * 0x9E3779B97F4A7C15ull) >> 40)) & (M - 1u)) != C) continue;
+        if (!win_insert(S, key, v & 1u)) stop = true;
+      }
+      __syncthreads();
+      const u32 D = S.live_n < WT_C ? S.live_n : WT_C;
+      if (S.overflow || S.live_n > WT_CAP) {
+        for (u32 j = tid; j < D; j += WIN_BLOCK) {
+          const u32 slot = S.live[j];
+          S.key[slot] = EMPTY; S.n0[slot] = 0; S.n1[slot] = 0;
+        }
+        __syncthreads();
+        if (tid == 0) {
+          S.live_n = 0; S.overflow = 0;
+          if (M >= (1u << 23) || S.sp_top + 2 > 64) {
+            atomicAdd(&A.acc->bad_mem, 1ull);   // hash bits exhausted: report
+          } else {
+            S.stack_m[S.sp_top] = 2 * M; S.stack_c[S.sp_top] = C;
+            S.stack_m[S.sp_top + 1] = 2 * M; S.stack_c[S.sp_top + 1] = C + M;
+            S.sp_top += 2;
+          }
+        }
+        __syncthreads();
+        continue;
+      }
+      u64 mins = 0, wins = 0, lo = 0, hi = 0;
+      for (u32 j = tid; j < D; j += WIN_BLOCK) {
+        const u32 slot = S.live[j];
+        const u32 a = S.n0[slot], c = S.n1[slot];
+        mins += a < c ? a : c;
+        wins += (u64)a + c;
+        u64 tl, th;
+        if (a < 16 && c < 16) { tl = S.tlo[a * 16 + c]; th = S.thi[a * 16 + c]; }
+        else yterm(a, c, tl, th);
+        u64 nl = lo + tl; hi += th + (nl < lo); lo = nl;
+        S.key[slot] = EMPTY; S.n0[slot] = 0; S.n1[slot] = 0;
+      }
+      mins = wave_sum_u64(mins);
+      wins = wave_sum_u64(wins);
+      wave_sum_u128(lo, hi);
+      if (lane == 0) {
+        if (mins) atomicAdd(&S.minsum, mins);
+        if (wins) atomicAdd(&S.windows, wins);
+        atomic_add_u128(&S.ylo, &S.yhi, lo, hi);
+      }
+      __syncthreads();
+      if (tid == 0) S.live_n = 0;
+      __syncthreads();
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+  if (tid == 0) {
+    if (S.minsum) atomicAdd(&A.acc->br_minsum, S.minsum);
+    if (S.windows) atomicAdd(&A.acc->br_windows, S.windows);
+    atomic_add_u128(&A.acc->yok_lo, &A.acc->yok_hi, S.ylo, S.yhi);
+  }
+}
+
+hipError_t scan_u32(u32 *data, u64 n, u32 *tmp, hipStream_t s) {
+  const u64 nb = (n + SCAN_TILE - 1) / SCAN_TILE;
+  if (nb == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(SCAN_BLOCK), 0, s, data, n, tmp);
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(SCAN_BLOCK), 0, s, tmp, nb);
+  hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(SCAN_BLOCK), 0, s, data, n, tmp);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+namespace aiwc_kernels {
+
+u64 scan_tmp_elems(u64 n) { return (n + SCAN_TILE - 1) / SCAN_TILE + 1; }
+u64 br_tiles_for(u64 n) { return (n + BR_TILE - 1) / BR_TILE; }
+u64 br_blocks_for(u64 n) { return (n + WIN_T - 1) / WIN_T; }
+
+hipError_t launch_branch(const TraceArgs &a, hipStream_t s, StageMarks *pm) {
+  if (a.n_branch == 0) return hipSuccess;
+  unsigned g = (unsigned)((a.n_branch + 255) / 256);
+  if (g > 8192) g = 8192;
+  hipLaunchKernelGGL(k_br_pack, dim3(g), dim3(256), 0, s, a, a.br_a);
+  AIWC_MARK(pm, "k_br_pack", s);
+  u32 *cur = a.br_a, *nxt = a.br_b;
+  for (u32 p = 0; p < a.br_passes; ++p) {
+    const u32 shift = 1u + 8u * p;
+    hipLaunchKernelGGL(k_br_upsweep, dim3((unsigned)a.br_tiles), dim3(BR_BLOCK), 0, s, cur,
+                       a.n_branch, shift, a.br_cnt, a.br_tiles);
+    hipError_t e = scan_u32(a.br_cnt, 256ull * a.br_tiles, a.scan_tmp, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_br_downsweep, dim3((unsigned)a.br_tiles), dim3(BR_BLOCK), 0, s, cur, nxt,
+                       a.n_branch, shift, a.br_cnt, a.br_tiles);
+    u32 *t = cur; cur = nxt; nxt = t;
+  }
+  AIWC_MARK(pm, "k_br_sort", s);
+  hipLaunchKernelGGL(k_br_segments, dim3(g), dim3(256), 0, s, a, cur);
+  AIWC_MARK(pm, "k_br_segments", s);
+  u64 nb = a.br_blocks < 256 ? a.br_blocks : 256;
+  hipLaunchKernelGGL(k_br_windows, dim3((unsigned)nb), dim3(WIN_BLOCK), 0, s, a, cur);
+  AIWC_MARK(pm, "k_br_windows", s);
+  return hipGetLastError();
+}
+
+}  // namespace aiwc_kernels

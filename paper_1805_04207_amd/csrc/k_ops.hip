@@ -1,0 +1,253 @@
+// k_ops.hip -- the instruction stream pass (compute and parallelism metrics).
+//
+// One pass over the u16 opcode stream produces
+//  * the per-id instruction histogram (Table I, Compute rows: opcode counts;
+//    the SIMD width statistics follow from it exactly, since a width is a
+//    property of the id), and
+//  * the instructions-to-barrier and instructions-per-thread samples (Table I,
+//    Parallelism rows; Metrics section: a per-work-item tally saved and reset
+//    at each barrier, the end of the kernel being a final implicit barrier).
+//
+// Work decomposition: the stream is cut into tasks of ~ops_task events whose
+// boundaries are snapped to work-item boundaries (binary search in
+// wi_offsets), so no ITB segment crosses a task.  A wavefront owns a task and
+// walks it in 512-event chunks: 8 coalesced u16 loads per lane, barrier
+// positions gathered with ballots, and the (rare) barrier and work-item end
+// markers walked in wave-uniform scalar code.  Histogram increments go to
+// LDS copies (lane % ncopies) to spread same-id conflicts of the Zipf-like
+// opcode mix.
+#include "common.h"
+
+namespace {
+
+constexpr int OPS_BLOCK = 256;
+constexpr int OPS_WAVES = OPS_BLOCK / AIWC_WAVE;
+constexpr u32 LDS_VALS = 4096;   // ITB / IPT values below this counted in LDS
+constexpr u32 KIND_BARRIER = AIWC_KIND_BARRIER;
+
+__device__ __forceinline__ u64 lower_bound(const u64 *a, u64 n, u64 x) {
+  // first i in [0, n) with a[i] >= x (n if none)
+  u64 lo = 0, hi = n;
+  while (lo < hi) {
+    u64 mid = (lo + hi) >> 1;
+    if (a[mid] < x) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+struct WaveStats {
+  u64 itb_min, itb_max, itb_cnt, itb_sum;
+  u64 ipt_min, ipt_max, ipt_cnt, ipt_sum;
+  u64 barriers, bad;
+};
+
+__device__ __forceinline__ void record_value(u64 v, u32 *lds_hist, u64 *g_hist,
+                                             u64 *g_large, u64 *g_large_n, u64 cap,
+                                             int lane) {
+  if (lane == 0) {
+    if (v < LDS_VALS) atomicAdd(&lds_hist[v], 1u);
+    else if (v < VAL_DENSE) atomicAdd(&g_hist[v], 1ull);
+    else {
+      u64 i = atomicAdd(g_large_n, 1ull);
+      if (i < cap) g_large[i] = v;
+    }
+  }
+}
+
+template <bool LDS_IDS>
+__global__ void __launch_bounds__(OPS_BLOCK) k_ops(TraceArgs A, u32 ncopies) {
+  extern __shared__ u32 lds[];
+  const u32 nid = A.n_ids;
+  WaveStats *ws = (WaveStats *)lds;                   // [OPS_WAVES]
+  u32 *itbh = lds + OPS_WAVES * sizeof(WaveStats) / 4; // [LDS_VALS]
+  u32 *ipth = itbh + LDS_VALS;                        // [LDS_VALS]
+  u32 *hist = ipth + LDS_VALS;                        // [ncopies][nid]
+  u32 *info = hist + (LDS_IDS ? ncopies * nid : 0);   // [nid]
+
+  const int tid = threadIdx.x, lane = lane_id(), wave = tid / AIWC_WAVE;
+  if (LDS_IDS) {
+    for (u32 i = tid; i < ncopies * nid; i += OPS_BLOCK) hist[i] = 0;
+    for (u32 i = tid; i < nid; i += OPS_BLOCK) info[i] = A.op_info[i];
+  }
+  for (u32 i = tid; i < 2 * LDS_VALS; i += OPS_BLOCK) itbh[i] = 0;
+  __syncthreads();
+
+  const u32 copy = LDS_IDS ? (u32)lane & (ncopies - 1u) : 0u;
+  WaveStats st;
+  st.itb_min = st.ipt_min = ~0ull;
+  st.itb_max = st.itb_cnt = st.itb_sum = 0;
+  st.ipt_max = st.ipt_cnt = st.ipt_sum = 0;
+  st.barriers = st.bad = 0;
+
+  const u64 nwaves = (u64)gridDim.x * OPS_WAVES;
+  for (u64 t = (u64)blockIdx.x * OPS_WAVES + wave; t < A.ops_tasks; t += nwaves) {
+    u64 w_lo = lower_bound(A.wi_off, A.n_wi + 1, t * A.ops_task);
+    u64 w_hi = (t + 1 == A.ops_tasks) ? A.n_wi
+                                      : lower_bound(A.wi_off, A.n_wi + 1, (t + 1) * A.ops_task);
+    if (w_lo > A.n_wi) w_lo = A.n_wi;
+    if (w_hi > A.n_wi) w_hi = A.n_wi;
+    if (w_hi <= w_lo) continue;
+    // clamp to the stream so malformed offsets cannot read past it
+    const u64 e1 = A.wi_off[w_hi] < A.n_events ? A.wi_off[w_hi] : A.n_events;
+    const u64 e0 = A.wi_off[w_lo] < e1 ? A.wi_off[w_lo] : e1;
+    u64 cur_w = w_lo, cur_begin = e0, seg_start = e0;
+    u64 cur_end = A.wi_off[cur_w + 1];
+
+    for (u64 cb = e0; cb < e1; cb += 8 * AIWC_WAVE) {
+      u32 ids[8];
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        u64 i = cb + (u64)s * AIWC_WAVE + lane;
+        ids[s] = (i < e1) ? (u32)A.opcode[i] : 0xFFFFFFFFu;
+      }
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        const u64 sb = cb + (u64)s * AIWC_WAVE;
+        if (sb >= e1) break;
+        const u32 id = ids[s];
+        bool isbar = false;
+        if (id != 0xFFFFFFFFu) {
+          if (id < nid) {
+            u32 in;
+            if (LDS_IDS) {
+              in = info[id];
+              atomicAdd(&hist[copy * nid + id], 1u);
+            } else {
+              in = A.op_info[id];
+              atomicAdd(&A.id_hist[id], 1ull);
+            }
+            isbar = (in & 0xFFu) == KIND_BARRIER;
+          } else {
+            st.bad += 1;  // per lane; summed at the end
+          }
+        }
+        u64 B = __ballot(isbar);
+        const u64 lim = (sb + AIWC_WAVE < e1) ? sb + AIWC_WAVE : e1;
+        // walk barrier and work-item-end markers of [sb, lim) in order
+        while (true) {
+          const u64 nb = B ? sb + (u64)__builtin_ctzll(B) : ~0ull;
+          if (cur_w < w_hi && cur_end <= lim && cur_end <= nb) {
+            const u64 v = cur_end - seg_start, ipt = cur_end - cur_begin;
+            record_value(v, itbh, A.itb_hist, A.itb_large, &A.acc->itb_large_n, A.large_cap, lane);
+            record_value(ipt, ipth, A.ipt_hist, A.ipt_large, &A.acc->ipt_large_n, A.large_cap, lane);
+            st.itb_min = v < st.itb_min ? v : st.itb_min;
+            st.itb_max = v > st.itb_max ? v : st.itb_max;
+            st.itb_cnt += 1; st.itb_sum += v;
+            st.ipt_min = ipt < st.ipt_min ? ipt : st.ipt_min;
+            st.ipt_max = ipt > st.ipt_max ? ipt : st.ipt_max;
+            st.ipt_cnt += 1; st.ipt_sum += ipt;
+            seg_start = cur_begin = cur_end;
+            ++cur_w;
+            cur_end = (cur_w < w_hi) ? A.wi_off[cur_w + 1] : ~0ull;
+            continue;
+          }
+          if (B == 0) break;
+          const u64 v = nb + 1 - seg_start;
+          record_value(v, itbh, A.itb_hist, A.itb_large, &A.acc->itb_large_n, A.large_cap, lane);
+          st.itb_min = v < st.itb_min ? v : st.itb_min;
+          st.itb_max = v > st.itb_max ? v : st.itb_max;
+          st.itb_cnt += 1; st.itb_sum += v;
+          st.barriers += 1;
+          seg_start = nb + 1;
+          B &= B - 1;
+        }
+      }
+    }
+    // work-items left open at the end of the task (trailing empty ones)
+    while (cur_w < w_hi) {
+      const u64 v = cur_end - seg_start, ipt = cur_end - cur_begin;
+      record_value(v, itbh, A.itb_hist, A.itb_large, &A.acc->itb_large_n, A.large_cap, lane);
+      record_value(ipt, ipth, A.ipt_hist, A.ipt_large, &A.acc->ipt_large_n, A.large_cap, lane);
+      st.itb_min = v < st.itb_min ? v : st.itb_min;
+      st.itb_max = v > st.itb_max ? v : st.itb_max;
+      st.itb_cnt += 1; st.itb_sum += v;
+      st.ipt_min = ipt < st.ipt_min ? ipt : st.ipt_min;
+      st.ipt_max = ipt > st.ipt_max ? ipt : st.ipt_max;
+      st.ipt_cnt += 1; st.ipt_sum += ipt;
+      seg_start = cur_begin = cur_end;
+      ++cur_w;
+      cur_end = (cur_w < w_hi) ? A.wi_off[cur_w + 1] : ~0ull;
+    }
+  }
+  st.bad = wave_sum_u64(st.bad);
+  if (lane == 0) ws[wave] = st;
+  __syncthreads();
+
+  if (LDS_IDS) {
+    for (u32 id = tid; id < nid; id += OPS_BLOCK) {
+      u64 s = 0;
+      for (u32 c = 0; c < ncopies; ++c) s += hist[c * nid + id];
+      if (s) atomicAdd(&A.id_hist[id], s);
+    }
+  }
+  for (u32 v = tid; v < LDS_VALS; v += OPS_BLOCK) {
+    if (itbh[v]) atomicAdd(&A.itb_hist[v], (u64)itbh[v]);
+    if (ipth[v]) atomicAdd(&A.ipt_hist[v], (u64)ipth[v]);
+  }
+  if (tid == 0) {
+    WaveStats r = ws[0];
+    for (int w = 1; w < OPS_WAVES; ++w) {
+      const WaveStats &o = ws[w];
+      r.itb_min = o.itb_min < r.itb_min ? o.itb_min : r.itb_min;
+      r.itb_max = o.itb_max > r.itb_max ? o.itb_max : r.itb_max;
+      r.ipt_min = o.ipt_min < r.ipt_min ? o.ipt_min : r.ipt_min;
+      r.ipt_max = o.ipt_max > r.ipt_max ? o.ipt_max : r.ipt_max;
+      r.itb_cnt += o.itb_cnt; r.itb_sum += o.itb_sum;
+      r.ipt_cnt += o.ipt_cnt; r.ipt_sum += o.ipt_sum;
+      r.barriers += o.barriers; r.bad += o.bad;
+    }
+    DevAccum *acc = A.acc;
+    if (r.itb_cnt) {
+      atomicMax(&acc->itb_min_inv, ~r.itb_min);
+      atomicMax(&acc->itb_max, r.itb_max);
+      atomicAdd(&acc->itb_cnt, r.itb_cnt);
+      atomicAdd(&acc->itb_sum, r.itb_sum);
+    }
+    if (r.ipt_cnt) {
+      atomicMax(&acc->ipt_min_inv, ~r.ipt_min);
+      atomicMax(&acc->ipt_max, r.ipt_max);
+      atomicAdd(&acc->ipt_cnt, r.ipt_cnt);
+      atomicAdd(&acc->ipt_sum, r.ipt_sum);
+    }
+    if (r.barriers) atomicAdd(&acc->barriers, r.barriers);
+    if (r.bad) atomicAdd(&acc->bad_ids, r.bad);
+  }
+}
+
+__global__ void k_zero(uint4 *p, size_t n16) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (; i < n16; i += stride) p[i] = make_uint4(0, 0, 0, 0);
+}
+
+}  // namespace
+
+namespace aiwc_kernels {
+
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t s) {
+  size_t n16 = bytes / 16;
+  if (n16 == 0) return hipSuccess;
+  unsigned grid = (unsigned)((n16 + 255) / 256);
+  if (grid > 4096) grid = 4096;
+  hipLaunchKernelGGL(k_zero, dim3(grid), dim3(256), 0, s, (uint4 *)p, n16);
+  return hipGetLastError();
+}
+
+hipError_t launch_ops(const TraceArgs &a, hipStream_t s, StageMarks *pm) {
+  if (a.ops_tasks == 0) return hipSuccess;
+  u64 waves = a.ops_tasks < 4096 ? a.ops_tasks : 4096;
+  unsigned grid = (unsigned)((waves + OPS_WAVES - 1) / OPS_WAVES);
+  size_t tail = 2 * LDS_VALS * 4 + OPS_WAVES * sizeof(WaveStats);
+  if (a.n_ids <= 8192) {
+    u32 nc = 1;
+    while (nc < 16 && (size_t)(nc * 2) * a.n_ids * 4 <= 32768) nc *= 2;
+    size_t lds = ((size_t)nc * a.n_ids + a.n_ids) * 4 + tail;
+    hipLaunchKernelGGL(k_ops<true>, dim3(grid), dim3(OPS_BLOCK), lds, s, a, nc);
+  } else {
+    hipLaunchKernelGGL(k_ops<false>, dim3(grid), dim3(OPS_BLOCK), tail, s, a, 1u);
+  }
+  AIWC_MARK(pm, "k_ops", s);
+  return hipGetLastError();
+}
+
+}  // namespace aiwc_kernels
