@@ -50,14 +50,16 @@ static inline u32 ceil_log2(u64 x) {
 // ------------------------------------------------------------------ plan
 // Scratch layout of one trace: a zero region (cleared by a kernel) followed
 // by buffers that every stage fully writes before reading.
-void plan_trace(const aiwc_trace *t, u32 pbits, TracePlan &p) {
+void plan_trace(const aiwc_trace *t, u32 pbits, TracePlan &p, const Tune *tune) {
   const aiwc_trace_desc &d = t->d;
+  const Tune T = tune ? *tune : Tune();
   p = TracePlan();
-  p.pbits = d.n_mem ? pbits : 4;
+  int pb = (int)pbits + T.part_shift;
+  p.pbits = d.n_mem ? (u32)std::min(15, std::max(4, pb)) : 4;
   const u64 P = 1ull << p.pbits;
-  // memory: histogram blocks = one per CU at most, >= 16K records each
+  // memory: histogram blocks up to the tuned maximum, >= 16K records each
   u64 nb = (d.n_mem + 16383) / 16384;
-  nb = std::max<u64>(1, std::min<u64>(nb, 256));
+  nb = std::max<u64>(1, std::min<u64>(nb, std::max<u32>(1, T.hist_blocks)));
   p.n_hist_blocks = (u32)nb;
   p.hist_chunk = align_up((d.n_mem + nb - 1) / nb, 4);
   if (p.hist_chunk == 0) p.hist_chunk = 4;
@@ -71,6 +73,8 @@ void plan_trace(const aiwc_trace *t, u32 pbits, TracePlan &p) {
   // ops
   p.large_cap = d.n_events / 65536 + 1;
   u64 E = std::max<u64>(4096, (d.n_events + 16383) / 16384);
+  if (T.ops_shift > 0) E <<= T.ops_shift;
+  if (T.ops_shift < 0) E = std::max<u64>(2048, E >> (-T.ops_shift));
   p.ops_task = align_up(E, 512);
   p.ops_tasks = std::max<u64>(1, (d.n_events + p.ops_task - 1) / p.ops_task);
 
@@ -163,16 +167,42 @@ void fill_args(const aiwc_trace *t, const TracePlan &p, char *scratch, char *res
   a.out_class_hist = (u64 *)(result + p.r_class);
   a.out_spec = (u64 *)(result + p.r_spec);
   a.spec_export_cap = p.spec_export_cap;
+  a.br_sorted = (p.br_passes & 1) ? a.br_b : a.br_a;
+  a.zero_base = scratch + p.o_acc;
+  a.zero_bytes = p.zero_bytes;
 }
 
-hipError_t enqueue_trace(const TraceArgs &a, const TracePlan &p, char *scratch,
-                         hipStream_t s, StageMarks *pm) {
-  hipError_t e = aiwc_kernels::launch_zero(scratch, p.zero_bytes, s);
+// Fold one trace into the launch shapes of a batch.
+void add_dims(const aiwc_trace *t, const TracePlan &p, const TraceArgs &a, BatchDims &d) {
+  const aiwc_trace_desc &D = t->d;
+  d.max_ops_tasks = std::max<u64>(d.max_ops_tasks, p.ops_tasks);
+  d.max_zero16 = std::max<u64>(d.max_zero16, p.zero_bytes / 16);
+  d.max_ids = std::max<u32>(d.max_ids, D.n_opcode_ids);
+  d.ops_lds = std::max<u64>(d.ops_lds, aiwc_kernels::ops_lds_bytes(D.n_opcode_ids));
+  if (D.n_mem) {
+    d.any_mem = true;
+    d.max_hist_blocks = std::max<u64>(d.max_hist_blocks, p.n_hist_blocks);
+    d.max_parts = std::max<u64>(d.max_parts, 1ull << p.pbits);
+    if ((uintptr_t)a.addr % 16 || (uintptr_t)a.mem_kind % 4) d.vec = false;
+  }
+  if (D.n_branch) {
+    d.any_branch = true;
+    d.max_tiles = std::max<u64>(d.max_tiles, p.br_tiles);
+    d.max_passes = std::max<u32>(d.max_passes, p.br_passes);
+    d.max_br_blocks = std::max<u64>(d.max_br_blocks, p.br_blocks);
+    d.max_scan_blocks = std::max<u64>(d.max_scan_blocks,
+                                      aiwc_kernels::scan_blocks_for(256 * p.br_tiles));
+  }
+}
+
+hipError_t enqueue_stages(const TraceArgs &a, const BatchDims &d, hipStream_t s,
+                          StageMarks *pm) {
+  hipError_t e = aiwc_kernels::launch_zero(a, d, s);
   AIWC_MARK(pm, "k_zero", s);
-  if (e == hipSuccess) e = aiwc_kernels::launch_ops(a, s, pm);
-  if (e == hipSuccess) e = aiwc_kernels::launch_mem(a, s, pm);
-  if (e == hipSuccess) e = aiwc_kernels::launch_branch(a, s, pm);
-  if (e == hipSuccess) e = aiwc_kernels::launch_finalize(a, s, pm);
+  if (e == hipSuccess) e = aiwc_kernels::launch_ops(a, d, s, pm);
+  if (e == hipSuccess) e = aiwc_kernels::launch_mem(a, d, s, pm);
+  if (e == hipSuccess) e = aiwc_kernels::launch_branch(a, d, s, pm);
+  if (e == hipSuccess) e = aiwc_kernels::launch_finalize(a, d, s, pm);
   return e;
 }
 
@@ -378,19 +408,23 @@ extern "C" aiwc_status aiwc_trace_destroy(aiwc_trace *t) {
 
 // ------------------------------------------------------------ characterize
 aiwc_status new_metrics(aiwc_ctx *ctx, const aiwc_trace *t, const TracePlan &p,
-                        aiwc_metrics **out) {
+                        aiwc_metrics **out, SharedBuf *shared, void *buf) {
   aiwc_metrics *m = new aiwc_metrics();
   m->ctx = ctx;
   m->plan = p;
   m->n_classes = t->n_classes;
-  if (hipMalloc(&m->buf, p.result_bytes) != hipSuccess) {
+  if (shared) {
+    m->shared = shared;
+    m->buf = buf;
+    shared->refs += 1;
+  } else if (hipMalloc(&m->buf, p.result_bytes) != hipSuccess) {
     hipGetLastError();
     delete m;
     ctx_error(ctx, "out of device memory for a result buffer");
     return AIWC_ERR_OUT_OF_MEMORY;
   }
   if (hipEventCreateWithFlags(&m->done, hipEventDisableTiming) != hipSuccess) {
-    hipFree(m->buf);
+    if (!shared) hipFree(m->buf); else shared->refs -= 1;
     delete m;
     ctx_error(ctx, "hipEventCreate failed");
     return AIWC_ERR_HIP;
@@ -413,7 +447,9 @@ aiwc_status characterize_planned(aiwc_ctx *ctx, const aiwc_trace *t, u32 pbits,
   fill_args(t, p, ctx->arena, (char *)m->buf, a);
   StageMarks *pm = nullptr;
   if (ctx->prof.on) { ctx->prof.begin(s); pm = &ctx->prof; }
-  hipError_t e = enqueue_trace(a, p, ctx->arena, s, pm);
+  BatchDims dims;
+  add_dims(t, p, a, dims);
+  hipError_t e = enqueue_stages(a, dims, s, pm);
   if (e != hipSuccess) {
     ctx_error(ctx, "kernel launch failed: %s", hipGetErrorString(e));
     aiwc_metrics_destroy(m);
@@ -513,7 +549,14 @@ extern "C" aiwc_status aiwc_metrics_spectrum(aiwc_metrics *m, int space, uint64_
 extern "C" aiwc_status aiwc_metrics_destroy(aiwc_metrics *m) {
   if (!m) return AIWC_OK;
   if (m->done) { hipEventSynchronize(m->done); hipEventDestroy(m->done); }
-  if (m->buf) hipFree(m->buf);
+  if (m->shared) {
+    if (--m->shared->refs == 0) {
+      hipFree(m->shared->p);
+      delete m->shared;
+    }
+  } else if (m->buf) {
+    hipFree(m->buf);
+  }
   delete m;
   return AIWC_OK;
 }

@@ -6,6 +6,16 @@
 
 #include "common.h"
 
+// Launch-shape knobs the autotuner searches (defaults = built-in shapes).
+struct Tune {
+  int ops_shift = 0;        // ops task size = default * 2^ops_shift
+  u32 hist_blocks = 256;    // max blocks of the partition histogram / scatter
+  int part_shift = 0;       // partitions = sized count * 2^part_shift
+  bool operator==(const Tune &o) const {
+    return ops_shift == o.ops_shift && hist_blocks == o.hist_blocks && part_shift == o.part_shift;
+  }
+};
+
 struct TracePlan {
   u32 pbits = 4;
   u32 n_hist_blocks = 1;
@@ -54,6 +64,8 @@ struct aiwc_ctx {
   BatchState *batch = nullptr;
   aiwc_batch_stats last_stats{};
   Profiler prof;
+  std::vector<std::pair<std::string, Tune>> tune_cache;  // class key -> best shape
+  bool tune_loaded = false;
 };
 
 struct aiwc_trace {
@@ -64,25 +76,33 @@ struct aiwc_trace {
   u32 *dev_info = nullptr;
 };
 
+// Device block shared by the metrics handles of one batch call.
+struct SharedBuf {
+  void *p = nullptr;
+  size_t refs = 0;
+};
+
 struct aiwc_metrics {
   aiwc_ctx *ctx = nullptr;
   TracePlan plan;
   u32 n_classes = 0;
   void *buf = nullptr;
+  SharedBuf *shared = nullptr;   // set when buf points into a batch block
   hipEvent_t done = nullptr;
   u32 spec_pairs[2] = {0, 0};
 };
 
 void ctx_error(aiwc_ctx *ctx, const char *fmt, ...);
-void plan_trace(const aiwc_trace *t, u32 pbits, TracePlan &p);
+void plan_trace(const aiwc_trace *t, u32 pbits, TracePlan &p, const Tune *tune = nullptr);
 u32 bound_pbits(u64 n_mem);
 void fill_args(const aiwc_trace *t, const TracePlan &p, char *scratch, char *result,
                TraceArgs &a);
-hipError_t enqueue_trace(const TraceArgs &a, const TracePlan &p, char *scratch, hipStream_t s,
-                         StageMarks *pm);
+hipError_t enqueue_stages(const TraceArgs &a, const BatchDims &d, hipStream_t s,
+                          StageMarks *pm);
+void add_dims(const aiwc_trace *t, const TracePlan &p, const TraceArgs &a, BatchDims &d);
 aiwc_status ensure_arena(aiwc_ctx *ctx, u64 bytes);
 aiwc_status new_metrics(aiwc_ctx *ctx, const aiwc_trace *t, const TracePlan &p,
-                        aiwc_metrics **out);
+                        aiwc_metrics **out, SharedBuf *shared = nullptr, void *buf = nullptr);
 aiwc_status characterize_planned(aiwc_ctx *ctx, const aiwc_trace *t, u32 pbits,
                                  hipStream_t s, aiwc_metrics **out);
 aiwc_status validate_on_device(aiwc_ctx *ctx, const aiwc_trace *t);

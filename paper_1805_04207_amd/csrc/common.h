@@ -47,6 +47,7 @@ struct TraceArgs {
   const u32 *op_info;        // per id: kind | width << 8 | class << 16
   u64 n_events, n_wi, n_mem, n_branch;
   u32 n_ids, n_classes, n_sites, m;
+  u32 wg_size, pad1;
   // planning
   u32 pbits;                 // memory partitions P = 2^pbits
   u32 n_hist_blocks;         // blocks of the partition histogram / scatter
@@ -78,7 +79,20 @@ struct TraceArgs {
   u64 *out_spec;             // [2][SPEC_DENSE] then sparse export
   u32 spec_export_cap;       // sparse pairs exported per space
   u32 pad0;
+  // batch bookkeeping
+  u32 *br_sorted;            // br_a or br_b: where the last radix pass leaves data
+  void *zero_base;           // start and size of this trace's zero region
+  u64 zero_bytes;
 };
+
+// A kernel either serves one trace (arguments by value) or a whole batch
+// (grid.y = trace index into a device array of TraceArgs).
+template <bool BATCH>
+__device__ __forceinline__ const TraceArgs &trace_args(const TraceArgs &A0,
+                                                       const TraceArgs *batch) {
+  if constexpr (BATCH) return batch[blockIdx.y];
+  else return A0;
+}
 
 // ------------------------------------------------------------ device math
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
@@ -159,12 +173,27 @@ struct StageMarks {
   virtual ~StageMarks() {}
 };
 
+// Launch shapes of a batch: the maxima over its traces (grid.x) and the
+// trace count (grid.y).  For one trace, batch == nullptr and n == 1.
+struct BatchDims {
+  u32 n = 1;
+  const TraceArgs *batch = nullptr;   // device array [n], or nullptr
+  u64 max_ops_tasks = 0, max_hist_blocks = 0, max_parts = 0, max_tiles = 0;
+  u64 max_br_blocks = 0, max_scan_blocks = 0, max_zero16 = 0;
+  u32 max_ids = 0, max_passes = 0;
+  u64 ops_lds = 0;                    // dynamic LDS of the ops kernel (max over traces)
+  bool any_mem = false, any_branch = false;
+  bool vec = true;                    // every address / kind array 16 / 4 B aligned
+};
+
 namespace aiwc_kernels {
-hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);
-hipError_t launch_ops(const TraceArgs &a, hipStream_t s, StageMarks *pm);
-hipError_t launch_mem(const TraceArgs &a, hipStream_t s, StageMarks *pm);
-hipError_t launch_branch(const TraceArgs &a, hipStream_t s, StageMarks *pm);
-hipError_t launch_finalize(const TraceArgs &a, hipStream_t s, StageMarks *pm);
+hipError_t launch_zero(const TraceArgs &a, const BatchDims &d, hipStream_t s);
+hipError_t launch_ops(const TraceArgs &a, const BatchDims &d, hipStream_t s, StageMarks *pm);
+hipError_t launch_mem(const TraceArgs &a, const BatchDims &d, hipStream_t s, StageMarks *pm);
+hipError_t launch_branch(const TraceArgs &a, const BatchDims &d, hipStream_t s, StageMarks *pm);
+hipError_t launch_finalize(const TraceArgs &a, const BatchDims &d, hipStream_t s, StageMarks *pm);
+u64 scan_blocks_for(u64 n);
+size_t ops_lds_bytes(u32 n_ids);
 }  // namespace aiwc_kernels
 
 #define AIWC_MARK(pm, name, s) \

@@ -36,7 +36,10 @@ constexpr u32 WT_CAP = 6656;
 constexpr u64 EMPTY = ~0ull;
 
 // ------------------------------------------------------------------ pack
-__global__ void k_br_pack(TraceArgs A, u32 *out) {
+template <bool BATCH>
+__global__ void k_br_pack(TraceArgs A0, const TraceArgs *batch) {
+  const TraceArgs &A = trace_args<BATCH>(A0, batch);
+  u32 *out = A.br_a;
   u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x;
   const u64 stride = (u64)gridDim.x * blockDim.x;
   u32 bad = 0;
@@ -51,9 +54,16 @@ __global__ void k_br_pack(TraceArgs A, u32 *out) {
 }
 
 // -------------------------------------------------------------- radix sort
-__global__ void __launch_bounds__(BR_BLOCK) k_br_upsweep(const u32 *in, u64 n, u32 shift,
-                                                        u32 *cnt, u64 n_tiles) {
+template <bool BATCH>
+__global__ void __launch_bounds__(BR_BLOCK) k_br_upsweep(TraceArgs A0, const TraceArgs *batch,
+                                                        u32 pass) {
   __shared__ u32 h[256];
+  const TraceArgs &A = trace_args<BATCH>(A0, batch);
+  if (pass >= A.br_passes || blockIdx.x >= A.br_tiles) return;
+  const u32 *in = (pass & 1) ? A.br_b : A.br_a;
+  const u64 n = A.n_branch, n_tiles = A.br_tiles;
+  const u32 shift = 1u + 8u * pass;
+  u32 *cnt = A.br_cnt;
   h[threadIdx.x] = 0;
   __syncthreads();
   const u64 t = blockIdx.x;
@@ -66,12 +76,19 @@ __global__ void __launch_bounds__(BR_BLOCK) k_br_upsweep(const u32 *in, u64 n, u
   cnt[(u64)threadIdx.x * n_tiles + t] = h[threadIdx.x];
 }
 
-__global__ void __launch_bounds__(BR_BLOCK) k_br_downsweep(const u32 *in, u32 *out, u64 n,
-                                                          u32 shift, const u32 *ofs,
-                                                          u64 n_tiles) {
+template <bool BATCH>
+__global__ void __launch_bounds__(BR_BLOCK) k_br_downsweep(TraceArgs A0, const TraceArgs *batch,
+                                                          u32 pass) {
   __shared__ u32 gofs[256];
   __shared__ u32 running[256];
   __shared__ u32 wcnt[BR_BLOCK / AIWC_WAVE][256];
+  const TraceArgs &A = trace_args<BATCH>(A0, batch);
+  if (pass >= A.br_passes || blockIdx.x >= A.br_tiles) return;
+  const u32 *in = (pass & 1) ? A.br_b : A.br_a;
+  u32 *out = (pass & 1) ? A.br_a : A.br_b;
+  const u64 n = A.n_branch, n_tiles = A.br_tiles;
+  const u32 shift = 1u + 8u * pass;
+  const u32 *ofs = A.br_cnt;
   const int tid = threadIdx.x, lane = lane_id(), wave = tid / AIWC_WAVE;
   const u64 t = blockIdx.x;
   gofs[tid] = ofs[(u64)tid * n_tiles + t];
@@ -133,8 +150,15 @@ __device__ u32 block_exclusive_scan(u32 v, u32 *wsum, u32 &total) {
   return before + x - v;
 }
 
-__global__ void __launch_bounds__(SCAN_BLOCK) k_scan_reduce(const u32 *in, u64 n, u32 *sums) {
+template <bool BATCH>
+__global__ void __launch_bounds__(SCAN_BLOCK) k_scan_reduce(TraceArgs A0, const TraceArgs *batch,
+                                                           u32 pass) {
   __shared__ u32 wsum[16];
+  const TraceArgs &A = trace_args<BATCH>(A0, batch);
+  const u64 n = 256ull * A.br_tiles;
+  if (pass >= A.br_passes || blockIdx.x >= (n + SCAN_TILE - 1) / SCAN_TILE) return;
+  const u32 *in = A.br_cnt;
+  u32 *sums = A.scan_tmp;
   const u64 base = (u64)blockIdx.x * SCAN_TILE;
   u32 s = 0;
   for (int j = 0; j < SCAN_PER; ++j) {
@@ -146,9 +170,15 @@ __global__ void __launch_bounds__(SCAN_BLOCK) k_scan_reduce(const u32 *in, u64 n
   if (threadIdx.x == 0) sums[blockIdx.x] = tot;
 }
 
-__global__ void __launch_bounds__(SCAN_BLOCK) k_scan_sums(u32 *sums, u64 nb) {
+template <bool BATCH>
+__global__ void __launch_bounds__(SCAN_BLOCK) k_scan_sums(TraceArgs A0, const TraceArgs *batch,
+                                                         u32 pass) {
   __shared__ u32 wsum[16];
   __shared__ u32 carry;
+  const TraceArgs &A = trace_args<BATCH>(A0, batch);
+  if (pass >= A.br_passes) return;
+  u32 *sums = A.scan_tmp;
+  const u64 nb = (256ull * A.br_tiles + SCAN_TILE - 1) / SCAN_TILE;
   if (threadIdx.x == 0) carry = 0;
   __syncthreads();
   for (u64 b = 0; b < nb; b += SCAN_BLOCK) {
@@ -164,8 +194,15 @@ __global__ void __launch_bounds__(SCAN_BLOCK) k_scan_sums(u32 *sums, u64 nb) {
   }
 }
 
-__global__ void __launch_bounds__(SCAN_BLOCK) k_scan_apply(u32 *data, u64 n, const u32 *sums) {
+template <bool BATCH>
+__global__ void __launch_bounds__(SCAN_BLOCK) k_scan_apply(TraceArgs A0, const TraceArgs *batch,
+                                                          u32 pass) {
   __shared__ u32 wsum[16];
+  const TraceArgs &A = trace_args<BATCH>(A0, batch);
+  const u64 n = 256ull * A.br_tiles;
+  if (pass >= A.br_passes || blockIdx.x >= (n + SCAN_TILE - 1) / SCAN_TILE) return;
+  u32 *data = A.br_cnt;
+  const u32 *sums = A.scan_tmp;
   const u64 base = (u64)blockIdx.x * SCAN_TILE;
   // each thread owns SCAN_PER consecutive elements
   u32 v[SCAN_PER];
@@ -186,7 +223,10 @@ __global__ void __launch_bounds__(SCAN_BLOCK) k_scan_apply(u32 *data, u64 n, con
 }
 
 // ------------------------------------------------------------- segments
-__global__ void k_br_segments(TraceArgs A, const u32 *sorted) {
+template <bool BATCH>
+__global__ void k_br_segments(TraceArgs A0, const TraceArgs *batch) {
+  const TraceArgs &A = trace_args<BATCH>(A0, batch);
+  const u32 *sorted = A.br_sorted;
   u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x;
   const u64 stride = (u64)gridDim.x * blockDim.x;
   const u64 n = A.n_branch;
@@ -249,8 +289,12 @@ __device__ __forceinline__ bool win_insert(WinShared &S, u64 key, u32 y) {
   }
 }
 
-__global__ void __launch_bounds__(WIN_BLOCK) k_br_windows(TraceArgs A, const u32 *sorted) {
+template <bool BATCH>
+__global__ void __launch_bounds__(WIN_BLOCK) k_br_windows(TraceArgs A0, const TraceArgs *batch) {
   __shared__ WinShared S;
+  const TraceArgs &A = trace_args<BATCH>(A0, batch);
+  if (A.n_branch == 0) return;
+  const u32 *sorted = A.br_sorted;
   const int tid = threadIdx.x, lane = lane_id(), wave = tid / AIWC_WAVE;
   const u32 m = A.m;
   const u64 hmask = (m >= 64) ? ~0ull : ((1ull << m) - 1ull);
@@ -348,15 +392,6 @@ __global__ void __launch_bounds__(WIN_BLOCK) k_br_windows(TraceArgs A, const u32
   }
 }
 
-hipError_t scan_u32(u32 *data, u64 n, u32 *tmp, hipStream_t s) {
-  const u64 nb = (n + SCAN_TILE - 1) / SCAN_TILE;
-  if (nb == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(SCAN_BLOCK), 0, s, data, n, tmp);
-  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(SCAN_BLOCK), 0, s, tmp, nb);
-  hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(SCAN_BLOCK), 0, s, data, n, tmp);
-  return hipGetLastError();
-}
-
 }  // namespace
 
 namespace aiwc_kernels {
@@ -365,29 +400,37 @@ u64 scan_tmp_elems(u64 n) { return (n + SCAN_TILE - 1) / SCAN_TILE + 1; }
 u64 br_tiles_for(u64 n) { return (n + BR_TILE - 1) / BR_TILE; }
 u64 br_blocks_for(u64 n) { return (n + WIN_T - 1) / WIN_T; }
 
-hipError_t launch_branch(const TraceArgs &a, hipStream_t s, StageMarks *pm) {
-  if (a.n_branch == 0) return hipSuccess;
-  unsigned g = (unsigned)((a.n_branch + 255) / 256);
-  if (g > 8192) g = 8192;
-  hipLaunchKernelGGL(k_br_pack, dim3(g), dim3(256), 0, s, a, a.br_a);
+u64 scan_blocks_for(u64 n) { return (n + SCAN_TILE - 1) / SCAN_TILE; }
+
+template <bool B>
+static void branch_launches(const TraceArgs &a, const BatchDims &d, hipStream_t s,
+                            StageMarks *pm) {
+  const TraceArgs *b = d.batch;
+  u64 gx = (d.max_tiles * BR_TILE + 255) / 256;
+  if (gx > 8192) gx = 8192;
+  if (gx == 0) gx = 1;
+  hipLaunchKernelGGL(k_br_pack<B>, dim3((unsigned)gx, d.n), dim3(256), 0, s, a, b);
   AIWC_MARK(pm, "k_br_pack", s);
-  u32 *cur = a.br_a, *nxt = a.br_b;
-  for (u32 p = 0; p < a.br_passes; ++p) {
-    const u32 shift = 1u + 8u * p;
-    hipLaunchKernelGGL(k_br_upsweep, dim3((unsigned)a.br_tiles), dim3(BR_BLOCK), 0, s, cur,
-                       a.n_branch, shift, a.br_cnt, a.br_tiles);
-    hipError_t e = scan_u32(a.br_cnt, 256ull * a.br_tiles, a.scan_tmp, s);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_br_downsweep, dim3((unsigned)a.br_tiles), dim3(BR_BLOCK), 0, s, cur, nxt,
-                       a.n_branch, shift, a.br_cnt, a.br_tiles);
-    u32 *t = cur; cur = nxt; nxt = t;
+  const dim3 gt((unsigned)d.max_tiles, d.n), gs((unsigned)d.max_scan_blocks, d.n), g1(1, d.n);
+  for (u32 p = 0; p < d.max_passes; ++p) {
+    hipLaunchKernelGGL(k_br_upsweep<B>, gt, dim3(BR_BLOCK), 0, s, a, b, p);
+    hipLaunchKernelGGL(k_scan_reduce<B>, gs, dim3(SCAN_BLOCK), 0, s, a, b, p);
+    hipLaunchKernelGGL(k_scan_sums<B>, g1, dim3(SCAN_BLOCK), 0, s, a, b, p);
+    hipLaunchKernelGGL(k_scan_apply<B>, gs, dim3(SCAN_BLOCK), 0, s, a, b, p);
+    hipLaunchKernelGGL(k_br_downsweep<B>, gt, dim3(BR_BLOCK), 0, s, a, b, p);
   }
   AIWC_MARK(pm, "k_br_sort", s);
-  hipLaunchKernelGGL(k_br_segments, dim3(g), dim3(256), 0, s, a, cur);
+  hipLaunchKernelGGL(k_br_segments<B>, dim3((unsigned)gx, d.n), dim3(256), 0, s, a, b);
   AIWC_MARK(pm, "k_br_segments", s);
-  u64 nb = a.br_blocks < 256 ? a.br_blocks : 256;
-  hipLaunchKernelGGL(k_br_windows, dim3((unsigned)nb), dim3(WIN_BLOCK), 0, s, a, cur);
+  u64 nb = d.max_br_blocks < 256 ? d.max_br_blocks : 256;
+  hipLaunchKernelGGL(k_br_windows<B>, dim3((unsigned)nb, d.n), dim3(WIN_BLOCK), 0, s, a, b);
   AIWC_MARK(pm, "k_br_windows", s);
+}
+
+hipError_t launch_branch(const TraceArgs &a, const BatchDims &d, hipStream_t s, StageMarks *pm) {
+  if (!d.any_branch) return hipSuccess;
+  if (d.batch) branch_launches<true>(a, d, s, pm);
+  else branch_launches<false>(a, d, s, pm);
   return hipGetLastError();
 }
 

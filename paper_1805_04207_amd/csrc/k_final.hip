@@ -143,8 +143,10 @@ __device__ double median_of(const u64 *hist, const u64 *large, u64 n_large, u64 
   return ((double)a + (double)b) * 0.5;
 }
 
-__global__ void __launch_bounds__(FB) k_finalize(TraceArgs A) {
+template <bool BATCH>
+__global__ void __launch_bounds__(FB) k_finalize(TraceArgs A0, const TraceArgs *batch) {
   __shared__ FinShared S;
+  const TraceArgs &A = trace_args<BATCH>(A0, batch);
   const int tid = threadIdx.x;
   DevAccum *acc = A.acc;
   aiwc_metrics_host *o = A.out;
@@ -313,8 +315,9 @@ __global__ void __launch_bounds__(FB) k_finalize(TraceArgs A) {
 
 namespace aiwc_kernels {
 
-hipError_t launch_finalize(const TraceArgs &a, hipStream_t s, StageMarks *pm) {
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FB), 0, s, a);
+hipError_t launch_finalize(const TraceArgs &a, const BatchDims &d, hipStream_t s, StageMarks *pm) {
+  if (d.batch) hipLaunchKernelGGL(k_finalize<true>, dim3(1, d.n), dim3(FB), 0, s, a, d.batch);
+  else hipLaunchKernelGGL(k_finalize<false>, dim3(1), dim3(FB), 0, s, a, nullptr);
   AIWC_MARK(pm, "k_finalize", s);
   return hipGetLastError();
 }

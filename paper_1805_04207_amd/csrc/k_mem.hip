@@ -51,10 +51,12 @@ __device__ __forceinline__ u64 make_record(u64 a, uint8_t kind, u32 pbits, u32 &
 // -------------------------------------------------------------- histogram
 constexpr u32 MAX_PARTS = 32768;
 
-template <bool VEC>
-__global__ void __launch_bounds__(MEM_BLOCK) k_mem_hist(TraceArgs A) {
+template <bool VEC, bool BATCH>
+__global__ void __launch_bounds__(MEM_BLOCK) k_mem_hist(TraceArgs A0, const TraceArgs *batch) {
   __shared__ u32 h[MAX_PARTS];
   __shared__ u64 sp_cnt[4];  // reads g, writes g, reads l, writes l
+  const TraceArgs &A = trace_args<BATCH>(A0, batch);
+  if (A.n_mem == 0 || blockIdx.x >= A.n_hist_blocks) return;
   const u32 P = 1u << A.pbits;
   for (u32 i = threadIdx.x; i < P; i += MEM_BLOCK) h[i] = 0;
   if (threadIdx.x < 4) sp_cnt[threadIdx.x] = 0;
@@ -107,10 +109,12 @@ __global__ void __launch_bounds__(MEM_BLOCK) k_mem_hist(TraceArgs A) {
 
 // Per partition: exclusive prefix over the histogram blocks (in place);
 // the partition total goes to part_off[b].
-__global__ void k_mem_colscan(TraceArgs A) {
+template <bool BATCH>
+__global__ void k_mem_colscan(TraceArgs A0, const TraceArgs *batch) {
+  const TraceArgs &A = trace_args<BATCH>(A0, batch);
   const u32 P = 1u << A.pbits;
   const u32 b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= P) return;
+  if (A.n_mem == 0 || b >= P) return;
   u32 s = 0;
   for (u32 w = 0; w < A.n_hist_blocks; ++w) {
     u32 *p = A.part_hist + (u64)w * P + b;
@@ -122,9 +126,12 @@ __global__ void k_mem_colscan(TraceArgs A) {
 }
 
 // Exclusive scan of the partition totals (one block); part_off[P] = n_mem.
-__global__ void __launch_bounds__(1024) k_mem_binscan(TraceArgs A) {
+template <bool BATCH>
+__global__ void __launch_bounds__(1024) k_mem_binscan(TraceArgs A0, const TraceArgs *batch) {
   __shared__ u32 wsum[16];
   __shared__ u32 carry;
+  const TraceArgs &A = trace_args<BATCH>(A0, batch);
+  if (A.n_mem == 0) return;
   const u32 P = 1u << A.pbits;
   if (threadIdx.x == 0) carry = 0;
   __syncthreads();
@@ -151,9 +158,11 @@ __global__ void __launch_bounds__(1024) k_mem_binscan(TraceArgs A) {
 }
 
 // -------------------------------------------------------------- scatter
-template <bool VEC>
-__global__ void __launch_bounds__(MEM_BLOCK) k_mem_scatter(TraceArgs A) {
+template <bool VEC, bool BATCH>
+__global__ void __launch_bounds__(MEM_BLOCK) k_mem_scatter(TraceArgs A0, const TraceArgs *batch) {
   __shared__ u32 cur[MAX_PARTS];
+  const TraceArgs &A = trace_args<BATCH>(A0, batch);
+  if (A.n_mem == 0 || blockIdx.x >= A.n_hist_blocks) return;
   const u32 P = 1u << A.pbits;
   const u32 *row = A.part_hist + (u64)blockIdx.x * P;
   for (u32 i = threadIdx.x; i < P; i += MEM_BLOCK) cur[i] = A.part_off[i] + row[i];
@@ -211,7 +220,7 @@ __device__ __forceinline__ void term_fx(u64 c, u64 N, u64 &lo, u64 &hi) {
   to_fx64(d, lo, hi);
 }
 
-__device__ void global_spec_add(TraceArgs &A, u32 s, u64 f, u64 m) {
+__device__ void global_spec_add(const TraceArgs &A, u32 s, u64 f, u64 m) {
   u64 *F = A.sp_f + (u64)s * A.sp_cap;
   u64 *M = A.sp_m + (u64)s * A.sp_cap;
   u32 slot = hash_slot(f, A.sp_cap);
@@ -222,7 +231,7 @@ __device__ void global_spec_add(TraceArgs &A, u32 s, u64 f, u64 m) {
   }
 }
 
-__device__ __forceinline__ void spec_cache_add(BucketShared &S, TraceArgs &A, u32 s, u64 f,
+__device__ __forceinline__ void spec_cache_add(BucketShared &S, const TraceArgs &A, u32 s, u64 f,
                                                u64 m) {
   u32 slot = (u32)((f * 0x9E3779B97F4A7C15ull) >> 56);  // 0..255
   for (u32 probe = 0; probe < 16; ++probe) {
@@ -262,8 +271,11 @@ __device__ __forceinline__ bool tbl_insert(BucketShared &S, u64 key, u64 flag, u
   }
 }
 
-__global__ void __launch_bounds__(MEM_BLOCK) k_mem_bucket(TraceArgs A) {
+template <bool BATCH>
+__global__ void __launch_bounds__(MEM_BLOCK) k_mem_bucket(TraceArgs A0, const TraceArgs *batch) {
   __shared__ BucketShared S;
+  const TraceArgs &A = trace_args<BATCH>(A0, batch);
+  if (A.n_mem == 0) return;
   const int tid = threadIdx.x, lane = lane_id();
   const u32 P = 1u << A.pbits;
   const u64 N[2] = {A.acc->sp_reads[0] + A.acc->sp_writes[0],
@@ -435,21 +447,37 @@ namespace aiwc_kernels {
 
 size_t bucket_lds_bytes() { return sizeof(BucketShared); }
 
-hipError_t launch_mem(const TraceArgs &a, hipStream_t s, StageMarks *pm) {
-  if (a.n_mem == 0) return hipSuccess;
-  const u32 P = 1u << a.pbits;
-  const bool vec = ((uintptr_t)a.addr % 16 == 0) && ((uintptr_t)a.mem_kind % 4 == 0);
-  if (vec) hipLaunchKernelGGL(k_mem_hist<true>, dim3(a.n_hist_blocks), dim3(MEM_BLOCK), 0, s, a);
-  else hipLaunchKernelGGL(k_mem_hist<false>, dim3(a.n_hist_blocks), dim3(MEM_BLOCK), 0, s, a);
+hipError_t launch_mem(const TraceArgs &a, const BatchDims &d, hipStream_t s, StageMarks *pm) {
+  if (!d.any_mem) return hipSuccess;
+  const dim3 gh((unsigned)d.max_hist_blocks, d.n), gc((unsigned)((d.max_parts + 255) / 256), d.n);
+  const dim3 g1(1, d.n), gb((unsigned)(d.max_parts < 256 ? d.max_parts : 256), d.n);
+  const TraceArgs *b = d.batch;
+  if (b) {
+    if (d.vec) hipLaunchKernelGGL((k_mem_hist<true, true>), gh, dim3(MEM_BLOCK), 0, s, a, b);
+    else hipLaunchKernelGGL((k_mem_hist<false, true>), gh, dim3(MEM_BLOCK), 0, s, a, b);
+  } else {
+    if (d.vec) hipLaunchKernelGGL((k_mem_hist<true, false>), gh, dim3(MEM_BLOCK), 0, s, a, b);
+    else hipLaunchKernelGGL((k_mem_hist<false, false>), gh, dim3(MEM_BLOCK), 0, s, a, b);
+  }
   AIWC_MARK(pm, "k_mem_hist", s);
-  hipLaunchKernelGGL(k_mem_colscan, dim3((P + 255) / 256), dim3(256), 0, s, a);
-  hipLaunchKernelGGL(k_mem_binscan, dim3(1), dim3(1024), 0, s, a);
+  if (b) {
+    hipLaunchKernelGGL(k_mem_colscan<true>, gc, dim3(256), 0, s, a, b);
+    hipLaunchKernelGGL(k_mem_binscan<true>, g1, dim3(1024), 0, s, a, b);
+  } else {
+    hipLaunchKernelGGL(k_mem_colscan<false>, gc, dim3(256), 0, s, a, b);
+    hipLaunchKernelGGL(k_mem_binscan<false>, g1, dim3(1024), 0, s, a, b);
+  }
   AIWC_MARK(pm, "k_mem_scan", s);
-  if (vec) hipLaunchKernelGGL(k_mem_scatter<true>, dim3(a.n_hist_blocks), dim3(MEM_BLOCK), 0, s, a);
-  else hipLaunchKernelGGL(k_mem_scatter<false>, dim3(a.n_hist_blocks), dim3(MEM_BLOCK), 0, s, a);
+  if (b) {
+    if (d.vec) hipLaunchKernelGGL((k_mem_scatter<true, true>), gh, dim3(MEM_BLOCK), 0, s, a, b);
+    else hipLaunchKernelGGL((k_mem_scatter<false, true>), gh, dim3(MEM_BLOCK), 0, s, a, b);
+  } else {
+    if (d.vec) hipLaunchKernelGGL((k_mem_scatter<true, false>), gh, dim3(MEM_BLOCK), 0, s, a, b);
+    else hipLaunchKernelGGL((k_mem_scatter<false, false>), gh, dim3(MEM_BLOCK), 0, s, a, b);
+  }
   AIWC_MARK(pm, "k_mem_scatter", s);
-  unsigned nb = P < 256 ? P : 256;
-  hipLaunchKernelGGL(k_mem_bucket, dim3(nb), dim3(MEM_BLOCK), 0, s, a);
+  if (b) hipLaunchKernelGGL(k_mem_bucket<true>, gb, dim3(MEM_BLOCK), 0, s, a, b);
+  else hipLaunchKernelGGL(k_mem_bucket<false>, gb, dim3(MEM_BLOCK), 0, s, a, b);
   AIWC_MARK(pm, "k_mem_bucket", s);
   return hipGetLastError();
 }

@@ -54,10 +54,18 @@ __device__ __forceinline__ void record_value(u64 v, u32 *lds_hist, u64 *g_hist,
   }
 }
 
-template <bool LDS_IDS>
-__global__ void __launch_bounds__(OPS_BLOCK) k_ops(TraceArgs A, u32 ncopies) {
+__host__ __device__ __forceinline__ u32 ops_copies(u32 nid) {
+  u32 nc = 1;
+  while (nc < 16 && (nc * 2) * nid * 4 <= 32768u) nc *= 2;
+  return nc;
+}
+
+template <bool LDS_IDS, bool BATCH>
+__global__ void __launch_bounds__(OPS_BLOCK) k_ops(TraceArgs A0, const TraceArgs *batch) {
   extern __shared__ u32 lds[];
+  const TraceArgs &A = trace_args<BATCH>(A0, batch);
   const u32 nid = A.n_ids;
+  const u32 ncopies = LDS_IDS ? ops_copies(nid) : 1u;
   WaveStats *ws = (WaveStats *)lds;                   // [OPS_WAVES]
   u32 *itbh = lds + OPS_WAVES * sizeof(WaveStats) / 4; // [LDS_VALS]
   u32 *ipth = itbh + LDS_VALS;                        // [LDS_VALS]
@@ -214,7 +222,11 @@ __global__ void __launch_bounds__(OPS_BLOCK) k_ops(TraceArgs A, u32 ncopies) {
   }
 }
 
-__global__ void k_zero(uint4 *p, size_t n16) {
+template <bool BATCH>
+__global__ void k_zero(TraceArgs A0, const TraceArgs *batch) {
+  const TraceArgs &A = trace_args<BATCH>(A0, batch);
+  uint4 *p = (uint4 *)A.zero_base;
+  const size_t n16 = A.zero_bytes / 16;
   size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   size_t stride = (size_t)gridDim.x * blockDim.x;
   for (; i < n16; i += stride) p[i] = make_uint4(0, 0, 0, 0);
@@ -224,27 +236,38 @@ __global__ void k_zero(uint4 *p, size_t n16) {
 
 namespace aiwc_kernels {
 
-hipError_t launch_zero(void *p, size_t bytes, hipStream_t s) {
-  size_t n16 = bytes / 16;
+hipError_t launch_zero(const TraceArgs &a, const BatchDims &d, hipStream_t s) {
+  u64 n16 = d.max_zero16;
   if (n16 == 0) return hipSuccess;
-  unsigned grid = (unsigned)((n16 + 255) / 256);
-  if (grid > 4096) grid = 4096;
-  hipLaunchKernelGGL(k_zero, dim3(grid), dim3(256), 0, s, (uint4 *)p, n16);
+  unsigned gx = (unsigned)((n16 + 255) / 256);
+  if (gx > 2048) gx = 2048;
+  if (d.batch) hipLaunchKernelGGL(k_zero<true>, dim3(gx, d.n), dim3(256), 0, s, a, d.batch);
+  else hipLaunchKernelGGL(k_zero<false>, dim3(gx), dim3(256), 0, s, a, nullptr);
   return hipGetLastError();
 }
 
-hipError_t launch_ops(const TraceArgs &a, hipStream_t s, StageMarks *pm) {
-  if (a.ops_tasks == 0) return hipSuccess;
-  u64 waves = a.ops_tasks < 4096 ? a.ops_tasks : 4096;
-  unsigned grid = (unsigned)((waves + OPS_WAVES - 1) / OPS_WAVES);
-  size_t tail = 2 * LDS_VALS * 4 + OPS_WAVES * sizeof(WaveStats);
-  if (a.n_ids <= 8192) {
-    u32 nc = 1;
-    while (nc < 16 && (size_t)(nc * 2) * a.n_ids * 4 <= 32768) nc *= 2;
-    size_t lds = ((size_t)nc * a.n_ids + a.n_ids) * 4 + tail;
-    hipLaunchKernelGGL(k_ops<true>, dim3(grid), dim3(OPS_BLOCK), lds, s, a, nc);
+size_t ops_lds_bytes(u32 n_ids) {
+  const size_t tail = OPS_WAVES * sizeof(WaveStats) + 2 * LDS_VALS * 4;
+  if (n_ids > 8192) return tail;
+  return tail + 4 * ((size_t)ops_copies(n_ids) * n_ids + n_ids);
+}
+
+hipError_t launch_ops(const TraceArgs &a, const BatchDims &d, hipStream_t s, StageMarks *pm) {
+  if (d.max_ops_tasks == 0) return hipSuccess;
+  u64 waves = d.max_ops_tasks < 4096 ? d.max_ops_tasks : 4096;
+  unsigned gx = (unsigned)((waves + OPS_WAVES - 1) / OPS_WAVES);
+  size_t tail = OPS_WAVES * sizeof(WaveStats) + 2 * LDS_VALS * 4;
+  if (d.max_ids <= 8192) {
+    const size_t lds = d.ops_lds ? d.ops_lds : ops_lds_bytes(d.max_ids);
+    if (d.batch)
+      hipLaunchKernelGGL((k_ops<true, true>), dim3(gx, d.n), dim3(OPS_BLOCK), lds, s, a, d.batch);
+    else
+      hipLaunchKernelGGL((k_ops<true, false>), dim3(gx), dim3(OPS_BLOCK), lds, s, a, nullptr);
   } else {
-    hipLaunchKernelGGL(k_ops<false>, dim3(grid), dim3(OPS_BLOCK), tail, s, a, 1u);
+    if (d.batch)
+      hipLaunchKernelGGL((k_ops<false, true>), dim3(gx, d.n), dim3(OPS_BLOCK), tail, s, a, d.batch);
+    else
+      hipLaunchKernelGGL((k_ops<false, false>), dim3(gx), dim3(OPS_BLOCK), tail, s, a, nullptr);
   }
   AIWC_MARK(pm, "k_ops", s);
   return hipGetLastError();

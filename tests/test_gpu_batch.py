@@ -1,0 +1,88 @@
+"""Batched path: bit-identical to the single-trace path and to the oracle,
+with and without a captured hipGraph, across admission waves and forced
+partition overflow (run with -m gpu)."""
+import numpy as np
+import pytest
+
+import oracle
+import tracegen as tg
+from oracle.compare import compare
+
+pytestmark = pytest.mark.gpu
+
+
+def _traces(n, scale=2e-3, seed=2):
+    import paper_1805_04207_amd as aiwc
+    from gpu_util import ctx
+    specs = tg.config3_specs(seed=seed, n_traces=n, scale=scale)
+    hosts, trs, keep = [], [], []
+    for sp in specs:
+        h = tg.generate_host(sp)
+        dev = aiwc.host_to_device(h, 0)
+        keep.append(dev)
+        hosts.append(h)
+        trs.append(aiwc.device_trace(ctx(), dev, h.table, sp.n_sites, sp.history_len, sp.wg_size))
+    return hosts, trs, keep
+
+
+@pytest.fixture(scope="module")
+def batch12():
+    return _traces(12)
+
+
+def test_batch_equals_single_and_oracle(batch12):
+    from gpu_util import ctx
+    hosts, trs, _ = batch12
+    print("batch sizes", [h.opcode.size for h in hosts], flush=True)
+    c = ctx()
+    got = [m.read() for m in c.characterize_batch(trs)]
+    single = [c.characterize(t).read() for t in trs]
+    for g, s in zip(got, single):
+        assert g == s
+    for h, g in list(zip(hosts, got))[:6]:
+        bad = compare(g, oracle.characterize(h))
+        assert not bad, "\n".join(bad[:10])
+
+
+def test_graph_replays_are_identical(batch12):
+    from gpu_util import ctx
+    hosts, trs, _ = batch12
+    c = ctx()
+    ref = [m.read() for m in c.characterize_batch(trs)]
+    for rep in range(3):
+        got = [m.read() for m in c.characterize_batch(trs, use_graph=True)]
+        assert got == ref, f"replay {rep}"
+        # eager work between replays
+        c.characterize(trs[0]).read()
+
+
+def test_admission_waves_and_forced_redo(batch12):
+    from gpu_util import ctx
+    hosts, trs, _ = batch12
+    c = ctx()
+    ref = [m.read() for m in c.characterize_batch(trs)]
+    got = [m.read() for m in c.characterize_batch(trs, admission_cap_bytes=64 << 20)]
+    assert got == ref
+    assert c.batch_stats()["waves"] >= 2
+    got = [m.read() for m in c.characterize_batch(trs, force_partition_log2=4)]
+    for g, r in zip(got, ref):
+        g = dict(g); r = dict(r)
+        assert g.pop("overflow_redos") >= 0 and g.pop("partitions") == 16 or r["space"][0]["total_accesses"] == 0
+        r.pop("overflow_redos"); r.pop("partitions")
+        assert g == r
+    assert c.batch_stats()["redo_partitions"] > 0
+
+
+def test_autotune_search_keeps_results(batch12, tmp_path, monkeypatch):
+    import paper_1805_04207_amd as aiwc
+    from gpu_util import ctx
+    monkeypatch.setenv("AIWC_TUNE_CACHE", str(tmp_path / "tune.json"))
+    hosts, trs, _ = batch12
+    c = ctx()
+    ref = [m.read() for m in c.characterize_batch(trs)]
+    got = [m.read() for m in c.characterize_batch(trs, autotune=aiwc.AUTOTUNE_SEARCH)]
+    for g, r in zip(got, ref):
+        g = dict(g); r = dict(r)
+        for f in ("overflow_redos", "partitions"):
+            g.pop(f); r.pop(f)
+        assert g == r
