@@ -95,6 +95,7 @@ void plan_trace(const aiwc_trace *t, u32 pbits, TracePlan &p, const Tune *tune) 
   p.o_part_hist = take(4ull * p.n_hist_blocks * P);
   p.o_part_off = take(4ull * (P + 1));
   p.o_part_rec = take(8ull * std::max<u64>(1, d.n_mem));
+  p.o_mem_stage = take(4ull * std::max<u64>(1, d.n_mem));
   p.o_br_a = take(4ull * std::max<u64>(1, d.n_branch));
   p.o_br_b = take(4ull * std::max<u64>(1, d.n_branch));
   p.o_br_cnt = take(4ull * 256 * std::max<u64>(1, p.br_tiles));
@@ -159,6 +160,7 @@ void fill_args(const aiwc_trace *t, const TracePlan &p, char *scratch, char *res
   a.part_hist = (u32 *)(scratch + p.o_part_hist);
   a.part_off = (u32 *)(scratch + p.o_part_off);
   a.part_rec = (u64 *)(scratch + p.o_part_rec);
+  a.mem_stage = (u32 *)(scratch + p.o_mem_stage);
   a.br_a = (u32 *)(scratch + p.o_br_a);
   a.br_b = (u32 *)(scratch + p.o_br_b);
   a.br_cnt = (u32 *)(scratch + p.o_br_cnt);
@@ -179,6 +181,7 @@ void add_dims(const aiwc_trace *t, const TracePlan &p, const TraceArgs &a, Batch
   d.max_zero16 = std::max<u64>(d.max_zero16, p.zero_bytes / 16);
   d.max_ids = std::max<u32>(d.max_ids, D.n_opcode_ids);
   d.ops_lds = std::max<u64>(d.ops_lds, aiwc_kernels::ops_lds_bytes(D.n_opcode_ids));
+  if ((uintptr_t)a.opcode % 16) d.ops_vec = false;
   if (D.n_mem) {
     d.any_mem = true;
     d.max_hist_blocks = std::max<u64>(d.max_hist_blocks, p.n_hist_blocks);

@@ -70,6 +70,7 @@ struct TraceArgs {
   u32 *part_hist;            // [n_hist_blocks][P]
   u32 *part_off;             // [P + 1]
   u64 *part_rec;             // [n_mem]
+  u32 *mem_stage;            // [n_mem] records regrouped page by page
   u32 *br_a, *br_b;          // [n_branch] radix ping-pong
   u32 *br_cnt;               // [256 * br_tiles]
   u32 *scan_tmp;             // block sums for the generic scan
@@ -184,6 +185,7 @@ struct BatchDims {
   u64 ops_lds = 0;                    // dynamic LDS of the ops kernel (max over traces)
   bool any_mem = false, any_branch = false;
   bool vec = true;                    // every address / kind array 16 / 4 B aligned
+  bool ops_vec = true;                // every opcode array 16 B aligned
 };
 
 namespace aiwc_kernels {

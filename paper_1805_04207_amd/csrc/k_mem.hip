@@ -33,11 +33,8 @@
 namespace {
 
 constexpr int MEM_BLOCK = 1024;
-constexpr u32 TBL_C = 9216;       // LDS table slots
-constexpr u32 TBL_CAP = 7680;     // live entries before a partition is split
-constexpr u32 SPEC_SLOTS = 256;   // per-space LDS cache of the level-0 spectrum
+constexpr u32 SPEC_SLOTS = 128;   // per-space LDS cache of the level-0 spectrum
 constexpr u64 EMPTY = ~0ull;
-constexpr int MAX_PER_THREAD = (TBL_CAP + MEM_BLOCK + MEM_BLOCK - 1) / MEM_BLOCK;  // 9
 
 __device__ __forceinline__ u64 make_record(u64 a, uint8_t kind, u32 pbits, u32 &bin) {
   const u64 h = mix54(a >> 10);
@@ -199,18 +196,46 @@ __global__ void __launch_bounds__(MEM_BLOCK) k_mem_scatter(TraceArgs A0, const T
 }
 
 // ---------------------------------------------------------------- bucket
+// One block per partition at a time (persistent, partitions from a queue).
+//  1. page pass   : an LDS table of the partition's pages (record >> 11, which
+//                   includes the space bit) counts the records of each page.
+//                   More than PT_CAP pages: the partition is split into rounds
+//                   by page-hash bits (never by record, so every a >> k bucket
+//                   stays whole) and redone.
+//  2. page sort   : records are regrouped page by page into a staging array
+//                   (u32: page index, byte offset, write flag).
+//  3. pages       : a wavefront takes a page, counts its records in a dense
+//                   array of 1024 byte-offset counters (LDS), then evaluates
+//                   every skip level at once: levels 0..4 from the 16
+//                   counters a lane holds, levels 5..10 by cross-lane sums.
+//                   Each non-empty node adds 1 to distinct_k and its entropy
+//                   term c*log2(N/c) (exact 2^-64 fixed point) to level k.
+//                   Pages with more than HEAVY records are counted by the
+//                   whole block first.
+constexpr u32 PT_SLOTS = 2048;
+constexpr u32 PT_CAP = 1536;
+constexpr int BK_BLOCK = 512;                    // 8 waves: 256 VGPRs per lane
+constexpr int BK_WAVES = BK_BLOCK / AIWC_WAVE;    // 8
+constexpr u32 HEAVY = 8192;
+constexpr u32 NSPEC = 8;                          // level-0 counts 1..8 kept per lane
+
 struct BucketShared {
-  u64 key[TBL_C];            // (key << 2) | read/write flags, EMPTY if free
-  u32 cnt[TBL_C];
-  uint16_t live[TBL_C];
-  u64 tlo[2][256], thi[2][256];   // entropy term table for c < 256, per space
-  u64 spf[2][SPEC_SLOTS], spm[2][SPEC_SLOTS];  // level-0 spectrum cache
+  u64 pkey[PT_SLOTS];              // page key, EMPTY if free
+  u32 pcnt[PT_SLOTS];              // records of the page
+  uint16_t pidx[PT_SLOTS];         // compact index of the page
+  uint16_t pslot[PT_CAP];          // slot of compact index
+  u32 poff[PT_CAP + 1];            // staging offset of compact index
+  u32 pcur[PT_CAP];
+  u32 dense[BK_WAVES][1024];       // per-wave byte-offset counters
+  u32 rbits[BK_WAVES][32], wbits[BK_WAVES][32];
+  u64 tlo[2][256], thi[2][256];    // entropy term table for c < 256
+  u64 spf[2][SPEC_SLOTS], spm[2][SPEC_SLOTS];
   u64 dist[2][AIWC_NSKIP], elo[2][AIWC_NSKIP], ehi[2][AIWC_NSKIP];
   u64 ur[2], uw[2];
   u64 redos;
-  u32 live_n, overflow, work;
+  u32 wsum[BK_WAVES];
+  u32 npages, overflow, work, next_page, sp_top;
   u32 stack_m[64], stack_c[64];
-  u32 sp_top;
 };
 
 // c * log2(N / c) as 2^-64 fixed point.
@@ -220,80 +245,173 @@ __device__ __forceinline__ void term_fx(u64 c, u64 N, u64 &lo, u64 &hi) {
   to_fx64(d, lo, hi);
 }
 
-__device__ void global_spec_add(const TraceArgs &A, u32 s, u64 f, u64 m) {
-  u64 *F = A.sp_f + (u64)s * A.sp_cap;
-  u64 *M = A.sp_m + (u64)s * A.sp_cap;
-  u32 slot = hash_slot(f, A.sp_cap);
-  for (u32 probe = 0; probe < A.sp_cap; ++probe) {
+// The sparse level-0 spectrum of one space in global memory: f -> m_f.
+struct SpecRef {
+  u64 *f, *m;
+  u32 cap;
+};
+
+__device__ void global_spec_add(SpecRef G, u32 s, u64 f, u64 m) {
+  u64 *F = G.f + (u64)s * G.cap;
+  u64 *M = G.m + (u64)s * G.cap;
+  u32 slot = hash_slot(f, G.cap);
+  for (u32 probe = 0; probe < G.cap; ++probe) {
     u64 old = atomicCAS(&F[slot], 0ull, f);
     if (old == 0ull || old == f) { atomicAdd(&M[slot], m); return; }
-    slot = (slot + 1 == A.sp_cap) ? 0 : slot + 1;
+    slot = (slot + 1 == G.cap) ? 0 : slot + 1;
   }
 }
 
-__device__ __forceinline__ void spec_cache_add(BucketShared &S, const TraceArgs &A, u32 s, u64 f,
-                                               u64 m) {
-  u32 slot = (u32)((f * 0x9E3779B97F4A7C15ull) >> 56);  // 0..255
+__device__ __noinline__ void spec_cache_add(BucketShared &S, SpecRef G, u32 s, u64 f, u64 m) {
+  u32 slot = (u32)((f * 0x9E3779B97F4A7C15ull) >> 56) & (SPEC_SLOTS - 1);
   for (u32 probe = 0; probe < 16; ++probe) {
     u64 old = atomicCAS(&S.spf[s][slot], 0ull, f);
     if (old == 0ull || old == f) { atomicAdd(&S.spm[s][slot], m); return; }
     slot = (slot + 1) & (SPEC_SLOTS - 1);
   }
-  global_spec_add(A, s, f, m);
+  global_spec_add(G, s, f, m);
 }
 
-// Level-0 inserts stop at TBL_CAP live entries (the partition is then split);
-// coarser levels never hold more entries than level 0, so they skip the check
-// and use the TBL_C - TBL_CAP spare slots only as probing slack.
-__device__ __forceinline__ bool tbl_insert(BucketShared &S, u64 key, u64 flag, u32 c,
-                                           bool capped) {
-  u32 slot = hash_slot(key, TBL_C);
-  const u64 word = (key << 2) | flag;
-  while (true) {
-    u64 w = S.key[slot];
-    if (w == EMPTY) {
-      if (capped && S.live_n >= TBL_CAP) { S.overflow = 1; return false; }
-      u64 old = atomicCAS(&S.key[slot], EMPTY, word);
-      if (old == EMPTY) {
-        atomicAdd(&S.cnt[slot], c);
-        u32 idx = atomicAdd(&S.live_n, 1u);
-        if (idx < TBL_C) S.live[idx] = (uint16_t)slot;
-        return true;
+// Per-lane accumulators of one address space (flushed when the space changes).
+struct LaneAcc {
+  u64 lo[AIWC_NSKIP], hi[AIWC_NSKIP];
+  u32 d[AIWC_NSKIP];
+  u32 spec[NSPEC];
+  u32 ur, uw;
+  int space;
+};
+
+__device__ __forceinline__ void lacc_clear(LaneAcc &L, int space) {
+#pragma unroll
+  for (int k = 0; k < AIWC_NSKIP; ++k) { L.lo[k] = 0; L.hi[k] = 0; L.d[k] = 0; }
+#pragma unroll
+  for (int j = 0; j < (int)NSPEC; ++j) L.spec[j] = 0;
+  L.ur = L.uw = 0;
+  L.space = space;
+}
+
+__device__ __forceinline__ void lacc_flush(LaneAcc &L, BucketShared &S, SpecRef G) {
+  const int s = L.space;
+  const int lane = lane_id();
+#pragma unroll
+  for (int k = 0; k < AIWC_NSKIP; ++k) {
+    u64 lo = L.lo[k], hi = L.hi[k];
+    wave_sum_u128(lo, hi);
+    const u64 d = wave_sum_u64(L.d[k]);
+    if (lane == 0) {
+      atomic_add_u128(&S.elo[s][k], &S.ehi[s][k], lo, hi);
+      if (d) atomicAdd(&S.dist[s][k], d);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < (int)NSPEC; ++j) {
+    const u64 m = wave_sum_u64(L.spec[j]);
+    if (lane == 0 && m) spec_cache_add(S, G, (u32)s, (u64)(j + 1), m);
+  }
+  const u64 r = wave_sum_u64(L.ur), w = wave_sum_u64(L.uw);
+  if (lane == 0) {
+    if (r) atomicAdd(&S.ur[s], r);
+    if (w) atomicAdd(&S.uw[s], w);
+  }
+  lacc_clear(L, s);
+}
+
+// large counts are rare: keep the logarithm out of line
+__device__ __noinline__ void term_big(u32 c, u64 N, u64 *lo, u64 *hi) {
+  u64 a, b;
+  term_fx(c, N, a, b);
+  *lo = a;
+  *hi = b;
+}
+
+// All levels of one page whose byte-offset counts sit in cnt[1024] (LDS,
+// owned by this wavefront) and whose read / write bitmaps in rb[32], wb[32].
+// Level k has 1024 >> k nodes; node i of level k >= 1 is the sum of nodes 2i
+// and 2i+1 of level k-1, reduced in place: within one wavefront every lane's
+// loads of an iteration are issued before its stores, and an iteration only
+// overwrites entries that earlier iterations have already read.
+__device__ __forceinline__ void page_levels(LaneAcc &L, BucketShared &S, SpecRef G,
+                                            u32 *cnt, const u32 *rb, const u32 *wb, u64 N) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int k = 0; k < AIWC_NSKIP; ++k) {
+    const u32 nodes = 1024u >> k;
+    u64 lo = 0, hi = 0;
+    u32 d = 0;
+    for (u32 i = (u32)lane; i < nodes; i += AIWC_WAVE) {
+      u32 c;
+      if (k == 0) {
+        c = cnt[i];
+      } else {
+        c = cnt[2 * i] + cnt[2 * i + 1];
+        cnt[i] = c;
       }
-      w = old;
+      if (c == 0) continue;
+      u64 tl, th;
+      if (c < 256) { tl = S.tlo[L.space][c]; th = S.thi[L.space][c]; }
+      else term_big(c, N, &tl, &th);
+      const u64 nl = lo + tl;
+      hi += th + (nl < lo ? 1ull : 0ull);
+      lo = nl;
+      d += 1;
+      if (k == 0) {
+        if (c <= NSPEC) {
+#pragma unroll
+          for (int j = 0; j < (int)NSPEC; ++j) L.spec[j] += (c == (u32)(j + 1));
+        } else {
+          spec_cache_add(S, G, (u32)L.space, c, 1ull);
+        }
+      }
     }
-    if ((w >> 2) == key) {
-      if (flag & ~w) atomicOr(&S.key[slot], flag);
-      atomicAdd(&S.cnt[slot], c);
-      return true;
-    }
-    slot = (slot + 1 == TBL_C) ? 0 : slot + 1;
+    const u64 nl = L.lo[k] + lo;
+    L.hi[k] += hi + (nl < L.lo[k] ? 1ull : 0ull);
+    L.lo[k] = nl;
+    L.d[k] += d;
+    __builtin_amdgcn_wave_barrier();
+  }
+  if (lane < 32) {
+    L.ur += __builtin_popcount(rb[lane]);
+    L.uw += __builtin_popcount(wb[lane]);
   }
 }
 
+__device__ __forceinline__ u32 pt_find(const BucketShared &S, u64 pk) {
+  u32 slot = hash_slot(pk, PT_SLOTS);
+  while (S.pkey[slot] != pk) slot = (slot + 1 == PT_SLOTS) ? 0 : slot + 1;
+  return slot;
+}
+
 template <bool BATCH>
-__global__ void __launch_bounds__(MEM_BLOCK) k_mem_bucket(TraceArgs A0, const TraceArgs *batch) {
+__global__ void __launch_bounds__(BK_BLOCK) k_mem_bucket(TraceArgs A0, const TraceArgs *batch) {
   __shared__ BucketShared S;
   const TraceArgs &A = trace_args<BATCH>(A0, batch);
   if (A.n_mem == 0) return;
-  const int tid = threadIdx.x, lane = lane_id();
+  const int tid = threadIdx.x, lane = lane_id(), wave = tid / AIWC_WAVE;
   const u32 P = 1u << A.pbits;
-  const u64 N[2] = {A.acc->sp_reads[0] + A.acc->sp_writes[0],
-                    A.acc->sp_reads[1] + A.acc->sp_writes[1]};
-  for (u32 i = tid; i < TBL_C; i += MEM_BLOCK) { S.key[i] = EMPTY; S.cnt[i] = 0; }
-  for (u32 i = tid; i < 2 * 256; i += MEM_BLOCK) {
+  const u32 sbit = PAGE_BITS - A.pbits;            // space bit position in a page key
+  const u64 N0 = A.acc->sp_reads[0] + A.acc->sp_writes[0];
+  const u64 N1 = A.acc->sp_reads[1] + A.acc->sp_writes[1];
+  u32 *staging = A.mem_stage;
+  const SpecRef G = {A.sp_f, A.sp_m, A.sp_cap};
+  for (u32 i = tid; i < PT_SLOTS; i += BK_BLOCK) { S.pkey[i] = EMPTY; S.pcnt[i] = 0; }
+  for (u32 i = tid; i < PT_CAP; i += BK_BLOCK) S.pcur[i] = 0;
+  for (u32 i = tid; i < 2 * 256; i += BK_BLOCK) {
     u64 lo, hi;
-    term_fx(i & 255u, N[i >> 8], lo, hi);
+    term_fx(i & 255u, (i >> 8) ? N1 : N0, lo, hi);
     S.tlo[i >> 8][i & 255u] = lo;
     S.thi[i >> 8][i & 255u] = hi;
-    S.spf[i >> 8][i & 255u] = 0;
-    S.spm[i >> 8][i & 255u] = 0;
+  }
+  for (u32 i = tid; i < 2 * SPEC_SLOTS; i += BK_BLOCK) {
+    (&S.spf[0][0])[i] = 0;
+    (&S.spm[0][0])[i] = 0;
   }
   if (tid < 2 * AIWC_NSKIP) {
     (&S.dist[0][0])[tid] = 0; (&S.elo[0][0])[tid] = 0; (&S.ehi[0][0])[tid] = 0;
   }
   if (tid < 2) { S.ur[tid] = 0; S.uw[tid] = 0; }
-  if (tid == 0) { S.redos = 0; S.live_n = 0; S.overflow = 0; }
+  if (tid == 0) { S.redos = 0; S.npages = 0; S.overflow = 0; }
+  LaneAcc L;
+  lacc_clear(L, 0);
   __syncthreads();
 
   while (true) {
@@ -302,31 +420,46 @@ __global__ void __launch_bounds__(MEM_BLOCK) k_mem_bucket(TraceArgs A0, const Tr
     const u32 p = S.work;
     if (p >= P) break;
     const u64 base = A.part_off[p];
-    const u64 n = (u64)A.part_off[p + 1] - base;
+    const u32 n = A.part_off[p + 1] - (u32)base;
     if (tid == 0) { S.sp_top = 1; S.stack_m[0] = 1; S.stack_c[0] = 0; }
     __syncthreads();
     while (S.sp_top > 0) {
-      __syncthreads();
       const u32 M = S.stack_m[S.sp_top - 1], C = S.stack_c[S.sp_top - 1];
       __syncthreads();
       if (tid == 0) S.sp_top -= 1;
-      // ---- level 0: insert this round's records
-      for (u64 i = tid; i < n; i += MEM_BLOCK) {
-        const u64 rec = A.part_rec[base + i];
-        if ((((u32)(rec >> 11)) & (M - 1u)) != C) continue;
-        if (!tbl_insert(S, rec >> 1, 1ull << (rec & 1ull), 1u, true)) break;
+      // ---- 1. page pass
+      for (u32 i = tid; i < n; i += BK_BLOCK) {
+        const u64 pk = A.part_rec[base + i] >> 11;
+        if (((u32)pk & (M - 1u)) != C) continue;
+        u32 slot = hash_slot(pk, PT_SLOTS);
+        while (true) {
+          u64 w = S.pkey[slot];
+          if (w == EMPTY) {
+            if (S.npages >= PT_CAP) { S.overflow = 1; break; }
+            u64 old = atomicCAS(&S.pkey[slot], EMPTY, pk);
+            if (old == EMPTY) {
+              const u32 ci = atomicAdd(&S.npages, 1u);
+              if (ci < PT_CAP) { S.pidx[slot] = (uint16_t)ci; S.pslot[ci] = (uint16_t)slot; }
+              else S.overflow = 1;
+              w = pk;
+            } else {
+              w = old;
+            }
+          }
+          if (w == pk) { atomicAdd(&S.pcnt[slot], 1u); break; }
+          slot = (slot + 1 == PT_SLOTS) ? 0 : slot + 1;
+        }
       }
       __syncthreads();
-      if (S.overflow || S.live_n > TBL_CAP) {
-        // clear, split this round in two by one more hash bit, retry later
-        const u32 D = S.live_n < TBL_C ? S.live_n : TBL_C;
-        for (u32 j = tid; j < D; j += MEM_BLOCK) { S.key[S.live[j]] = EMPTY; S.cnt[S.live[j]] = 0; }
+      const u32 np = S.npages < PT_CAP ? S.npages : PT_CAP;
+      if (S.overflow) {
+        // too many pages for one round: clear and split by one more hash bit
+        for (u32 i = tid; i < PT_SLOTS; i += BK_BLOCK) { S.pkey[i] = EMPTY; S.pcnt[i] = 0; }
         __syncthreads();
         if (tid == 0) {
-          S.live_n = 0; S.overflow = 0; S.redos += 1;
+          S.npages = 0; S.overflow = 0; S.redos += 1;
           if (M >= (1u << 30) || S.sp_top + 2 > 64) {
-            // hash bits exhausted (adversarial page ids): report, never spin
-            atomicAdd(&A.acc->bad_mem, 1ull);
+            atomicAdd(&A.acc->bad_mem, 1ull);   // hash bits exhausted: report, never spin
           } else {
             S.stack_m[S.sp_top] = 2 * M; S.stack_c[S.sp_top] = C;
             S.stack_m[S.sp_top + 1] = 2 * M; S.stack_c[S.sp_top + 1] = C + M;
@@ -336,94 +469,105 @@ __global__ void __launch_bounds__(MEM_BLOCK) k_mem_bucket(TraceArgs A0, const Tr
         __syncthreads();
         continue;
       }
-      // ---- levels 0..10
-      for (int k = 0; k < AIWC_NSKIP; ++k) {
-        const u32 D = S.live_n;
-        const u32 sbit = 64u - A.pbits - (u32)k;   // space bit position in key_k
-        u64 key[MAX_PER_THREAD];
-        u32 c[MAX_PER_THREAD];
-        u64 lo0 = 0, hi0 = 0, lo1 = 0, hi1 = 0;
-        u32 d1 = 0, ur0 = 0, uw0 = 0, ur1 = 0, uw1 = 0, dtot = 0;
+      // ---- 2. staging offsets (exclusive scan of page counts) and regroup
+      if (tid < BK_WAVES) S.wsum[tid] = 0;
+      __syncthreads();
+      for (u32 b0 = 0; b0 < np; b0 += BK_BLOCK) {
+        const u32 j = b0 + tid;
+        const u32 c = j < np ? S.pcnt[S.pslot[j]] : 0u;
+        u32 x = c;
 #pragma unroll
-        for (int q = 0; q < MAX_PER_THREAD; ++q) {
-          const u32 j = tid + q * MEM_BLOCK;
-          key[q] = EMPTY;
-          c[q] = 0;
-          if (j < D) {
-            const u32 slot = S.live[j];
-            const u64 w = S.key[slot];
-            key[q] = w >> 2;
-            c[q] = S.cnt[slot];
-            const u32 s = (u32)(key[q] >> sbit) & 1u;
-            u64 tl, th;
-            if (c[q] < 256) { tl = S.tlo[s][c[q]]; th = S.thi[s][c[q]]; }
-            else term_fx(c[q], N[s], tl, th);
-            if (s) { u64 nl = lo1 + tl; hi1 += th + (nl < lo1); lo1 = nl; d1 += 1; }
-            else   { u64 nl = lo0 + tl; hi0 += th + (nl < lo0); lo0 = nl; }
-            dtot += 1;
-            if (k == 0) {
-              if (w & 1ull) { if (s) ur1 += 1; else ur0 += 1; }
-              if (w & 2ull) { if (s) uw1 += 1; else uw0 += 1; }
-            }
-          }
+        for (int o = 1; o < 64; o <<= 1) {
+          const u32 y = __shfl_up(x, o, 64);
+          if (lane >= o) x += y;
         }
-        // level statistics -> per-block accumulators
-        wave_sum_u128(lo0, hi0);
-        wave_sum_u128(lo1, hi1);
-        const u64 sd1 = wave_sum_u64(d1), sdt = wave_sum_u64(dtot);
-        if (lane == 0) {
-          atomic_add_u128(&S.elo[0][k], &S.ehi[0][k], lo0, hi0);
-          atomic_add_u128(&S.elo[1][k], &S.ehi[1][k], lo1, hi1);
-          if (sd1) atomicAdd(&S.dist[1][k], sd1);
-          if (sdt - sd1) atomicAdd(&S.dist[0][k], sdt - sd1);
-        }
-        if (k == 0) {
-          const u64 a0 = wave_sum_u64(ur0), a1 = wave_sum_u64(uw0);
-          const u64 a2 = wave_sum_u64(ur1), a3 = wave_sum_u64(uw1);
-          if (lane == 0) {
-            if (a0) atomicAdd(&S.ur[0], a0);
-            if (a1) atomicAdd(&S.uw[0], a1);
-            if (a2) atomicAdd(&S.ur[1], a2);
-            if (a3) atomicAdd(&S.uw[1], a3);
-          }
-          // count spectrum: aggregate equal (space, count) pairs per wave
-#pragma unroll
-          for (int q = 0; q < MAX_PER_THREAD; ++q) {
-            const u64 v = (key[q] == EMPTY) ? ~0ull
-                                            : (((key[q] >> sbit) & 1ull) << 40) | (u64)c[q];
-            u64 pend = __ballot(v != ~0ull);
-            while (pend) {
-              const int leader = __builtin_ctzll(pend);
-              const u64 lv = __shfl(v, leader, 64);
-              const u64 mask = __ballot(v == lv);
-              if (lane == leader)
-                spec_cache_add(S, A, (u32)(lv >> 40), lv & 0xFFFFFFFFFFull,
-                               (u64)__builtin_popcountll(mask));
-              pend &= ~mask;
-            }
-          }
-        }
+        if (lane == 63) S.wsum[wave] = x;
         __syncthreads();
-        // free this level's slots
-#pragma unroll
-        for (int q = 0; q < MAX_PER_THREAD; ++q) {
-          const u32 j = tid + q * MEM_BLOCK;
-          if (j < D) { const u32 slot = S.live[j]; S.key[slot] = EMPTY; S.cnt[slot] = 0; }
-        }
+        u32 before = b0 == 0 ? 0u : S.poff[b0];
+        for (int w = 0; w < wave; ++w) before += S.wsum[w];
+        if (j < np) S.poff[j] = before + x - c;
+        u32 tot = b0 == 0 ? 0u : S.poff[b0];
+        for (int w = 0; w < BK_WAVES; ++w) tot += S.wsum[w];
         __syncthreads();
-        if (tid == 0) S.live_n = 0;
+        if (tid == 0) S.poff[b0 + BK_BLOCK < np ? b0 + BK_BLOCK : np] = tot;
         __syncthreads();
-        if (k + 1 < AIWC_NSKIP) {
-#pragma unroll
-          for (int q = 0; q < MAX_PER_THREAD; ++q)
-            if (key[q] != EMPTY) tbl_insert(S, key[q] >> 1, 0ull, c[q], false);
-          __syncthreads();
-        }
       }
+      for (u32 i = tid; i < n; i += BK_BLOCK) {
+        const u64 rec = A.part_rec[base + i];
+        const u64 pk = rec >> 11;
+        if (((u32)pk & (M - 1u)) != C) continue;
+        const u32 ci = S.pidx[pt_find(S, pk)];
+        const u32 pos = S.poff[ci] + atomicAdd(&S.pcur[ci], 1u);
+        staging[base + pos] = (ci << 11) | (u32)(rec & 2047ull);
+      }
+      __threadfence_block();
+      __syncthreads();
+      // ---- 3a. heavy pages: counted by the whole block into dense[0]
+      for (u32 ci = 0; ci < np; ++ci) {
+        const u32 cnt = S.poff[ci + 1] - S.poff[ci];
+        if (cnt <= HEAVY) continue;
+        for (u32 i = tid; i < 1024; i += BK_BLOCK) S.dense[0][i] = 0;
+        if (tid < 32) { S.rbits[0][tid] = 0; S.wbits[0][tid] = 0; }
+        __syncthreads();
+        for (u32 i = S.poff[ci] + tid; i < S.poff[ci + 1]; i += BK_BLOCK) {
+          const u32 v = staging[base + i];
+          const u32 off = (v >> 1) & 1023u;
+          atomicAdd(&S.dense[0][off], 1u);
+          atomicOr((v & 1u) ? &S.wbits[0][off >> 5] : &S.rbits[0][off >> 5], 1u << (off & 31u));
+        }
+        __syncthreads();
+        if (wave == 0) {
+          const int sp = (int)((S.pkey[S.pslot[ci]] >> sbit) & 1ull);
+          if (sp != L.space) { lacc_flush(L, S, G); L.space = sp; }
+          page_levels(L, S, G, S.dense[0], S.rbits[0], S.wbits[0], sp ? N1 : N0);
+        }
+        __syncthreads();
+      }
+      // ---- 3b. other pages: one wavefront each
+      if (tid == 0) S.next_page = 0;
+      __syncthreads();
+      u32 *dn = S.dense[wave];
+      u32 *rb = S.rbits[wave], *wb = S.wbits[wave];
+      while (true) {
+        u32 ci = 0;
+        if (lane == 0) ci = atomicAdd(&S.next_page, 1u);
+        ci = __shfl(ci, 0, 64);
+        if (ci >= np) break;
+        const u32 o0 = S.poff[ci], o1 = S.poff[ci + 1];
+        if (o1 - o0 > HEAVY) continue;
+        uint4 *z = reinterpret_cast<uint4 *>(dn + 16 * lane);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) z[q] = make_uint4(0, 0, 0, 0);
+        if (lane < 32) { rb[lane] = 0; wb[lane] = 0; }
+        __builtin_amdgcn_wave_barrier();
+        for (u32 i = o0 + lane; i < o1; i += AIWC_WAVE) {
+          const u32 v = staging[base + i];
+          const u32 off = (v >> 1) & 1023u;
+          atomicAdd(&dn[off], 1u);
+          atomicOr((v & 1u) ? &wb[off >> 5] : &rb[off >> 5], 1u << (off & 31u));
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        const int sp = (int)((S.pkey[S.pslot[ci]] >> sbit) & 1ull);
+        if (sp != L.space) { lacc_flush(L, S, G); L.space = sp; }
+        page_levels(L, S, G, dn, rb, wb, sp ? N1 : N0);
+        __builtin_amdgcn_wave_barrier();
+      }
+      __syncthreads();
+      // ---- release the page table for the next round / partition
+      for (u32 j = tid; j < np; j += BK_BLOCK) {
+        const u32 slot = S.pslot[j];
+        S.pkey[slot] = EMPTY;
+        S.pcnt[slot] = 0;
+        S.pcur[j] = 0;
+      }
+      __syncthreads();
+      if (tid == 0) S.npages = 0;
+      __syncthreads();
     }
-    __syncthreads();
   }
-  // ---- flush the block's accumulators
+  // ---- flush the lanes' and the block's accumulators
+  lacc_flush(L, S, G);
   __syncthreads();
   if (tid < 2 * AIWC_NSKIP) {
     const int s = tid / AIWC_NSKIP, k = tid % AIWC_NSKIP;
@@ -435,9 +579,9 @@ __global__ void __launch_bounds__(MEM_BLOCK) k_mem_bucket(TraceArgs A0, const Tr
     if (S.uw[tid]) atomicAdd(&A.acc->uniq_w[tid], S.uw[tid]);
   }
   if (tid == 0 && S.redos) atomicAdd(&A.acc->redos, S.redos);
-  for (u32 i = tid; i < 2 * SPEC_SLOTS; i += MEM_BLOCK) {
+  for (u32 i = tid; i < 2 * SPEC_SLOTS; i += BK_BLOCK) {
     const u32 s = i / SPEC_SLOTS, j = i % SPEC_SLOTS;
-    if (S.spf[s][j]) global_spec_add(A, s, S.spf[s][j], S.spm[s][j]);
+    if (S.spf[s][j]) global_spec_add(G, s, S.spf[s][j], S.spm[s][j]);
   }
 }
 
@@ -445,12 +589,11 @@ __global__ void __launch_bounds__(MEM_BLOCK) k_mem_bucket(TraceArgs A0, const Tr
 
 namespace aiwc_kernels {
 
-size_t bucket_lds_bytes() { return sizeof(BucketShared); }
 
 hipError_t launch_mem(const TraceArgs &a, const BatchDims &d, hipStream_t s, StageMarks *pm) {
   if (!d.any_mem) return hipSuccess;
   const dim3 gh((unsigned)d.max_hist_blocks, d.n), gc((unsigned)((d.max_parts + 255) / 256), d.n);
-  const dim3 g1(1, d.n), gb((unsigned)(d.max_parts < 256 ? d.max_parts : 256), d.n);
+  const dim3 g1(1, d.n), gb((unsigned)(d.max_parts < 512 ? d.max_parts : 512), d.n);
   const TraceArgs *b = d.batch;
   if (b) {
     if (d.vec) hipLaunchKernelGGL((k_mem_hist<true, true>), gh, dim3(MEM_BLOCK), 0, s, a, b);
@@ -476,8 +619,8 @@ hipError_t launch_mem(const TraceArgs &a, const BatchDims &d, hipStream_t s, Sta
     else hipLaunchKernelGGL((k_mem_scatter<false, false>), gh, dim3(MEM_BLOCK), 0, s, a, b);
   }
   AIWC_MARK(pm, "k_mem_scatter", s);
-  if (b) hipLaunchKernelGGL(k_mem_bucket<true>, gb, dim3(MEM_BLOCK), 0, s, a, b);
-  else hipLaunchKernelGGL(k_mem_bucket<false>, gb, dim3(MEM_BLOCK), 0, s, a, b);
+  if (b) hipLaunchKernelGGL(k_mem_bucket<true>, gb, dim3(BK_BLOCK), 0, s, a, b);
+  else hipLaunchKernelGGL(k_mem_bucket<false>, gb, dim3(BK_BLOCK), 0, s, a, b);
   AIWC_MARK(pm, "k_mem_bucket", s);
   return hipGetLastError();
 }

@@ -60,7 +60,7 @@ __host__ __device__ __forceinline__ u32 ops_copies(u32 nid) {
   return nc;
 }
 
-template <bool LDS_IDS, bool BATCH>
+template <bool LDS_IDS, bool BATCH, bool VEC>
 __global__ void __launch_bounds__(OPS_BLOCK) k_ops(TraceArgs A0, const TraceArgs *batch) {
   extern __shared__ u32 lds[];
   const TraceArgs &A = trace_args<BATCH>(A0, batch);
@@ -101,64 +101,79 @@ __global__ void __launch_bounds__(OPS_BLOCK) k_ops(TraceArgs A0, const TraceArgs
     u64 cur_w = w_lo, cur_begin = e0, seg_start = e0;
     u64 cur_end = A.wi_off[cur_w + 1];
 
-    for (u64 cb = e0; cb < e1; cb += 8 * AIWC_WAVE) {
+    // 512-event chunks: lane l holds events [cb + 8l, cb + 8l + 8) (one
+    // 16-byte load when aligned), barrier positions as per-lane bit masks.
+    for (u64 cb = e0 & ~7ull; cb < e1; cb += 8 * AIWC_WAVE) {
+      const u64 i0 = cb + 8ull * lane;
       u32 ids[8];
+      if (VEC && i0 >= e0 && i0 + 8 <= e1) {
+        const uint4 v = *reinterpret_cast<const uint4 *>(A.opcode + i0);
+        ids[0] = v.x & 0xFFFFu; ids[1] = v.x >> 16; ids[2] = v.y & 0xFFFFu; ids[3] = v.y >> 16;
+        ids[4] = v.z & 0xFFFFu; ids[5] = v.z >> 16; ids[6] = v.w & 0xFFFFu; ids[7] = v.w >> 16;
+      } else {
 #pragma unroll
-      for (int s = 0; s < 8; ++s) {
-        u64 i = cb + (u64)s * AIWC_WAVE + lane;
-        ids[s] = (i < e1) ? (u32)A.opcode[i] : 0xFFFFFFFFu;
-      }
-#pragma unroll
-      for (int s = 0; s < 8; ++s) {
-        const u64 sb = cb + (u64)s * AIWC_WAVE;
-        if (sb >= e1) break;
-        const u32 id = ids[s];
-        bool isbar = false;
-        if (id != 0xFFFFFFFFu) {
-          if (id < nid) {
-            u32 in;
-            if (LDS_IDS) {
-              in = info[id];
-              atomicAdd(&hist[copy * nid + id], 1u);
-            } else {
-              in = A.op_info[id];
-              atomicAdd(&A.id_hist[id], 1ull);
-            }
-            isbar = (in & 0xFFu) == KIND_BARRIER;
-          } else {
-            st.bad += 1;  // per lane; summed at the end
-          }
+        for (int j = 0; j < 8; ++j) {
+          const u64 i = i0 + j;
+          ids[j] = (i >= e0 && i < e1) ? (u32)A.opcode[i] : 0xFFFFFFFFu;
         }
-        u64 B = __ballot(isbar);
-        const u64 lim = (sb + AIWC_WAVE < e1) ? sb + AIWC_WAVE : e1;
-        // walk barrier and work-item-end markers of [sb, lim) in order
-        while (true) {
-          const u64 nb = B ? sb + (u64)__builtin_ctzll(B) : ~0ull;
-          if (cur_w < w_hi && cur_end <= lim && cur_end <= nb) {
-            const u64 v = cur_end - seg_start, ipt = cur_end - cur_begin;
-            record_value(v, itbh, A.itb_hist, A.itb_large, &A.acc->itb_large_n, A.large_cap, lane);
-            record_value(ipt, ipth, A.ipt_hist, A.ipt_large, &A.acc->ipt_large_n, A.large_cap, lane);
-            st.itb_min = v < st.itb_min ? v : st.itb_min;
-            st.itb_max = v > st.itb_max ? v : st.itb_max;
-            st.itb_cnt += 1; st.itb_sum += v;
-            st.ipt_min = ipt < st.ipt_min ? ipt : st.ipt_min;
-            st.ipt_max = ipt > st.ipt_max ? ipt : st.ipt_max;
-            st.ipt_cnt += 1; st.ipt_sum += ipt;
-            seg_start = cur_begin = cur_end;
-            ++cur_w;
-            cur_end = (cur_w < w_hi) ? A.wi_off[cur_w + 1] : ~0ull;
-            continue;
+      }
+      u32 bm = 0;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const u32 id = ids[j];
+        if (id == 0xFFFFFFFFu) continue;
+        if (id < nid) {
+          u32 in;
+          if (LDS_IDS) {
+            in = info[id];
+            atomicAdd(&hist[copy * nid + id], 1u);
+          } else {
+            in = A.op_info[id];
+            atomicAdd(&A.id_hist[id], 1ull);
           }
-          if (B == 0) break;
-          const u64 v = nb + 1 - seg_start;
+          if ((in & 0xFFu) == KIND_BARRIER) bm |= 1u << j;
+        } else {
+          st.bad += 1;  // per lane; summed at the end
+        }
+      }
+      u64 B = __ballot(bm != 0);
+      const u64 lim = (cb + 8 * AIWC_WAVE < e1) ? cb + 8 * AIWC_WAVE : e1;
+      // walk barrier and work-item-end markers of [cb, lim) in order
+      while (true) {
+        u64 nb = ~0ull;
+        int bl = 0;
+        u32 lm = 0;
+        if (B) {
+          bl = __builtin_ctzll(B);
+          lm = __shfl(bm, bl, 64);
+          nb = cb + 8ull * bl + (u64)__builtin_ctz(lm);
+        }
+        if (cur_w < w_hi && cur_end <= lim && cur_end <= nb) {
+          const u64 v = cur_end - seg_start, ipt = cur_end - cur_begin;
           record_value(v, itbh, A.itb_hist, A.itb_large, &A.acc->itb_large_n, A.large_cap, lane);
+          record_value(ipt, ipth, A.ipt_hist, A.ipt_large, &A.acc->ipt_large_n, A.large_cap, lane);
           st.itb_min = v < st.itb_min ? v : st.itb_min;
           st.itb_max = v > st.itb_max ? v : st.itb_max;
           st.itb_cnt += 1; st.itb_sum += v;
-          st.barriers += 1;
-          seg_start = nb + 1;
-          B &= B - 1;
+          st.ipt_min = ipt < st.ipt_min ? ipt : st.ipt_min;
+          st.ipt_max = ipt > st.ipt_max ? ipt : st.ipt_max;
+          st.ipt_cnt += 1; st.ipt_sum += ipt;
+          seg_start = cur_begin = cur_end;
+          ++cur_w;
+          cur_end = (cur_w < w_hi) ? A.wi_off[cur_w + 1] : ~0ull;
+          continue;
         }
+        if (B == 0) break;
+        const u64 v = nb + 1 - seg_start;
+        record_value(v, itbh, A.itb_hist, A.itb_large, &A.acc->itb_large_n, A.large_cap, lane);
+        st.itb_min = v < st.itb_min ? v : st.itb_min;
+        st.itb_max = v > st.itb_max ? v : st.itb_max;
+        st.itb_cnt += 1; st.itb_sum += v;
+        st.barriers += 1;
+        seg_start = nb + 1;
+        lm &= lm - 1;
+        if (lane == bl) bm = lm;
+        if (lm == 0) B &= B - 1;
       }
     }
     // work-items left open at the end of the task (trailing empty ones)
@@ -257,18 +272,18 @@ hipError_t launch_ops(const TraceArgs &a, const BatchDims &d, hipStream_t s, Sta
   u64 waves = d.max_ops_tasks < 4096 ? d.max_ops_tasks : 4096;
   unsigned gx = (unsigned)((waves + OPS_WAVES - 1) / OPS_WAVES);
   size_t tail = OPS_WAVES * sizeof(WaveStats) + 2 * LDS_VALS * 4;
+  const dim3 g(gx, d.n), blk(OPS_BLOCK);
+  const TraceArgs *b = d.batch;
+  const size_t lds = d.max_ids <= 8192 ? (d.ops_lds ? d.ops_lds : ops_lds_bytes(d.max_ids)) : tail;
+#define OPS_LAUNCH(L, B, V) hipLaunchKernelGGL((k_ops<L, B, V>), g, blk, lds, s, a, b)
   if (d.max_ids <= 8192) {
-    const size_t lds = d.ops_lds ? d.ops_lds : ops_lds_bytes(d.max_ids);
-    if (d.batch)
-      hipLaunchKernelGGL((k_ops<true, true>), dim3(gx, d.n), dim3(OPS_BLOCK), lds, s, a, d.batch);
-    else
-      hipLaunchKernelGGL((k_ops<true, false>), dim3(gx), dim3(OPS_BLOCK), lds, s, a, nullptr);
+    if (b) { if (d.ops_vec) OPS_LAUNCH(true, true, true); else OPS_LAUNCH(true, true, false); }
+    else { if (d.ops_vec) OPS_LAUNCH(true, false, true); else OPS_LAUNCH(true, false, false); }
   } else {
-    if (d.batch)
-      hipLaunchKernelGGL((k_ops<false, true>), dim3(gx, d.n), dim3(OPS_BLOCK), tail, s, a, d.batch);
-    else
-      hipLaunchKernelGGL((k_ops<false, false>), dim3(gx), dim3(OPS_BLOCK), tail, s, a, nullptr);
+    if (b) { if (d.ops_vec) OPS_LAUNCH(false, true, true); else OPS_LAUNCH(false, true, false); }
+    else { if (d.ops_vec) OPS_LAUNCH(false, false, true); else OPS_LAUNCH(false, false, false); }
   }
+#undef OPS_LAUNCH
   AIWC_MARK(pm, "k_ops", s);
   return hipGetLastError();
 }
