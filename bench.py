@@ -35,6 +35,75 @@ def algorithmic_bytes(name: str, n_ev: int, n_wi: int, n_mem: int, n_br: int, pa
     }.get(name, 0.0)
 
 
+def batch_legs(ctx, tr, spec, n_ev, args, stream):
+    """Batched + learned sizing vs the plain path: (1) the same large trace
+    through aiwc_characterize_batch with LEARNED sizing and a replayed
+    hipGraph; (2) a config3 batch of uneven traces, one plain call per trace
+    vs one batched call.  Metrics are checked identical."""
+    import torch
+    import tracegen as tg
+    import paper_1805_04207_amd as aiwc
+    from paper_1805_04207_amd.train_sizer import DEFAULT_WEIGHTS
+
+    out = {}
+    sizing = aiwc.SIZING_HEURISTIC
+    if os.path.exists(DEFAULT_WEIGHTS):
+        ctx.sizer_load(DEFAULT_WEIGHTS)
+        sizing = aiwc.SIZING_LEARNED
+    out["sizing"] = {aiwc.SIZING_LEARNED: "learned", aiwc.SIZING_HEURISTIC: "heuristic"}[sizing]
+    ref = ctx.characterize(tr, stream).read()
+    for _ in range(args.warmup):
+        got = ctx.characterize_batch([tr], sizing=sizing, use_graph=True, stream=stream)[0].read()
+    same = {k: v for k, v in got.items() if k not in ("overflow_redos", "partitions")} == \
+        {k: v for k, v in ref.items() if k not in ("overflow_redos", "partitions")}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        got = ctx.characterize_batch([tr], sizing=sizing, use_graph=True, stream=stream)[0].read()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out["large_trace"] = {"events_per_s": n_ev * args.steps / dt, "ms_per_step": 1e3 * dt / args.steps,
+                          "partitions": got["partitions"], "overflow_redos": got["overflow_redos"],
+                          "identical_to_plain": bool(same)}
+    # config3 batch: uneven traces, generated on the device
+    specs = tg.config3_specs(seed=2, n_traces=args.batch_traces, scale=args.batch_scale)
+    keep, trs, total = [], [], 0
+    for sp in specs:
+        d = tg.generate_device(sp, 0)
+        keep.append(d)
+        total += d["n_events"]
+        trs.append(aiwc.device_trace(ctx, d, tg.opcode_table(), sp.n_sites, sp.history_len,
+                                     sp.wg_size))
+    print(f"# config3 batch: {len(trs)} traces, {total} events", file=sys.stderr, flush=True)
+    plain = [ctx.characterize(t, stream).read() for t in trs]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(max(1, args.steps // 2)):
+        ms = [ctx.characterize(t, stream) for t in trs]
+        plain = [m.read() for m in ms]
+    torch.cuda.synchronize()
+    dt_plain = (time.perf_counter() - t0) / max(1, args.steps // 2)
+    bopts = dict(sizing=sizing, use_graph=True, autotune=aiwc.AUTOTUNE_SEARCH, stream=stream)
+    got = [m.read() for m in ctx.characterize_batch(trs, **bopts)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(max(1, args.steps // 2)):
+        got = [m.read() for m in ctx.characterize_batch(trs, **bopts)]
+    torch.cuda.synchronize()
+    dt_batch = (time.perf_counter() - t0) / max(1, args.steps // 2)
+    strip = lambda d: {k: v for k, v in d.items() if k not in ("overflow_redos", "partitions")}
+    st = ctx.batch_stats()
+    out["config3"] = {"traces": len(trs), "events": total,
+                      "plain_events_per_s": total / dt_plain,
+                      "batched_events_per_s": total / dt_batch,
+                      "speedup": dt_plain / dt_batch,
+                      "identical": all(strip(a) == strip(b) for a, b in zip(plain, got)),
+                      "waves": st["waves"], "redo_partitions": st["redo_partitions"],
+                      "total_partitions": st["total_partitions"]}
+    del keep
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -43,6 +112,10 @@ def main() -> int:
     ap.add_argument("--n-wi-log2", type=int, default=20, help="work-items = 2^x (config2 recipe)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-wi-log2", type=int, default=15)
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched legs")
+    ap.add_argument("--batch-traces", type=int, default=512)
+    ap.add_argument("--batch-scale", type=float, default=0.05,
+                    help="config3 lengths are scaled by this factor")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the multi-GPU sharding "
@@ -94,6 +167,10 @@ def main() -> int:
     print("# per-kernel ms: " + ", ".join(f"{k}={v:.3f}" for k, v in avg.items()),
           file=sys.stderr, flush=True)
 
+    batched = None
+    if not args.no_batch:
+        batched = batch_legs(ctx, tr, spec, n_ev, args, stream)
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -119,7 +196,7 @@ def main() -> int:
                    "compulsory_bytes": compulsory, "compulsory_gbps": comp_gbs,
                    "compulsory_hbm_frac": comp_gbs / HBM_PEAK_GBS,
                    "kernel_ms": avg, "partitions": r["partitions"],
-                   "overflow_redos": r["overflow_redos"]},
+                   "overflow_redos": r["overflow_redos"], "batched": batched},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None},
         "cpu_baseline": cpu,

@@ -57,9 +57,13 @@ void plan_trace(const aiwc_trace *t, u32 pbits, TracePlan &p, const Tune *tune) 
   int pb = (int)pbits + T.part_shift;
   p.pbits = d.n_mem ? (u32)std::min(15, std::max(4, pb)) : 4;
   const u64 P = 1ull << p.pbits;
-  // memory: histogram blocks up to the tuned maximum, >= 16K records each
+  // memory: histogram blocks up to the tuned maximum (more when the
+  // partition table is small enough for several blocks per CU), >= 16K
+  // records each
   u64 nb = (d.n_mem + 16383) / 16384;
-  nb = std::max<u64>(1, std::min<u64>(nb, std::max<u32>(1, T.hist_blocks)));
+  u64 nbmax = std::max<u32>(1, T.hist_blocks);
+  if (P <= 4096) nbmax *= 4; else if (P <= 8192) nbmax *= 2;
+  nb = std::max<u64>(1, std::min<u64>(nb, nbmax));
   p.n_hist_blocks = (u32)nb;
   p.hist_chunk = align_up((d.n_mem + nb - 1) / nb, 4);
   if (p.hist_chunk == 0) p.hist_chunk = 4;
@@ -111,8 +115,8 @@ void plan_trace(const aiwc_trace *t, u32 pbits, TracePlan &p, const Tune *tune) 
 }
 
 u32 bound_pbits(u64 n_mem) {
-  // distinct <= accesses: aim at <= 4096 distinct addresses per partition
-  u64 want = (n_mem + 4095) / 4096;
+  // pages <= accesses: aim at <= 1024 pages (1 KiB) per partition
+  u64 want = (n_mem + 1023) / 1024;
   u32 b = ceil_log2(std::max<u64>(want, 1));
   return std::min<u32>(15, std::max<u32>(4, b));
 }

@@ -9,12 +9,16 @@
 
 namespace {
 
-constexpr int FB = 1024;
+constexpr int FB = 512;
+
+constexpr u32 SPEC_LDS = 4096;   // spectrum pairs compacted into LDS
 
 struct FinShared {
   u64 red[FB / AIWC_WAVE];
   u64 red2[FB / AIWC_WAVE];
   u64 bcast[4];
+  u64 cf[SPEC_LDS], cm[SPEC_LDS];  // compacted (f, m_f) pairs of one space
+  u32 nc;
 };
 
 __device__ u64 block_sum(u64 v, FinShared &S) {
@@ -210,13 +214,28 @@ __global__ void __launch_bounds__(FB) k_finalize(TraceArgs A0, const TraceArgs *
   const double itb_med = median_of(A.itb_hist, A.itb_large, nl_itb, acc->itb_cnt, S);
   const double ipt_med = median_of(A.ipt_hist, A.ipt_large, nl_ipt, acc->ipt_cnt, S);
 
-  // ---- memory
+  // ---- memory: compact each space's sparse spectrum, then the coverage scan
   u64 fp90[2];
   for (int s = 0; s < 2; ++s) {
     const u64 *F = A.sp_f + (u64)s * A.sp_cap, *M = A.sp_m + (u64)s * A.sp_cap;
     const u64 N = acc->sp_reads[s] + acc->sp_writes[s];
-    fp90[s] = coverage90((u64)A.sp_cap, N,
-                         [F, M](u64 i, u64 &f, u64 &m) { f = F[i]; m = f ? M[i] : 0; }, S);
+    __syncthreads();
+    if (tid == 0) S.nc = 0;
+    __syncthreads();
+    for (u64 i = tid; i < A.sp_cap; i += FB) {
+      if (!F[i]) continue;
+      const u32 j = atomicAdd(&S.nc, 1u);
+      if (j < SPEC_LDS) { S.cf[j] = F[i]; S.cm[j] = M[i]; }
+    }
+    __syncthreads();
+    const u32 nc = S.nc;
+    if (nc <= SPEC_LDS) {
+      const u64 *cf = S.cf, *cm = S.cm;
+      fp90[s] = coverage90((u64)nc, N, [cf, cm](u64 i, u64 &f, u64 &m) { f = cf[i]; m = cm[i]; }, S);
+    } else {
+      fp90[s] = coverage90((u64)A.sp_cap, N,
+                           [F, M](u64 i, u64 &f, u64 &m) { f = F[i]; m = f ? M[i] : 0; }, S);
+    }
   }
 
   // ---- branches

@@ -50,7 +50,7 @@ constexpr u32 MAX_PARTS = 32768;
 
 template <bool VEC, bool BATCH>
 __global__ void __launch_bounds__(MEM_BLOCK) k_mem_hist(TraceArgs A0, const TraceArgs *batch) {
-  __shared__ u32 h[MAX_PARTS];
+  extern __shared__ u32 h[];   // [P]
   __shared__ u64 sp_cnt[4];  // reads g, writes g, reads l, writes l
   const TraceArgs &A = trace_args<BATCH>(A0, batch);
   if (A.n_mem == 0 || blockIdx.x >= A.n_hist_blocks) return;
@@ -157,7 +157,7 @@ __global__ void __launch_bounds__(1024) k_mem_binscan(TraceArgs A0, const TraceA
 // -------------------------------------------------------------- scatter
 template <bool VEC, bool BATCH>
 __global__ void __launch_bounds__(MEM_BLOCK) k_mem_scatter(TraceArgs A0, const TraceArgs *batch) {
-  __shared__ u32 cur[MAX_PARTS];
+  extern __shared__ u32 cur[];   // [P]
   const TraceArgs &A = trace_args<BATCH>(A0, batch);
   if (A.n_mem == 0 || blockIdx.x >= A.n_hist_blocks) return;
   const u32 P = 1u << A.pbits;
@@ -590,17 +590,32 @@ __global__ void __launch_bounds__(BK_BLOCK) k_mem_bucket(TraceArgs A0, const Tra
 namespace aiwc_kernels {
 
 
+template <typename K>
+static void allow_big_lds(K kernel) {
+  hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
+                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)(MAX_PARTS * 4));
+}
+
 hipError_t launch_mem(const TraceArgs &a, const BatchDims &d, hipStream_t s, StageMarks *pm) {
   if (!d.any_mem) return hipSuccess;
+  static bool attrs = false;
+  if (!attrs) {
+    allow_big_lds(k_mem_hist<true, true>); allow_big_lds(k_mem_hist<false, true>);
+    allow_big_lds(k_mem_hist<true, false>); allow_big_lds(k_mem_hist<false, false>);
+    allow_big_lds(k_mem_scatter<true, true>); allow_big_lds(k_mem_scatter<false, true>);
+    allow_big_lds(k_mem_scatter<true, false>); allow_big_lds(k_mem_scatter<false, false>);
+    attrs = true;
+  }
+  const size_t lds = (size_t)d.max_parts * 4;
   const dim3 gh((unsigned)d.max_hist_blocks, d.n), gc((unsigned)((d.max_parts + 255) / 256), d.n);
   const dim3 g1(1, d.n), gb((unsigned)(d.max_parts < 512 ? d.max_parts : 512), d.n);
   const TraceArgs *b = d.batch;
   if (b) {
-    if (d.vec) hipLaunchKernelGGL((k_mem_hist<true, true>), gh, dim3(MEM_BLOCK), 0, s, a, b);
-    else hipLaunchKernelGGL((k_mem_hist<false, true>), gh, dim3(MEM_BLOCK), 0, s, a, b);
+    if (d.vec) hipLaunchKernelGGL((k_mem_hist<true, true>), gh, dim3(MEM_BLOCK), lds, s, a, b);
+    else hipLaunchKernelGGL((k_mem_hist<false, true>), gh, dim3(MEM_BLOCK), lds, s, a, b);
   } else {
-    if (d.vec) hipLaunchKernelGGL((k_mem_hist<true, false>), gh, dim3(MEM_BLOCK), 0, s, a, b);
-    else hipLaunchKernelGGL((k_mem_hist<false, false>), gh, dim3(MEM_BLOCK), 0, s, a, b);
+    if (d.vec) hipLaunchKernelGGL((k_mem_hist<true, false>), gh, dim3(MEM_BLOCK), lds, s, a, b);
+    else hipLaunchKernelGGL((k_mem_hist<false, false>), gh, dim3(MEM_BLOCK), lds, s, a, b);
   }
   AIWC_MARK(pm, "k_mem_hist", s);
   if (b) {
@@ -612,11 +627,11 @@ hipError_t launch_mem(const TraceArgs &a, const BatchDims &d, hipStream_t s, Sta
   }
   AIWC_MARK(pm, "k_mem_scan", s);
   if (b) {
-    if (d.vec) hipLaunchKernelGGL((k_mem_scatter<true, true>), gh, dim3(MEM_BLOCK), 0, s, a, b);
-    else hipLaunchKernelGGL((k_mem_scatter<false, true>), gh, dim3(MEM_BLOCK), 0, s, a, b);
+    if (d.vec) hipLaunchKernelGGL((k_mem_scatter<true, true>), gh, dim3(MEM_BLOCK), lds, s, a, b);
+    else hipLaunchKernelGGL((k_mem_scatter<false, true>), gh, dim3(MEM_BLOCK), lds, s, a, b);
   } else {
-    if (d.vec) hipLaunchKernelGGL((k_mem_scatter<true, false>), gh, dim3(MEM_BLOCK), 0, s, a, b);
-    else hipLaunchKernelGGL((k_mem_scatter<false, false>), gh, dim3(MEM_BLOCK), 0, s, a, b);
+    if (d.vec) hipLaunchKernelGGL((k_mem_scatter<true, false>), gh, dim3(MEM_BLOCK), lds, s, a, b);
+    else hipLaunchKernelGGL((k_mem_scatter<false, false>), gh, dim3(MEM_BLOCK), lds, s, a, b);
   }
   AIWC_MARK(pm, "k_mem_scatter", s);
   if (b) hipLaunchKernelGGL(k_mem_bucket<true>, gb, dim3(BK_BLOCK), 0, s, a, b);

@@ -657,8 +657,9 @@ extern "C" aiwc_status aiwc_sizer_load(aiwc_ctx *ctx, const char *path) {
 }
 
 // ------------------------------------------------------------ sizing policy
-static u32 pbits_for_distinct(double distinct) {
-  double want = std::ceil(std::max(1.0, distinct) / 4096.0);
+// Partitions so that one holds about 1024 pages (1 KiB address blocks).
+static u32 pbits_for_pages(double pages) {
+  double want = std::ceil(std::max(1.0, pages) / 1024.0);
   u32 b = 0;
   while ((double)(1ull << b) < want) ++b;
   return std::min<u32>(15, std::max<u32>(4, b));
@@ -696,15 +697,17 @@ aiwc_status sizer_plan_pbits(aiwc_ctx *ctx, const aiwc_trace *const *traces, siz
     const double nmem = (double)traces[i]->d.n_mem;
     const double npref = std::exp2((double)f[34]) - 1.0;
     const double scale = npref > 0 ? nmem / npref : 1.0;
-    // local space: prefix distinct extrapolated linearly (an upper estimate)
-    const double loc = std::min(nmem, (std::exp2((double)f[19]) - 1.0) * scale);
+    // pages (distinct at skip 10).  Local space: the prefix's local pages
+    // extrapolated linearly (an upper estimate); global space: the network's
+    // prediction plus the margin, or the prefix extrapolated linearly.
+    const double loc = std::min(nmem, (std::exp2((double)f[29]) - 1.0) * scale);
     double glob;
     if (mode == AIWC_SIZING_LEARNED)
-      glob = std::exp2((double)hp[i * NT] + ctx->sizer->margin) - 1.0;
+      glob = std::exp2((double)hp[i * NT + 10] + ctx->sizer->margin) - 1.0;
     else
-      glob = (std::exp2((double)f[8]) - 1.0) * scale;   // prefix extrapolation
+      glob = (std::exp2((double)f[18]) - 1.0) * scale;
     glob = std::min(glob, nmem);
-    pbits[i] = pbits_for_distinct(glob + loc);
+    pbits[i] = pbits_for_pages(glob + loc);
   }
   return AIWC_OK;
 }
