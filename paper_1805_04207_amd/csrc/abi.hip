@@ -65,8 +65,8 @@ void plan_trace(const aiwc_trace *t, u32 pbits, TracePlan &p, const Tune *tune) 
   if (P <= 4096) nbmax *= 4; else if (P <= 8192) nbmax *= 2;
   nb = std::max<u64>(1, std::min<u64>(nb, nbmax));
   p.n_hist_blocks = (u32)nb;
-  p.hist_chunk = align_up((d.n_mem + nb - 1) / nb, 4);
-  if (p.hist_chunk == 0) p.hist_chunk = 4;
+  p.hist_chunk = align_up((d.n_mem + nb - 1) / nb, 8);
+  if (p.hist_chunk == 0) p.hist_chunk = 8;
   u64 r = (u64)std::sqrt((double)(2 * d.n_mem)) + 2;
   p.sp_cap = (u32)std::max<u64>(64, 1ull << ceil_log2(2 * r));
   // branches
@@ -190,7 +190,7 @@ void add_dims(const aiwc_trace *t, const TracePlan &p, const TraceArgs &a, Batch
     d.any_mem = true;
     d.max_hist_blocks = std::max<u64>(d.max_hist_blocks, p.n_hist_blocks);
     d.max_parts = std::max<u64>(d.max_parts, 1ull << p.pbits);
-    if ((uintptr_t)a.addr % 16 || (uintptr_t)a.mem_kind % 4) d.vec = false;
+    if ((uintptr_t)a.addr % 16 || (uintptr_t)a.mem_kind % 8) d.vec = false;
   }
   if (D.n_branch) {
     d.any_branch = true;

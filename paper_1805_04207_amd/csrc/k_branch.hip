@@ -65,13 +65,18 @@ __global__ void __launch_bounds__(BR_BLOCK) k_br_upsweep(TraceArgs A0, const Tra
   const u32 shift = 1u + 8u * pass;
   u32 *cnt = A.br_cnt;
   h[threadIdx.x] = 0;
-  __syncthreads();
   const u64 t = blockIdx.x;
   const u64 base = t * BR_TILE;
+  u32 vals[BR_ROUNDS];
+#pragma unroll
   for (int r = 0; r < BR_ROUNDS; ++r) {
     const u64 i = base + (u64)r * BR_BLOCK + threadIdx.x;
-    if (i < n) atomicAdd(&h[(in[i] >> shift) & 255u], 1u);
+    vals[r] = i < n ? in[i] : ~0u;
   }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < BR_ROUNDS; ++r)
+    if (vals[r] != ~0u) atomicAdd(&h[(vals[r] >> shift) & 255u], 1u);
   __syncthreads();
   cnt[(u64)threadIdx.x * n_tiles + t] = h[threadIdx.x];
 }
@@ -95,13 +100,20 @@ __global__ void __launch_bounds__(BR_BLOCK) k_br_downsweep(TraceArgs A0, const T
   running[tid] = 0;
   const u64 base = t * BR_TILE;
   const u64 lt = (1ull << lane) - 1ull;
+  u32 vals[BR_ROUNDS];
+#pragma unroll
+  for (int r = 0; r < BR_ROUNDS; ++r) {
+    const u64 i = base + (u64)r * BR_BLOCK + tid;
+    vals[r] = i < n ? in[i] : 0u;
+  }
+#pragma unroll
   for (int r = 0; r < BR_ROUNDS; ++r) {
 #pragma unroll
     for (int w = 0; w < BR_BLOCK / AIWC_WAVE; ++w) wcnt[w][tid] = 0;
     __syncthreads();
     const u64 i = base + (u64)r * BR_BLOCK + tid;
     const bool valid = i < n;
-    const u32 v = valid ? in[i] : 0u;
+    const u32 v = vals[r];
     const u32 d = (v >> shift) & 255u;
     u64 peers = __ballot(valid);
 #pragma unroll
@@ -317,25 +329,36 @@ __global__ void __launch_bounds__(WIN_BLOCK) k_br_windows(TraceArgs A0, const Tr
       __syncthreads();
       if (tid == 0) S.sp_top -= 1;
       bool stop = false;
-      for (u64 cb = r0 + (u64)wave * AIWC_WAVE; cb < r1; cb += (u64)WIN_BLOCK) {
-        const u64 i = cb + lane;
-        const bool valid = i < r1;
-        const u32 v = valid ? sorted[i] : 0u;
-        const u64 ip = i - AIWC_WAVE;                 // same lane, previous chunk
-        const u32 vp = (cb >= AIWC_WAVE) ? sorted[ip] : 0u;
-        const u64 B = __ballot(valid && (v & 1u));
-        const u64 Bp = __ballot((cb >= AIWC_WAVE) && (vp & 1u));
-        if (!valid || stop) continue;
-        const u32 s = v >> 1;
-        if (i - A.seg_start[s] < m) continue;
-        const u32 sh = 64u + (u32)lane - m;           // in [32, 127]
-        u64 E;
-        if (sh >= 64) E = B >> (sh - 64);
-        else E = (Bp >> sh) | (B << (64 - sh));
-        E &= hmask;
-        const u64 key = ((u64)s << m) | E;
-        if (M > 1 && (((u32)((key * 0x9E3779B97F4A7C15ull) >> 40)) & (M - 1u)) != C) continue;
-        if (!win_insert(S, key, v & 1u)) stop = true;
+      for (u64 cb0 = r0 + (u64)wave * AIWC_WAVE; cb0 < r1; cb0 += 4ull * WIN_BLOCK) {
+        // four chunks' loads in flight before any is used
+        u32 pv[4], pp[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const u64 cb = cb0 + (u64)q * WIN_BLOCK, i = cb + lane;
+          pv[q] = (i < r1) ? sorted[i] : 0u;
+          pp[q] = (cb >= AIWC_WAVE && cb < r1) ? sorted[i - AIWC_WAVE] : 0u;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const u64 cb = cb0 + (u64)q * WIN_BLOCK;
+          if (cb >= r1) break;
+          const u64 i = cb + lane;
+          const bool valid = i < r1;
+          const u32 v = pv[q], vp = pp[q];
+          const u64 B = __ballot(valid && (v & 1u));
+          const u64 Bp = __ballot((cb >= AIWC_WAVE) && (vp & 1u));
+          if (!valid || stop) continue;
+          const u32 s = v >> 1;
+          if (i - A.seg_start[s] < m) continue;
+          const u32 sh = 64u + (u32)lane - m;           // in [32, 127]
+          u64 E;
+          if (sh >= 64) E = B >> (sh - 64);
+          else E = (Bp >> sh) | (B << (64 - sh));
+          E &= hmask;
+          const u64 key = ((u64)s << m) | E;
+          if (M > 1 && (((u32)((key * 0x9E3779B97F4A7C15ull) >> 40)) & (M - 1u)) != C) continue;
+          if (!win_insert(S, key, v & 1u)) stop = true;
+        }
       }
       __syncthreads();
       const u32 D = S.live_n < WT_C ? S.live_n : WT_C;

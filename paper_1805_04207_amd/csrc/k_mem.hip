@@ -61,27 +61,28 @@ __global__ void __launch_bounds__(MEM_BLOCK) k_mem_hist(TraceArgs A0, const Trac
   const u64 c0 = (u64)blockIdx.x * A.hist_chunk;
   const u64 c1 = (c0 + A.hist_chunk < A.n_mem) ? c0 + A.hist_chunk : A.n_mem;
   u32 cnt[4] = {0, 0, 0, 0};
-  for (u64 i = c0 + 4ull * threadIdx.x; i < c1; i += 4ull * MEM_BLOCK) {
-    u64 a[4];
-    u32 kk;
-    int n = 4;
-    if (VEC && i + 4 <= c1) {
+  for (u64 i = c0 + 8ull * threadIdx.x; i < c1; i += 8ull * MEM_BLOCK) {
+    u64 a[8];
+    uint2 kk2;
+    int n = 8;
+    if (VEC && i + 8 <= c1) {
       const ulonglong2 *pa = reinterpret_cast<const ulonglong2 *>(A.addr + i);
-      ulonglong2 x = pa[0], y = pa[1];
-      a[0] = x.x; a[1] = x.y; a[2] = y.x; a[3] = y.y;
-      kk = *reinterpret_cast<const u32 *>(A.mem_kind + i);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) { const ulonglong2 x = pa[q]; a[2 * q] = x.x; a[2 * q + 1] = x.y; }
+      kk2 = *reinterpret_cast<const uint2 *>(A.mem_kind + i);
     } else {
-      n = (int)((c1 - i) < 4 ? (c1 - i) : 4);
-      kk = 0;
-      for (int j = 0; j < 4; ++j) {
+      n = (int)((c1 - i) < 8 ? (c1 - i) : 8);
+      kk2 = make_uint2(0, 0);
+      for (int j = 0; j < 8; ++j) {
         a[j] = j < n ? A.addr[i + j] : 0;
-        kk |= (u32)(j < n ? A.mem_kind[i + j] : 0) << (8 * j);
+        const u32 kb = j < n ? A.mem_kind[i + j] : 0;
+        if (j < 4) kk2.x |= kb << (8 * j); else kk2.y |= kb << (8 * (j - 4));
       }
     }
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < 8; ++j) {
       if (j < n) {
-        const uint8_t k = (uint8_t)(kk >> (8 * j));
+        const uint8_t k = (uint8_t)((j < 4 ? kk2.x : kk2.y) >> (8 * (j & 3)));
         u32 bin;
         make_record(a[j], k, A.pbits, bin);
         atomicAdd(&h[bin], 1u);
@@ -166,28 +167,30 @@ __global__ void __launch_bounds__(MEM_BLOCK) k_mem_scatter(TraceArgs A0, const T
   __syncthreads();
   const u64 c0 = (u64)blockIdx.x * A.hist_chunk;
   const u64 c1 = (c0 + A.hist_chunk < A.n_mem) ? c0 + A.hist_chunk : A.n_mem;
-  for (u64 i = c0 + 4ull * threadIdx.x; i < c1; i += 4ull * MEM_BLOCK) {
-    u64 a[4];
-    u32 kk;
-    int n = 4;
-    if (VEC && i + 4 <= c1) {
+  for (u64 i = c0 + 8ull * threadIdx.x; i < c1; i += 8ull * MEM_BLOCK) {
+    u64 a[8];
+    uint2 kk2;
+    int n = 8;
+    if (VEC && i + 8 <= c1) {
       const ulonglong2 *pa = reinterpret_cast<const ulonglong2 *>(A.addr + i);
-      ulonglong2 x = pa[0], y = pa[1];
-      a[0] = x.x; a[1] = x.y; a[2] = y.x; a[3] = y.y;
-      kk = *reinterpret_cast<const u32 *>(A.mem_kind + i);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) { const ulonglong2 x = pa[q]; a[2 * q] = x.x; a[2 * q + 1] = x.y; }
+      kk2 = *reinterpret_cast<const uint2 *>(A.mem_kind + i);
     } else {
-      n = (int)((c1 - i) < 4 ? (c1 - i) : 4);
-      kk = 0;
-      for (int j = 0; j < 4; ++j) {
+      n = (int)((c1 - i) < 8 ? (c1 - i) : 8);
+      kk2 = make_uint2(0, 0);
+      for (int j = 0; j < 8; ++j) {
         a[j] = j < n ? A.addr[i + j] : 0;
-        kk |= (u32)(j < n ? A.mem_kind[i + j] : 0) << (8 * j);
+        const u32 kb = j < n ? A.mem_kind[i + j] : 0;
+        if (j < 4) kk2.x |= kb << (8 * j); else kk2.y |= kb << (8 * (j - 4));
       }
     }
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < 8; ++j) {
       if (j < n) {
         u32 bin;
-        const u64 rec = make_record(a[j], (uint8_t)(kk >> (8 * j)), A.pbits, bin);
+        const u64 rec = make_record(a[j], (uint8_t)((j < 4 ? kk2.x : kk2.y) >> (8 * (j & 3))),
+                                    A.pbits, bin);
         const u32 pos = atomicAdd(&cur[bin], 1u);
         A.part_rec[pos] = rec;
       }
@@ -217,6 +220,9 @@ constexpr u32 PT_CAP = 1536;
 constexpr int BK_BLOCK = 512;                    // 8 waves: 256 VGPRs per lane
 constexpr int BK_WAVES = BK_BLOCK / AIWC_WAVE;    // 8
 constexpr u32 HEAVY = 8192;
+constexpr u32 SMALL = 32;                         // pages up to this many records are
+                                                  // sorted in registers, 2..many per wave
+constexpr int UNROLL = 8;                         // records in flight per thread
 constexpr u32 NSPEC = 8;                          // level-0 counts 1..8 kept per lane
 
 struct BucketShared {
@@ -233,8 +239,9 @@ struct BucketShared {
   u64 dist[2][AIWC_NSKIP], elo[2][AIWC_NSKIP], ehi[2][AIWC_NSKIP];
   u64 ur[2], uw[2];
   u64 redos;
+  uint16_t big[PT_CAP];            // compact indices of pages with > SMALL records
   u32 wsum[BK_WAVES];
-  u32 npages, overflow, work, next_page, sp_top;
+  u32 npages, overflow, work, next_page, next_win, nbig, sp_top;
   u32 stack_m[64], stack_c[64];
 };
 
@@ -375,6 +382,67 @@ __device__ __forceinline__ void page_levels(LaneAcc &L, BucketShared &S, SpecRef
   }
 }
 
+
+// Bitonic sort of one u32 per lane across the wavefront (ascending).
+__device__ __forceinline__ u32 wave_sort(u32 v) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int size = 2; size <= AIWC_WAVE; size <<= 1) {
+#pragma unroll
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      const u32 o = __shfl_xor(v, stride, 64);
+      const bool up = (lane & size) == 0;
+      const bool low = (lane & stride) == 0;
+      v = (low == up) ? (v < o ? v : o) : (v > o ? v : o);
+    }
+  }
+  return v;
+}
+
+// The records of several small pages (<= SMALL records each, one record per
+// lane, key = page << 11 | offset << 1 | write; invalid lanes hold ~0u):
+// sort them, then every run of equal key >> (1 + k) is one node of level k.
+__device__ __forceinline__ void small_pages_levels(LaneAcc &L, BucketShared &S, SpecRef G,
+                                                   u32 key) {
+  const int lane = lane_id();
+  const u32 v = wave_sort(key);
+  const u32 nv = (u32)__builtin_popcountll(__ballot(v != ~0u));
+  const u64 after = (lane == 63) ? 0ull : (~0ull << (lane + 1));
+#pragma unroll
+  for (int k = 0; k < AIWC_NSKIP; ++k) {
+    const u32 g = v >> (1 + k);
+    const u32 gp = __shfl_up(g, 1, 64);
+    const bool head = (u32)lane < nv && (lane == 0 || g != gp);
+    const u64 B = __ballot(head);
+    if (head) {
+      const u64 nx = B & after;
+      const u32 end = nx ? (u32)__builtin_ctzll(nx) : nv;
+      const u32 c = end - (u32)lane;            // <= 64 < 256: table term
+      const u64 tl = S.tlo[L.space][c], th = S.thi[L.space][c];
+      const u64 nl = L.lo[k] + tl;
+      L.hi[k] += th + (nl < L.lo[k] ? 1ull : 0ull);
+      L.lo[k] = nl;
+      L.d[k] += 1;
+      if (k == 0) {
+        if (c <= NSPEC) {
+#pragma unroll
+          for (int j = 0; j < (int)NSPEC; ++j) L.spec[j] += (c == (u32)(j + 1));
+        } else {
+          spec_cache_add(S, G, (u32)L.space, c, 1ull);
+        }
+        L.ur += (v & 1u) == 0;                  // reads sort before writes
+      }
+    }
+    if (k == 0) {
+      // last element of each level-0 run carries the write flag of the run
+      const u64 nx = B & after;
+      const u32 end = nx ? (u32)__builtin_ctzll(nx) : nv;
+      const u32 lastv = __shfl(v, (int)(end > 0 ? end - 1 : 0), 64);
+      if (head) L.uw += lastv & 1u;
+    }
+  }
+}
+
 __device__ __forceinline__ u32 pt_find(const BucketShared &S, u64 pk) {
   u32 slot = hash_slot(pk, PT_SLOTS);
   while (S.pkey[slot] != pk) slot = (slot + 1 == PT_SLOTS) ? 0 : slot + 1;
@@ -427,27 +495,37 @@ __global__ void __launch_bounds__(BK_BLOCK) k_mem_bucket(TraceArgs A0, const Tra
       const u32 M = S.stack_m[S.sp_top - 1], C = S.stack_c[S.sp_top - 1];
       __syncthreads();
       if (tid == 0) S.sp_top -= 1;
-      // ---- 1. page pass
-      for (u32 i = tid; i < n; i += BK_BLOCK) {
-        const u64 pk = A.part_rec[base + i] >> 11;
-        if (((u32)pk & (M - 1u)) != C) continue;
-        u32 slot = hash_slot(pk, PT_SLOTS);
-        while (true) {
-          u64 w = S.pkey[slot];
-          if (w == EMPTY) {
-            if (S.npages >= PT_CAP) { S.overflow = 1; break; }
-            u64 old = atomicCAS(&S.pkey[slot], EMPTY, pk);
-            if (old == EMPTY) {
-              const u32 ci = atomicAdd(&S.npages, 1u);
-              if (ci < PT_CAP) { S.pidx[slot] = (uint16_t)ci; S.pslot[ci] = (uint16_t)slot; }
-              else S.overflow = 1;
-              w = pk;
-            } else {
-              w = old;
+      // ---- 1. page pass (UNROLL records in flight per thread)
+      for (u32 i0 = tid; i0 < n; i0 += BK_BLOCK * UNROLL) {
+        u64 rv[UNROLL];
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+          const u32 i = i0 + (u32)u * BK_BLOCK;
+          rv[u] = i < n ? A.part_rec[base + i] : EMPTY;
+        }
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+          if (rv[u] == EMPTY) continue;
+          const u64 pk = rv[u] >> 11;
+          if (((u32)pk & (M - 1u)) != C) continue;
+          u32 slot = hash_slot(pk, PT_SLOTS);
+          while (true) {
+            u64 w = S.pkey[slot];
+            if (w == EMPTY) {
+              if (S.npages >= PT_CAP) { S.overflow = 1; break; }
+              u64 old = atomicCAS(&S.pkey[slot], EMPTY, pk);
+              if (old == EMPTY) {
+                const u32 ci = atomicAdd(&S.npages, 1u);
+                if (ci < PT_CAP) { S.pidx[slot] = (uint16_t)ci; S.pslot[ci] = (uint16_t)slot; }
+                else S.overflow = 1;
+                w = pk;
+              } else {
+                w = old;
+              }
             }
+            if (w == pk) { atomicAdd(&S.pcnt[slot], 1u); break; }
+            slot = (slot + 1 == PT_SLOTS) ? 0 : slot + 1;
           }
-          if (w == pk) { atomicAdd(&S.pcnt[slot], 1u); break; }
-          slot = (slot + 1 == PT_SLOTS) ? 0 : slot + 1;
         }
       }
       __syncthreads();
@@ -492,13 +570,26 @@ __global__ void __launch_bounds__(BK_BLOCK) k_mem_bucket(TraceArgs A0, const Tra
         if (tid == 0) S.poff[b0 + BK_BLOCK < np ? b0 + BK_BLOCK : np] = tot;
         __syncthreads();
       }
-      for (u32 i = tid; i < n; i += BK_BLOCK) {
-        const u64 rec = A.part_rec[base + i];
-        const u64 pk = rec >> 11;
-        if (((u32)pk & (M - 1u)) != C) continue;
-        const u32 ci = S.pidx[pt_find(S, pk)];
-        const u32 pos = S.poff[ci] + atomicAdd(&S.pcur[ci], 1u);
-        staging[base + pos] = (ci << 11) | (u32)(rec & 2047ull);
+      if (tid == 0) { S.nbig = 0; S.next_page = 0; S.next_win = 0; }
+      __syncthreads();
+      for (u32 j = tid; j < np; j += BK_BLOCK)
+        if (S.poff[j + 1] - S.poff[j] > SMALL) S.big[atomicAdd(&S.nbig, 1u)] = (uint16_t)j;
+      for (u32 i0 = tid; i0 < n; i0 += BK_BLOCK * UNROLL) {
+        u64 rv[UNROLL];
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+          const u32 i = i0 + (u32)u * BK_BLOCK;
+          rv[u] = i < n ? A.part_rec[base + i] : EMPTY;
+        }
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+          if (rv[u] == EMPTY) continue;
+          const u64 pk = rv[u] >> 11;
+          if (((u32)pk & (M - 1u)) != C) continue;
+          const u32 ci = S.pidx[pt_find(S, pk)];
+          const u32 pos = S.poff[ci] + atomicAdd(&S.pcur[ci], 1u);
+          staging[base + pos] = (ci << 11) | (u32)(rv[u] & 2047ull);
+        }
       }
       __threadfence_block();
       __syncthreads();
@@ -523,16 +614,16 @@ __global__ void __launch_bounds__(BK_BLOCK) k_mem_bucket(TraceArgs A0, const Tra
         }
         __syncthreads();
       }
-      // ---- 3b. other pages: one wavefront each
-      if (tid == 0) S.next_page = 0;
-      __syncthreads();
+      // ---- 3b. big pages (> SMALL records): one wavefront each, dense counters
       u32 *dn = S.dense[wave];
       u32 *rb = S.rbits[wave], *wb = S.wbits[wave];
+      const u32 nbig = S.nbig;
       while (true) {
-        u32 ci = 0;
-        if (lane == 0) ci = atomicAdd(&S.next_page, 1u);
-        ci = __shfl(ci, 0, 64);
-        if (ci >= np) break;
+        u32 bi = 0;
+        if (lane == 0) bi = atomicAdd(&S.next_page, 1u);
+        bi = __shfl(bi, 0, 64);
+        if (bi >= nbig) break;
+        const u32 ci = S.big[bi];
         const u32 o0 = S.poff[ci], o1 = S.poff[ci + 1];
         if (o1 - o0 > HEAVY) continue;
         uint4 *z = reinterpret_cast<uint4 *>(dn + 16 * lane);
@@ -540,11 +631,20 @@ __global__ void __launch_bounds__(BK_BLOCK) k_mem_bucket(TraceArgs A0, const Tra
         for (int q = 0; q < 4; ++q) z[q] = make_uint4(0, 0, 0, 0);
         if (lane < 32) { rb[lane] = 0; wb[lane] = 0; }
         __builtin_amdgcn_wave_barrier();
-        for (u32 i = o0 + lane; i < o1; i += AIWC_WAVE) {
-          const u32 v = staging[base + i];
-          const u32 off = (v >> 1) & 1023u;
-          atomicAdd(&dn[off], 1u);
-          atomicOr((v & 1u) ? &wb[off >> 5] : &rb[off >> 5], 1u << (off & 31u));
+        for (u32 i0 = o0 + lane; i0 < o1; i0 += AIWC_WAVE * 4) {
+          u32 vv[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const u32 i = i0 + (u32)u * AIWC_WAVE;
+            vv[u] = i < o1 ? staging[base + i] : ~0u;
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            if (vv[u] == ~0u) continue;
+            const u32 off = (vv[u] >> 1) & 1023u;
+            atomicAdd(&dn[off], 1u);
+            atomicOr((vv[u] & 1u) ? &wb[off >> 5] : &rb[off >> 5], 1u << (off & 31u));
+          }
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -552,6 +652,33 @@ __global__ void __launch_bounds__(BK_BLOCK) k_mem_bucket(TraceArgs A0, const Tra
         if (sp != L.space) { lacc_flush(L, S, G); L.space = sp; }
         page_levels(L, S, G, dn, rb, wb, sp ? N1 : N0);
         __builtin_amdgcn_wave_barrier();
+      }
+      // ---- 3c. small pages, in windows of 32 staging positions: the pages
+      // starting in a window (<= SMALL records each) fit one wavefront
+      const u32 R = S.poff[np];
+      const u32 nwin = (R + SMALL - 1) / SMALL;
+      while (true) {
+        u32 w = 0;
+        if (lane == 0) w = atomicAdd(&S.next_win, 1u);
+        w = __shfl(w, 0, 64);
+        if (w >= nwin) break;
+        const u32 lo = w * SMALL, i = lo + (u32)lane;
+        const u32 v = i < R ? staging[base + i] : ~0u;
+        const u32 ci = v >> 11;
+        bool ok = i < R;
+        u32 sp = 0;
+        if (ok) {
+          const u32 p0 = S.poff[ci];
+          ok = (S.poff[ci + 1] - p0) <= SMALL && p0 >= lo && p0 < lo + SMALL;
+          sp = (u32)((S.pkey[S.pslot[ci]] >> sbit) & 1ull);
+        }
+        const u64 has1 = __ballot(ok && sp == 1u), has0 = __ballot(ok && sp == 0u);
+        for (u32 s2 = 0; s2 < 2; ++s2) {
+          if (!(s2 ? has1 : has0)) continue;
+          if ((int)s2 != L.space) { lacc_flush(L, S, G); L.space = (int)s2; }
+          const u32 key = (ok && sp == s2) ? ((ci << 11) | (v & 2047u)) : ~0u;
+          small_pages_levels(L, S, G, key);
+        }
       }
       __syncthreads();
       // ---- release the page table for the next round / partition

@@ -103,11 +103,24 @@ __global__ void __launch_bounds__(OPS_BLOCK) k_ops(TraceArgs A0, const TraceArgs
 
     // 512-event chunks: lane l holds events [cb + 8l, cb + 8l + 8) (one
     // 16-byte load when aligned), barrier positions as per-lane bit masks.
-    for (u64 cb = e0 & ~7ull; cb < e1; cb += 8 * AIWC_WAVE) {
+    for (u64 cb0 = e0 & ~7ull; cb0 < e1; cb0 += 4 * 8 * AIWC_WAVE) {
+      // four chunks' loads in flight before any is used
+      uint4 pre[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const u64 i0 = cb0 + (u64)q * 8 * AIWC_WAVE + 8ull * lane;
+        pre[q] = (VEC && i0 >= e0 && i0 + 8 <= e1)
+                     ? *reinterpret_cast<const uint4 *>(A.opcode + i0)
+                     : make_uint4(0, 0, 0, 0);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+      const u64 cb = cb0 + (u64)q * 8 * AIWC_WAVE;
+      if (cb >= e1) break;
       const u64 i0 = cb + 8ull * lane;
       u32 ids[8];
       if (VEC && i0 >= e0 && i0 + 8 <= e1) {
-        const uint4 v = *reinterpret_cast<const uint4 *>(A.opcode + i0);
+        const uint4 v = pre[q];
         ids[0] = v.x & 0xFFFFu; ids[1] = v.x >> 16; ids[2] = v.y & 0xFFFFu; ids[3] = v.y >> 16;
         ids[4] = v.z & 0xFFFFu; ids[5] = v.z >> 16; ids[6] = v.w & 0xFFFFu; ids[7] = v.w >> 16;
       } else {
@@ -174,6 +187,7 @@ __global__ void __launch_bounds__(OPS_BLOCK) k_ops(TraceArgs A0, const TraceArgs
         lm &= lm - 1;
         if (lane == bl) bm = lm;
         if (lm == 0) B &= B - 1;
+      }
       }
     }
     // work-items left open at the end of the task (trailing empty ones)

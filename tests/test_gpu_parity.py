@@ -90,11 +90,12 @@ def test_many_opcode_ids_global_path():
 
 
 def test_partition_overflow_redo(monkeypatch):
-    # 4 partitions for ~60K distinct addresses: every partition overflows the
-    # on-chip table and is split and redone; results must stay exact
+    # 16 partitions for ~150K distinct pages: every partition holds more pages
+    # than one round of the on-chip page table and is split and redone;
+    # results must stay exact
     monkeypatch.setenv("AIWC_FORCE_PARTITION_LOG2", "4")
     rng = np.random.default_rng(11)
-    a = rng.integers(0, 1 << 22, size=200_000, dtype=np.uint64) * 4
+    a = rng.integers(0, 1 << 28, size=200_000, dtype=np.uint64) * 4
     got = check(mem_trace(a, (rng.random(a.size) < 0.4).astype(np.uint8)))
     assert got["overflow_redos"] > 0
 
