@@ -205,43 +205,52 @@ __global__ void __launch_bounds__(MEM_BLOCK) k_mem_scatter(TraceArgs A0, const T
 //                   More than PT_CAP pages: the partition is split into rounds
 //                   by page-hash bits (never by record, so every a >> k bucket
 //                   stays whole) and redone.
-//  2. page sort   : records are regrouped page by page into a staging array
-//                   (u32: page index, byte offset, write flag).
-//  3. pages       : a wavefront takes a page, counts its records in a dense
-//                   array of 1024 byte-offset counters (LDS), then evaluates
-//                   every skip level at once: levels 0..4 from the 16
-//                   counters a lane holds, levels 5..10 by cross-lane sums.
-//                   Each non-empty node adds 1 to distinct_k and its entropy
-//                   term c*log2(N/c) (exact 2^-64 fixed point) to level k.
-//                   Pages with more than HEAVY records are counted by the
-//                   whole block first.
+//  2. regroup     : records are regrouped page by page into a staging array
+//                   (u32: compact page index, byte offset, write flag), small
+//                   pages (<= SMALL records) of space 0, then of space 1, then
+//                   every other page.
+//  3. levels      : the node of level k holding a record is the set of records
+//                   of its page whose byte offsets agree on bits k..9.
+//       pages <= MEDIUM records, one record per lane: that set is the page's
+//                   lane mask AND-ed with one ballot per offset bit; its lowest
+//                   lane owns the node and adds its count.  Small pages are
+//                   packed: a wavefront takes the pages that start in a window
+//                   of SMALL staging positions (they end within 2 * SMALL).
+//       larger pages: the wavefront counts the page's byte offsets in 1024
+//                   dense LDS counters, then reduces them level by level.
+//       pages > HEAVY records are counted by the whole block.
+//     Each node adds 1 to distinct_k and its entropy term c*log2(N/c) (exact
+//     2^-64 fixed point) to level k; nodes with c = 1 are only counted and
+//     multiplied by log2(N) when the accumulators are flushed.  Level-0 counts
+//     below SPEC_LDS go to an LDS spectrum histogram.
 constexpr u32 PT_SLOTS = 2048;
 constexpr u32 PT_CAP = 1536;
 constexpr int BK_BLOCK = 512;                    // 8 waves: 256 VGPRs per lane
 constexpr int BK_WAVES = BK_BLOCK / AIWC_WAVE;    // 8
 constexpr u32 HEAVY = 8192;
-constexpr u32 SMALL = 32;                         // pages up to this many records are
-                                                  // sorted in registers, 2..many per wave
+constexpr u32 SMALL = 32;
+constexpr u32 MEDIUM = 64;
 constexpr int UNROLL = 8;                         // records in flight per thread
-constexpr u32 NSPEC = 8;                          // level-0 counts 1..8 kept per lane
+constexpr u32 SPEC_LDS = 256;
 
 struct BucketShared {
   u64 pkey[PT_SLOTS];              // page key, EMPTY if free
   u32 pcnt[PT_SLOTS];              // records of the page
   uint16_t pidx[PT_SLOTS];         // compact index of the page
   uint16_t pslot[PT_CAP];          // slot of compact index
-  u32 poff[PT_CAP + 1];            // staging offset of compact index
-  u32 pcur[PT_CAP];
+  u32 psz[PT_CAP];                 // records of compact index
+  u32 pend[PT_CAP];                // staging cursor, then end, of compact index
   u32 dense[BK_WAVES][1024];       // per-wave byte-offset counters
   u32 rbits[BK_WAVES][32], wbits[BK_WAVES][32];
-  u64 tlo[2][256], thi[2][256];    // entropy term table for c < 256
+  ulonglong2 term[2][256];         // c*log2(N_s/c) for c < 256, (lo, hi)
+  u32 spec[2][SPEC_LDS];           // level-0 nodes of count c, 2 <= c < SPEC_LDS
   u64 spf[2][SPEC_SLOTS], spm[2][SPEC_SLOTS];
   u64 dist[2][AIWC_NSKIP], elo[2][AIWC_NSKIP], ehi[2][AIWC_NSKIP];
   u64 ur[2], uw[2];
   u64 redos;
-  uint16_t big[PT_CAP];            // compact indices of pages with > SMALL records
-  u32 wsum[BK_WAVES];
-  u32 npages, overflow, work, next_page, next_win, nbig, sp_top;
+  uint16_t big[PT_CAP];            // pages > SMALL: space 0 from the front, 1 from the back
+  u32 ctot[3], ccur[3];
+  u32 npages, overflow, work, nbig0, nbig1, nheavy, next_item, sp_top;
   u32 stack_m[64], stack_c[64];
 };
 
@@ -282,38 +291,42 @@ __device__ __noinline__ void spec_cache_add(BucketShared &S, SpecRef G, u32 s, u
 // Per-lane accumulators of one address space (flushed when the space changes).
 struct LaneAcc {
   u64 lo[AIWC_NSKIP], hi[AIWC_NSKIP];
-  u32 d[AIWC_NSKIP];
-  u32 spec[NSPEC];
+  u32 d[AIWC_NSKIP];               // nodes
+  u32 ones[AIWC_NSKIP];            // nodes of count 1 (term log2 N, added at flush)
   u32 ur, uw;
   int space;
 };
 
 __device__ __forceinline__ void lacc_clear(LaneAcc &L, int space) {
 #pragma unroll
-  for (int k = 0; k < AIWC_NSKIP; ++k) { L.lo[k] = 0; L.hi[k] = 0; L.d[k] = 0; }
-#pragma unroll
-  for (int j = 0; j < (int)NSPEC; ++j) L.spec[j] = 0;
+  for (int k = 0; k < AIWC_NSKIP; ++k) { L.lo[k] = 0; L.hi[k] = 0; L.d[k] = 0; L.ones[k] = 0; }
   L.ur = L.uw = 0;
   L.space = space;
 }
 
-__device__ __forceinline__ void lacc_flush(LaneAcc &L, BucketShared &S, SpecRef G) {
+__device__ __forceinline__ void add128(u64 &lo, u64 &hi, u64 tl, u64 th) {
+  const u64 nl = lo + tl;
+  hi += th + (nl < lo ? 1ull : 0ull);
+  lo = nl;
+}
+
+__device__ __forceinline__ void lacc_flush(LaneAcc &L, BucketShared &S) {
   const int s = L.space;
   const int lane = lane_id();
+  const ulonglong2 t1 = S.term[s][1];
 #pragma unroll
   for (int k = 0; k < AIWC_NSKIP; ++k) {
     u64 lo = L.lo[k], hi = L.hi[k];
     wave_sum_u128(lo, hi);
     const u64 d = wave_sum_u64(L.d[k]);
+    const u64 n1 = wave_sum_u64(L.ones[k]);
     if (lane == 0) {
+      // + n1 * log2(N): 128-bit product of the fixed-point term and the count
+      add128(lo, hi, t1.x * n1, __umul64hi(t1.x, n1) + t1.y * n1);
       atomic_add_u128(&S.elo[s][k], &S.ehi[s][k], lo, hi);
       if (d) atomicAdd(&S.dist[s][k], d);
+      if (k == 0 && n1) atomicAdd(&S.spec[s][1], (u32)n1);
     }
-  }
-#pragma unroll
-  for (int j = 0; j < (int)NSPEC; ++j) {
-    const u64 m = wave_sum_u64(L.spec[j]);
-    if (lane == 0 && m) spec_cache_add(S, G, (u32)s, (u64)(j + 1), m);
   }
   const u64 r = wave_sum_u64(L.ur), w = wave_sum_u64(L.uw);
   if (lane == 0) {
@@ -324,11 +337,23 @@ __device__ __forceinline__ void lacc_flush(LaneAcc &L, BucketShared &S, SpecRef 
 }
 
 // large counts are rare: keep the logarithm out of line
-__device__ __noinline__ void term_big(u32 c, u64 N, u64 *lo, u64 *hi) {
+__device__ __noinline__ ulonglong2 term_big(u32 c, u64 N) {
   u64 a, b;
   term_fx(c, N, a, b);
-  *lo = a;
-  *hi = b;
+  return make_ulonglong2(a, b);
+}
+
+// One node of level k with count c >= 1, owned by the calling lane.
+__device__ __forceinline__ void add_node(LaneAcc &L, BucketShared &S, SpecRef G, int k, u32 c,
+                                         u64 N) {
+  L.d[k] += 1;
+  if (c == 1) { L.ones[k] += 1; return; }
+  const ulonglong2 t = c < 256 ? S.term[L.space][c] : term_big(c, N);
+  add128(L.lo[k], L.hi[k], t.x, t.y);
+  if (k == 0) {
+    if (c < SPEC_LDS) atomicAdd(&S.spec[L.space][c], 1u);
+    else spec_cache_add(S, G, (u32)L.space, c, 1ull);
+  }
 }
 
 // All levels of one page whose byte-offset counts sit in cnt[1024] (LDS,
@@ -343,8 +368,6 @@ __device__ __forceinline__ void page_levels(LaneAcc &L, BucketShared &S, SpecRef
 #pragma unroll
   for (int k = 0; k < AIWC_NSKIP; ++k) {
     const u32 nodes = 1024u >> k;
-    u64 lo = 0, hi = 0;
-    u32 d = 0;
     for (u32 i = (u32)lane; i < nodes; i += AIWC_WAVE) {
       u32 c;
       if (k == 0) {
@@ -353,27 +376,8 @@ __device__ __forceinline__ void page_levels(LaneAcc &L, BucketShared &S, SpecRef
         c = cnt[2 * i] + cnt[2 * i + 1];
         cnt[i] = c;
       }
-      if (c == 0) continue;
-      u64 tl, th;
-      if (c < 256) { tl = S.tlo[L.space][c]; th = S.thi[L.space][c]; }
-      else term_big(c, N, &tl, &th);
-      const u64 nl = lo + tl;
-      hi += th + (nl < lo ? 1ull : 0ull);
-      lo = nl;
-      d += 1;
-      if (k == 0) {
-        if (c <= NSPEC) {
-#pragma unroll
-          for (int j = 0; j < (int)NSPEC; ++j) L.spec[j] += (c == (u32)(j + 1));
-        } else {
-          spec_cache_add(S, G, (u32)L.space, c, 1ull);
-        }
-      }
+      if (c) add_node(L, S, G, k, c, N);
     }
-    const u64 nl = L.lo[k] + lo;
-    L.hi[k] += hi + (nl < L.lo[k] ? 1ull : 0ull);
-    L.lo[k] = nl;
-    L.d[k] += d;
     __builtin_amdgcn_wave_barrier();
   }
   if (lane < 32) {
@@ -382,64 +386,30 @@ __device__ __forceinline__ void page_levels(LaneAcc &L, BucketShared &S, SpecRef
   }
 }
 
-
-// Bitonic sort of one u32 per lane across the wavefront (ascending).
-__device__ __forceinline__ u32 wave_sort(u32 v) {
+// Up to 64 records of one address space, one per lane.  pm: the lanes that
+// hold records of this lane's page (0 for an idle lane).  The level-k node of
+// a lane's record is pm AND the lanes whose byte offsets agree with it on
+// bits k..9; its lowest lane owns it.
+__device__ __forceinline__ void match_levels(LaneAcc &L, BucketShared &S, SpecRef G, u32 off,
+                                             u32 w, u64 pm, u64 N) {
   const int lane = lane_id();
+  const u64 below = (1ull << lane) - 1ull;
+  u64 P = pm;
 #pragma unroll
-  for (int size = 2; size <= AIWC_WAVE; size <<= 1) {
-#pragma unroll
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      const u32 o = __shfl_xor(v, stride, 64);
-      const bool up = (lane & size) == 0;
-      const bool low = (lane & stride) == 0;
-      v = (low == up) ? (v < o ? v : o) : (v > o ? v : o);
+  for (int k = AIWC_NSKIP - 1; k >= 0; --k) {
+    if (k < AIWC_NSKIP - 1) {
+      const bool b = ((off >> k) & 1u) != 0;
+      const u64 B = __ballot(b);
+      P &= b ? B : ~B;
     }
+    if (P != 0 && (P & below) == 0) add_node(L, S, G, k, (u32)__builtin_popcountll(P), N);
   }
-  return v;
-}
-
-// The records of several small pages (<= SMALL records each, one record per
-// lane, key = page << 11 | offset << 1 | write; invalid lanes hold ~0u):
-// sort them, then every run of equal key >> (1 + k) is one node of level k.
-__device__ __forceinline__ void small_pages_levels(LaneAcc &L, BucketShared &S, SpecRef G,
-                                                   u32 key) {
-  const int lane = lane_id();
-  const u32 v = wave_sort(key);
-  const u32 nv = (u32)__builtin_popcountll(__ballot(v != ~0u));
-  const u64 after = (lane == 63) ? 0ull : (~0ull << (lane + 1));
-#pragma unroll
-  for (int k = 0; k < AIWC_NSKIP; ++k) {
-    const u32 g = v >> (1 + k);
-    const u32 gp = __shfl_up(g, 1, 64);
-    const bool head = (u32)lane < nv && (lane == 0 || g != gp);
-    const u64 B = __ballot(head);
-    if (head) {
-      const u64 nx = B & after;
-      const u32 end = nx ? (u32)__builtin_ctzll(nx) : nv;
-      const u32 c = end - (u32)lane;            // <= 64 < 256: table term
-      const u64 tl = S.tlo[L.space][c], th = S.thi[L.space][c];
-      const u64 nl = L.lo[k] + tl;
-      L.hi[k] += th + (nl < L.lo[k] ? 1ull : 0ull);
-      L.lo[k] = nl;
-      L.d[k] += 1;
-      if (k == 0) {
-        if (c <= NSPEC) {
-#pragma unroll
-          for (int j = 0; j < (int)NSPEC; ++j) L.spec[j] += (c == (u32)(j + 1));
-        } else {
-          spec_cache_add(S, G, (u32)L.space, c, 1ull);
-        }
-        L.ur += (v & 1u) == 0;                  // reads sort before writes
-      }
-    }
-    if (k == 0) {
-      // last element of each level-0 run carries the write flag of the run
-      const u64 nx = B & after;
-      const u32 end = nx ? (u32)__builtin_ctzll(nx) : nv;
-      const u32 lastv = __shfl(v, (int)(end > 0 ? end - 1 : 0), 64);
-      if (head) L.uw += lastv & 1u;
-    }
+  // distinct read / written addresses: the lowest read (write) of each level-0 node
+  const u64 Bw = __ballot(w != 0);
+  const u64 Q = P & (w ? Bw : ~Bw);
+  if (P != 0 && (Q & below) == 0) {
+    if (w) L.uw += 1;
+    else L.ur += 1;
   }
 }
 
@@ -448,6 +418,8 @@ __device__ __forceinline__ u32 pt_find(const BucketShared &S, u64 pk) {
   while (S.pkey[slot] != pk) slot = (slot + 1 == PT_SLOTS) ? 0 : slot + 1;
   return slot;
 }
+
+__device__ __forceinline__ u64 low_mask(u32 n) { return n >= 64 ? ~0ull : (1ull << n) - 1ull; }
 
 template <bool BATCH>
 __global__ void __launch_bounds__(BK_BLOCK) k_mem_bucket(TraceArgs A0, const TraceArgs *batch) {
@@ -462,12 +434,11 @@ __global__ void __launch_bounds__(BK_BLOCK) k_mem_bucket(TraceArgs A0, const Tra
   u32 *staging = A.mem_stage;
   const SpecRef G = {A.sp_f, A.sp_m, A.sp_cap};
   for (u32 i = tid; i < PT_SLOTS; i += BK_BLOCK) { S.pkey[i] = EMPTY; S.pcnt[i] = 0; }
-  for (u32 i = tid; i < PT_CAP; i += BK_BLOCK) S.pcur[i] = 0;
   for (u32 i = tid; i < 2 * 256; i += BK_BLOCK) {
     u64 lo, hi;
     term_fx(i & 255u, (i >> 8) ? N1 : N0, lo, hi);
-    S.tlo[i >> 8][i & 255u] = lo;
-    S.thi[i >> 8][i & 255u] = hi;
+    S.term[i >> 8][i & 255u] = make_ulonglong2(lo, hi);
+    (&S.spec[0][0])[i] = 0;
   }
   for (u32 i = tid; i < 2 * SPEC_SLOTS; i += BK_BLOCK) {
     (&S.spf[0][0])[i] = 0;
@@ -547,33 +518,59 @@ __global__ void __launch_bounds__(BK_BLOCK) k_mem_bucket(TraceArgs A0, const Tra
         __syncthreads();
         continue;
       }
-      // ---- 2. staging offsets (exclusive scan of page counts) and regroup
-      if (tid < BK_WAVES) S.wsum[tid] = 0;
+      // ---- 2. page classes (small space 0 / small space 1 / other) and
+      // staging offsets; order inside a class is free
+      if (tid < 3) S.ctot[tid] = 0;
+      if (tid == 0) { S.nbig0 = 0; S.nbig1 = 0; S.nheavy = 0; S.next_item = 0; }
       __syncthreads();
-      for (u32 b0 = 0; b0 < np; b0 += BK_BLOCK) {
-        const u32 j = b0 + tid;
-        const u32 c = j < np ? S.pcnt[S.pslot[j]] : 0u;
-        u32 x = c;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-          const u32 y = __shfl_up(x, o, 64);
-          if (lane >= o) x += y;
+      for (u32 j0 = 0; j0 < np; j0 += BK_BLOCK) {
+        const u32 j = j0 + tid;
+        u32 c = 0, cl = 3;
+        if (j < np) {
+          const u32 slot = S.pslot[j];
+          c = S.pcnt[slot];
+          const u32 sp = (u32)((S.pkey[slot] >> sbit) & 1ull);
+          cl = c <= SMALL ? sp : 2u;
+          S.psz[j] = c;
+          if (c > SMALL) {
+            if (sp == 0) S.big[atomicAdd(&S.nbig0, 1u)] = (uint16_t)j;
+            else S.big[PT_CAP - 1 - atomicAdd(&S.nbig1, 1u)] = (uint16_t)j;
+            if (c > HEAVY) atomicAdd(&S.nheavy, 1u);
+          }
         }
-        if (lane == 63) S.wsum[wave] = x;
-        __syncthreads();
-        u32 before = b0 == 0 ? 0u : S.poff[b0];
-        for (int w = 0; w < wave; ++w) before += S.wsum[w];
-        if (j < np) S.poff[j] = before + x - c;
-        u32 tot = b0 == 0 ? 0u : S.poff[b0];
-        for (int w = 0; w < BK_WAVES; ++w) tot += S.wsum[w];
-        __syncthreads();
-        if (tid == 0) S.poff[b0 + BK_BLOCK < np ? b0 + BK_BLOCK : np] = tot;
-        __syncthreads();
+#pragma unroll
+        for (u32 q = 0; q < 3; ++q) {
+          const u64 t = wave_sum_u64(cl == q ? c : 0u);
+          if (lane == 0 && t) atomicAdd(&S.ctot[q], (u32)t);
+        }
       }
-      if (tid == 0) { S.nbig = 0; S.next_page = 0; S.next_win = 0; }
       __syncthreads();
-      for (u32 j = tid; j < np; j += BK_BLOCK)
-        if (S.poff[j + 1] - S.poff[j] > SMALL) S.big[atomicAdd(&S.nbig, 1u)] = (uint16_t)j;
+      if (tid == 0) { S.ccur[0] = 0; S.ccur[1] = S.ctot[0]; S.ccur[2] = S.ctot[0] + S.ctot[1]; }
+      __syncthreads();
+      for (u32 j0 = 0; j0 < np; j0 += BK_BLOCK) {
+        const u32 j = j0 + tid;
+        u32 c = 0, cl = 3;
+        if (j < np) {
+          c = S.psz[j];
+          cl = c <= SMALL ? (u32)((S.pkey[S.pslot[j]] >> sbit) & 1ull) : 2u;
+        }
+#pragma unroll
+        for (u32 q = 0; q < 3; ++q) {
+          const u32 v = cl == q ? c : 0u;
+          u32 x = v;
+#pragma unroll
+          for (int o = 1; o < 64; o <<= 1) {
+            const u32 y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+          }
+          const u32 tot = __shfl(x, 63, 64);
+          u32 b = 0;
+          if (lane == 0 && tot) b = atomicAdd(&S.ccur[q], tot);
+          b = __shfl(b, 0, 64);
+          if (cl == q) S.pend[j] = b + x - v;
+        }
+      }
+      __syncthreads();
       for (u32 i0 = tid; i0 < n; i0 += BK_BLOCK * UNROLL) {
         u64 rv[UNROLL];
 #pragma unroll
@@ -587,97 +584,104 @@ __global__ void __launch_bounds__(BK_BLOCK) k_mem_bucket(TraceArgs A0, const Tra
           const u64 pk = rv[u] >> 11;
           if (((u32)pk & (M - 1u)) != C) continue;
           const u32 ci = S.pidx[pt_find(S, pk)];
-          const u32 pos = S.poff[ci] + atomicAdd(&S.pcur[ci], 1u);
+          const u32 pos = atomicAdd(&S.pend[ci], 1u);
           staging[base + pos] = (ci << 11) | (u32)(rv[u] & 2047ull);
         }
       }
       __threadfence_block();
       __syncthreads();
+      const u32 nb0 = S.nbig0, nb1 = S.nbig1;
       // ---- 3a. heavy pages: counted by the whole block into dense[0]
-      for (u32 ci = 0; ci < np; ++ci) {
-        const u32 cnt = S.poff[ci + 1] - S.poff[ci];
-        if (cnt <= HEAVY) continue;
-        for (u32 i = tid; i < 1024; i += BK_BLOCK) S.dense[0][i] = 0;
-        if (tid < 32) { S.rbits[0][tid] = 0; S.wbits[0][tid] = 0; }
-        __syncthreads();
-        for (u32 i = S.poff[ci] + tid; i < S.poff[ci + 1]; i += BK_BLOCK) {
-          const u32 v = staging[base + i];
-          const u32 off = (v >> 1) & 1023u;
-          atomicAdd(&S.dense[0][off], 1u);
-          atomicOr((v & 1u) ? &S.wbits[0][off >> 5] : &S.rbits[0][off >> 5], 1u << (off & 31u));
-        }
-        __syncthreads();
-        if (wave == 0) {
-          const int sp = (int)((S.pkey[S.pslot[ci]] >> sbit) & 1ull);
-          if (sp != L.space) { lacc_flush(L, S, G); L.space = sp; }
-          page_levels(L, S, G, S.dense[0], S.rbits[0], S.wbits[0], sp ? N1 : N0);
-        }
-        __syncthreads();
-      }
-      // ---- 3b. big pages (> SMALL records): one wavefront each, dense counters
-      u32 *dn = S.dense[wave];
-      u32 *rb = S.rbits[wave], *wb = S.wbits[wave];
-      const u32 nbig = S.nbig;
-      while (true) {
-        u32 bi = 0;
-        if (lane == 0) bi = atomicAdd(&S.next_page, 1u);
-        bi = __shfl(bi, 0, 64);
-        if (bi >= nbig) break;
-        const u32 ci = S.big[bi];
-        const u32 o0 = S.poff[ci], o1 = S.poff[ci + 1];
-        if (o1 - o0 > HEAVY) continue;
-        uint4 *z = reinterpret_cast<uint4 *>(dn + 16 * lane);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) z[q] = make_uint4(0, 0, 0, 0);
-        if (lane < 32) { rb[lane] = 0; wb[lane] = 0; }
-        __builtin_amdgcn_wave_barrier();
-        for (u32 i0 = o0 + lane; i0 < o1; i0 += AIWC_WAVE * 4) {
-          u32 vv[4];
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const u32 i = i0 + (u32)u * AIWC_WAVE;
-            vv[u] = i < o1 ? staging[base + i] : ~0u;
+      if (S.nheavy) {
+        for (u32 bi = 0; bi < nb0 + nb1; ++bi) {
+          const u32 ci = S.big[bi < nb0 ? bi : PT_CAP - 1 - (bi - nb0)];
+          const u32 sz = S.psz[ci];
+          if (sz <= HEAVY) continue;
+          const u32 o1 = S.pend[ci], o0 = o1 - sz;
+          for (u32 i = tid; i < 1024; i += BK_BLOCK) S.dense[0][i] = 0;
+          if (tid < 32) { S.rbits[0][tid] = 0; S.wbits[0][tid] = 0; }
+          __syncthreads();
+          for (u32 i = o0 + tid; i < o1; i += BK_BLOCK) {
+            const u32 v = staging[base + i];
+            const u32 off = (v >> 1) & 1023u;
+            atomicAdd(&S.dense[0][off], 1u);
+            atomicOr((v & 1u) ? &S.wbits[0][off >> 5] : &S.rbits[0][off >> 5], 1u << (off & 31u));
           }
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            if (vv[u] == ~0u) continue;
-            const u32 off = (vv[u] >> 1) & 1023u;
-            atomicAdd(&dn[off], 1u);
-            atomicOr((vv[u] & 1u) ? &wb[off >> 5] : &rb[off >> 5], 1u << (off & 31u));
+          __syncthreads();
+          if (wave == 0) {
+            const int sp = bi < nb0 ? 0 : 1;
+            if (sp != L.space) { lacc_flush(L, S); L.space = sp; }
+            page_levels(L, S, G, S.dense[0], S.rbits[0], S.wbits[0], sp ? N1 : N0);
           }
+          __syncthreads();
         }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        const int sp = (int)((S.pkey[S.pslot[ci]] >> sbit) & 1ull);
-        if (sp != L.space) { lacc_flush(L, S, G); L.space = sp; }
-        page_levels(L, S, G, dn, rb, wb, sp ? N1 : N0);
-        __builtin_amdgcn_wave_barrier();
       }
-      // ---- 3c. small pages, in windows of 32 staging positions: the pages
-      // starting in a window (<= SMALL records each) fit one wavefront
-      const u32 R = S.poff[np];
-      const u32 nwin = (R + SMALL - 1) / SMALL;
-      while (true) {
-        u32 w = 0;
-        if (lane == 0) w = atomicAdd(&S.next_win, 1u);
-        w = __shfl(w, 0, 64);
-        if (w >= nwin) break;
-        const u32 lo = w * SMALL, i = lo + (u32)lane;
-        const u32 v = i < R ? staging[base + i] : ~0u;
-        const u32 ci = v >> 11;
-        bool ok = i < R;
-        u32 sp = 0;
-        if (ok) {
-          const u32 p0 = S.poff[ci];
-          ok = (S.poff[ci + 1] - p0) <= SMALL && p0 >= lo && p0 < lo + SMALL;
-          sp = (u32)((S.pkey[S.pslot[ci]] >> sbit) & 1ull);
-        }
-        const u64 has1 = __ballot(ok && sp == 1u), has0 = __ballot(ok && sp == 0u);
-        for (u32 s2 = 0; s2 < 2; ++s2) {
-          if (!(s2 ? has1 : has0)) continue;
-          if ((int)s2 != L.space) { lacc_flush(L, S, G); L.space = (int)s2; }
-          const u32 key = (ok && sp == s2) ? ((ci << 11) | (v & 2047u)) : ~0u;
-          small_pages_levels(L, S, G, key);
+      // ---- 3b. per-wavefront items, space 0 first: small-page windows,
+      // then larger pages; then the same for space 1
+      {
+        const u32 R0 = S.ctot[0], R1 = S.ctot[1];
+        const u32 W0 = (R0 + SMALL - 1) / SMALL, W1 = (R1 + SMALL - 1) / SMALL;
+        const u32 e0 = W0, e1 = e0 + nb0, e2 = e1 + W1, e3 = e2 + nb1;
+        u32 *dn = S.dense[wave];
+        u32 *rb = S.rbits[wave], *wb = S.wbits[wave];
+        while (true) {
+          u32 it = 0;
+          if (lane == 0) it = atomicAdd(&S.next_item, 1u);
+          it = __shfl(it, 0, 64);
+          if (it >= e3) break;
+          const int sp = (it < e1) ? 0 : 1;
+          const u64 N = sp ? N1 : N0;
+          if (sp != L.space) { lacc_flush(L, S); L.space = sp; }
+          if (it < e0 || (it >= e1 && it < e2)) {
+            // window of SMALL start positions inside the small pages of space sp
+            const u32 lo = (it < e0) ? it * SMALL : R0 + (it - e1) * SMALL;
+            const u32 rend = (it < e0) ? R0 : R0 + R1;
+            const u32 i = lo + (u32)lane;
+            u32 v = 0;
+            u64 pm = 0;
+            if (i < rend) {
+              v = staging[base + i];
+              const u32 ci = v >> 11;
+              const u32 sz = S.psz[ci], st = S.pend[ci] - sz;
+              if (st >= lo && st < lo + SMALL) pm = low_mask(sz) << (st - lo);
+            }
+            match_levels(L, S, G, (v >> 1) & 1023u, v & 1u, pm, N);
+            continue;
+          }
+          const u32 ci = S.big[(it < e1) ? it - e0 : PT_CAP - 1 - (it - e2)];
+          const u32 sz = S.psz[ci];
+          if (sz > HEAVY) continue;
+          const u32 o1 = S.pend[ci], o0 = o1 - sz;
+          if (sz <= MEDIUM) {
+            const u32 v = (u32)lane < sz ? staging[base + o0 + lane] : 0u;
+            match_levels(L, S, G, (v >> 1) & 1023u, v & 1u, (u32)lane < sz ? low_mask(sz) : 0ull,
+                         N);
+            continue;
+          }
+          uint4 *z = reinterpret_cast<uint4 *>(dn + 16 * lane);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) z[q] = make_uint4(0, 0, 0, 0);
+          if (lane < 32) { rb[lane] = 0; wb[lane] = 0; }
+          __builtin_amdgcn_wave_barrier();
+          for (u32 i0 = o0 + lane; i0 < o1; i0 += AIWC_WAVE * 4) {
+            u32 vv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const u32 i = i0 + (u32)u * AIWC_WAVE;
+              vv[u] = i < o1 ? staging[base + i] : ~0u;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              if (vv[u] == ~0u) continue;
+              const u32 off = (vv[u] >> 1) & 1023u;
+              atomicAdd(&dn[off], 1u);
+              atomicOr((vv[u] & 1u) ? &wb[off >> 5] : &rb[off >> 5], 1u << (off & 31u));
+            }
+          }
+          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          page_levels(L, S, G, dn, rb, wb, N);
+          __builtin_amdgcn_wave_barrier();
         }
       }
       __syncthreads();
@@ -686,7 +690,6 @@ __global__ void __launch_bounds__(BK_BLOCK) k_mem_bucket(TraceArgs A0, const Tra
         const u32 slot = S.pslot[j];
         S.pkey[slot] = EMPTY;
         S.pcnt[slot] = 0;
-        S.pcur[j] = 0;
       }
       __syncthreads();
       if (tid == 0) S.npages = 0;
@@ -694,7 +697,7 @@ __global__ void __launch_bounds__(BK_BLOCK) k_mem_bucket(TraceArgs A0, const Tra
     }
   }
   // ---- flush the lanes' and the block's accumulators
-  lacc_flush(L, S, G);
+  lacc_flush(L, S);
   __syncthreads();
   if (tid < 2 * AIWC_NSKIP) {
     const int s = tid / AIWC_NSKIP, k = tid % AIWC_NSKIP;
@@ -710,7 +713,12 @@ __global__ void __launch_bounds__(BK_BLOCK) k_mem_bucket(TraceArgs A0, const Tra
     const u32 s = i / SPEC_SLOTS, j = i % SPEC_SLOTS;
     if (S.spf[s][j]) global_spec_add(G, s, S.spf[s][j], S.spm[s][j]);
   }
+  for (u32 i = tid; i < 2 * SPEC_LDS; i += BK_BLOCK) {
+    const u32 s = i / SPEC_LDS, c = i % SPEC_LDS;
+    if (S.spec[s][c]) global_spec_add(G, s, c, S.spec[s][c]);
+  }
 }
+
 
 }  // namespace
 
