@@ -99,7 +99,6 @@ void plan_trace(const aiwc_trace *t, u32 pbits, TracePlan &p, const Tune *tune) 
   p.o_part_hist = take(4ull * p.n_hist_blocks * P);
   p.o_part_off = take(4ull * (P + 1));
   p.o_part_rec = take(8ull * std::max<u64>(1, d.n_mem));
-  p.o_mem_stage = take(4ull * std::max<u64>(1, d.n_mem));
   p.o_br_a = take(4ull * std::max<u64>(1, d.n_branch));
   p.o_br_b = take(4ull * std::max<u64>(1, d.n_branch));
   p.o_br_cnt = take(4ull * 256 * std::max<u64>(1, p.br_tiles));
@@ -164,7 +163,6 @@ void fill_args(const aiwc_trace *t, const TracePlan &p, char *scratch, char *res
   a.part_hist = (u32 *)(scratch + p.o_part_hist);
   a.part_off = (u32 *)(scratch + p.o_part_off);
   a.part_rec = (u64 *)(scratch + p.o_part_rec);
-  a.mem_stage = (u32 *)(scratch + p.o_mem_stage);
   a.br_a = (u32 *)(scratch + p.o_br_a);
   a.br_b = (u32 *)(scratch + p.o_br_b);
   a.br_cnt = (u32 *)(scratch + p.o_br_cnt);

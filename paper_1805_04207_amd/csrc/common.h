@@ -70,7 +70,6 @@ struct TraceArgs {
   u32 *part_hist;            // [n_hist_blocks][P]
   u32 *part_off;             // [P + 1]
   u64 *part_rec;             // [n_mem]
-  u32 *mem_stage;            // [n_mem] records regrouped page by page
   u32 *br_a, *br_b;          // [n_branch] radix ping-pong
   u32 *br_cnt;               // [256 * br_tiles]
   u32 *scan_tmp;             // block sums for the generic scan

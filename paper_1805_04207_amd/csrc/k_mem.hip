@@ -33,7 +33,7 @@
 namespace {
 
 constexpr int MEM_BLOCK = 1024;
-constexpr u32 SPEC_SLOTS = 128;   // per-space LDS cache of the level-0 spectrum
+constexpr u32 SPEC_SLOTS = 64;    // per-space LDS cache of the level-0 spectrum
 constexpr u64 EMPTY = ~0ull;
 
 __device__ __forceinline__ u64 make_record(u64 a, uint8_t kind, u32 pbits, u32 &bin) {
@@ -205,10 +205,12 @@ __global__ void __launch_bounds__(MEM_BLOCK) k_mem_scatter(TraceArgs A0, const T
 //                   More than PT_CAP pages: the partition is split into rounds
 //                   by page-hash bits (never by record, so every a >> k bucket
 //                   stays whole) and redone.
-//  2. regroup     : records are regrouped page by page into a staging array
-//                   (u32: compact page index, byte offset, write flag), small
-//                   pages (<= SMALL records) of space 0, then of space 1, then
-//                   every other page.
+//  2. regroup     : records are regrouped page by page into an LDS staging
+//                   array (u32: compact page index, byte offset, write flag),
+//                   small pages (<= SMALL records) of space 0, then of space 1,
+//                   then every other page up to HEAVY records.  A round whose
+//                   staged records exceed STAGE_CAP is split like a page
+//                   overflow.
 //  3. levels      : the node of level k holding a record is the set of records
 //                   of its page whose byte offsets agree on bits k..9.
 //       pages <= MEDIUM records, one record per lane: that set is the page's
@@ -218,11 +220,14 @@ __global__ void __launch_bounds__(MEM_BLOCK) k_mem_scatter(TraceArgs A0, const T
 //                   of SMALL staging positions (they end within 2 * SMALL).
 //       larger pages: the wavefront counts the page's byte offsets in 1024
 //                   dense LDS counters, then reduces them level by level.
-//       pages > HEAVY records are counted by the whole block.
-//     Each node adds 1 to distinct_k and its entropy term c*log2(N/c) (exact
-//     2^-64 fixed point) to level k; nodes with c = 1 are only counted and
-//     multiplied by log2(N) when the accumulators are flushed.  Level-0 counts
-//     below SPEC_LDS go to an LDS spectrum histogram.
+//       pages > HEAVY records are not staged: the whole block counts them
+//                   straight from the partition's records.
+//     Each node adds 1 to distinct_k and its entropy term c*log2(N/c) (fixed
+//     point, truncated to 2^-40, integer sums) to level k; nodes with c = 1
+//     are only counted and multiplied by log2(N) when the accumulators are
+//     flushed.  Level-0 counts below SPEC_LDS go to an LDS spectrum histogram;
+//     dense-tree nodes with c >= 256 are listed and added by the block after
+//     the round.
 constexpr u32 PT_SLOTS = 2048;
 constexpr u32 PT_CAP = 1536;
 constexpr int BK_BLOCK = 512;                    // 8 waves: 256 VGPRs per lane
@@ -232,33 +237,46 @@ constexpr u32 SMALL = 32;
 constexpr u32 MEDIUM = 64;
 constexpr int UNROLL = 8;                         // records in flight per thread
 constexpr u32 SPEC_LDS = 256;
+constexpr u32 STAGE_CAP = 16384;                  // staged records per round
+// Dense-tree nodes of count >= 256 found by the wavefronts in one round, kept
+// for the block: at most 11 levels * STAGE_CAP / 256 of them.
+constexpr u32 BLIST_CAP = AIWC_NSKIP * STAGE_CAP / 256;
 
 struct BucketShared {
   u64 pkey[PT_SLOTS];              // page key, EMPTY if free
   u32 pcnt[PT_SLOTS];              // records of the page
   uint16_t pidx[PT_SLOTS];         // compact index of the page
   uint16_t pslot[PT_CAP];          // slot of compact index
-  u32 psz[PT_CAP];                 // records of compact index
+  uint16_t psz[PT_CAP];            // records of compact index (saturated at 65535)
   u32 pend[PT_CAP];                // staging cursor, then end, of compact index
   u32 dense[BK_WAVES][1024];       // per-wave byte-offset counters
   u32 rbits[BK_WAVES][32], wbits[BK_WAVES][32];
-  ulonglong2 term[2][256];         // c*log2(N_s/c) for c < 256, (lo, hi)
+  u64 term[2][256];                // c*log2(N_s/c) for c < 256, 2^-40 units
   u32 spec[2][SPEC_LDS];           // level-0 nodes of count c, 2 <= c < SPEC_LDS
   u64 spf[2][SPEC_SLOTS], spm[2][SPEC_SLOTS];
-  u64 dist[2][AIWC_NSKIP], elo[2][AIWC_NSKIP], ehi[2][AIWC_NSKIP];
+  u64 dist[2][AIWC_NSKIP], elo[2][AIWC_NSKIP], ehi[2][AIWC_NSKIP];   // entropy: 2^-40 units
   u64 ur[2], uw[2];
   u64 redos;
   uint16_t big[PT_CAP];            // pages > SMALL: space 0 from the front, 1 from the back
   u32 ctot[3], ccur[3];
   u32 npages, overflow, work, nbig0, nbig1, nheavy, next_item, sp_top;
-  u32 stack_m[64], stack_c[64];
+  u32 stack_m[32], stack_c[32];
+  u32 stage[STAGE_CAP];            // the round's records, page by page
+  u32 blist[BLIST_CAP];            // space << 31 | level << 24 | count
+  u32 nblist;
 };
 
-// c * log2(N / c) as 2^-64 fixed point.
+// c * log2(N / c) in units of 2^-40, truncated (lo, hi words).  Every term
+// of every path is rounded this one way, so the sums do not depend on how the
+// work was split; with N < 2^32 the sum of a level's terms is at least
+// (nodes - 1), so the truncation costs at most 2^-39 relative.
 __device__ __forceinline__ void term_fx(u64 c, u64 N, u64 &lo, u64 &hi) {
   if (c == 0 || c >= N) { lo = hi = 0; return; }
   const double d = (double)c * (log1p((double)(N - c) / (double)c) * 1.4426950408889634074);
-  to_fx64(d, lo, hi);
+  u64 l64, h64;
+  to_fx64(d, l64, h64);
+  lo = (l64 >> 24) | (h64 << 40);
+  hi = h64 >> 24;
 }
 
 // The sparse level-0 spectrum of one space in global memory: f -> m_f.
@@ -288,18 +306,22 @@ __device__ __noinline__ void spec_cache_add(BucketShared &S, SpecRef G, u32 s, u
   global_spec_add(G, s, f, m);
 }
 
-// Per-lane accumulators of one address space (flushed when the space changes).
+// Per-lane accumulators of one address space within one round (flushed when
+// the space changes and at the end of the round) for nodes of count < 256.
+// A round stages at most STAGE_CAP records, so per level its terms sum below
+// STAGE_CAP * 32 < 2^20 (2^60 units) and its nodes number below 2^16 (dn:
+// nodes | nodes of count 1 << 16); a heavy page has at most 1024 nodes per
+// level, whose small terms sum below 1024 * 256 * 32 = 2^23.
 struct LaneAcc {
-  u64 lo[AIWC_NSKIP], hi[AIWC_NSKIP];
-  u32 d[AIWC_NSKIP];               // nodes
-  u32 ones[AIWC_NSKIP];            // nodes of count 1 (term log2 N, added at flush)
+  u64 lo[AIWC_NSKIP];              // 2^-40 units
+  u32 dn[AIWC_NSKIP];
   u32 ur, uw;
   int space;
 };
 
 __device__ __forceinline__ void lacc_clear(LaneAcc &L, int space) {
 #pragma unroll
-  for (int k = 0; k < AIWC_NSKIP; ++k) { L.lo[k] = 0; L.hi[k] = 0; L.d[k] = 0; L.ones[k] = 0; }
+  for (int k = 0; k < AIWC_NSKIP; ++k) { L.lo[k] = 0; L.dn[k] = 0; }
   L.ur = L.uw = 0;
   L.space = space;
 }
@@ -310,19 +332,19 @@ __device__ __forceinline__ void add128(u64 &lo, u64 &hi, u64 tl, u64 th) {
   lo = nl;
 }
 
+
 __device__ __forceinline__ void lacc_flush(LaneAcc &L, BucketShared &S) {
   const int s = L.space;
   const int lane = lane_id();
-  const ulonglong2 t1 = S.term[s][1];
+  const u64 t1 = S.term[s][1];
 #pragma unroll
   for (int k = 0; k < AIWC_NSKIP; ++k) {
-    u64 lo = L.lo[k], hi = L.hi[k];
-    wave_sum_u128(lo, hi);
-    const u64 d = wave_sum_u64(L.d[k]);
-    const u64 n1 = wave_sum_u64(L.ones[k]);
+    u64 lo = wave_sum_u64(L.lo[k]), hi = 0;
+    const u64 dn = wave_sum_u64((u64)(L.dn[k] & 0xFFFFu) | ((u64)(L.dn[k] >> 16) << 32));
+    const u64 d = dn & 0xFFFFFFFFull, n1 = dn >> 32;
     if (lane == 0) {
       // + n1 * log2(N): 128-bit product of the fixed-point term and the count
-      add128(lo, hi, t1.x * n1, __umul64hi(t1.x, n1) + t1.y * n1);
+      add128(lo, hi, t1 * n1, __umul64hi(t1, n1));
       atomic_add_u128(&S.elo[s][k], &S.ehi[s][k], lo, hi);
       if (d) atomicAdd(&S.dist[s][k], d);
       if (k == 0 && n1) atomicAdd(&S.spec[s][1], (u32)n1);
@@ -336,62 +358,147 @@ __device__ __forceinline__ void lacc_flush(LaneAcc &L, BucketShared &S) {
   lacc_clear(L, s);
 }
 
-// large counts are rare: keep the logarithm out of line
-__device__ __noinline__ ulonglong2 term_big(u32 c, u64 N) {
-  u64 a, b;
-  term_fx(c, N, a, b);
-  return make_ulonglong2(a, b);
+// A node of level k with count c < 256 (c = 0: no node).  Count-1 nodes are
+// only counted; the others add their tabulated term.  Branch free, so that a
+// wavefront issues its table loads back to back.
+__device__ __forceinline__ void add_small_node(LaneAcc &L, const BucketShared &S, int k, u32 c) {
+  L.lo[k] += S.term[L.space][c >= 2 ? c : 0u];   // term[0] = 0
+  L.dn[k] += (c != 0 ? 1u : 0u) + (c == 1 ? 0x10000u : 0u);
 }
 
-// One node of level k with count c >= 1, owned by the calling lane.
-__device__ __forceinline__ void add_node(LaneAcc &L, BucketShared &S, SpecRef G, int k, u32 c,
+// A node of count >= 256 (rare): its term goes straight to the block's
+// accumulators.
+__device__ __forceinline__ void big_node(BucketShared &S, SpecRef G, int s, int k, u32 v,
                                          u64 N) {
-  L.d[k] += 1;
-  if (c == 1) { L.ones[k] += 1; return; }
-  const ulonglong2 t = c < 256 ? S.term[L.space][c] : term_big(c, N);
-  add128(L.lo[k], L.hi[k], t.x, t.y);
-  if (k == 0) {
-    if (c < SPEC_LDS) atomicAdd(&S.spec[L.space][c], 1u);
-    else spec_cache_add(S, G, (u32)L.space, c, 1ull);
+  u64 lo, hi;
+  term_fx(v, N, lo, hi);
+  atomic_add_u128(&S.elo[s][k], &S.ehi[s][k], lo, hi);
+  atomicAdd(&S.dist[s][k], 1ull);
+  if (k == 0) spec_cache_add(S, G, (u32)s, v, 1ull);
+}
+
+// The nodes of count >= 256 of the dense tree over cnt[1024] (see
+// page_levels).  Few pages have any: plain loops, so that the logarithm is
+// emitted twice rather than once per node (and no call spills registers).
+__device__ __forceinline__ void big_pass(BucketShared &S, SpecRef G, const u32 *cnt, int s,
+                                         u64 N) {
+  const int lane = lane_id();
+  const u32 *my = cnt + 16 * lane;
+#pragma unroll 1
+  for (int k = 0; k <= 4; ++k) {
+#pragma unroll 1
+    for (int j = 0; j < (16 >> k); ++j) {
+      u32 v = 0;
+#pragma unroll 1
+      for (int q = 0; q < (1 << k); ++q) v += my[(j << k) + q];
+      if (v >= 256) big_node(S, G, s, k, v, N);
+    }
+  }
+  u32 t = 0;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) t += my[q];
+  u32 tk[AIWC_NSKIP - 5];
+#pragma unroll
+  for (int k = 5; k < AIWC_NSKIP; ++k) {
+    t += __shfl_xor(t, 1 << (k - 5), 64);
+    tk[k - 5] = ((lane & ((1 << (k - 4)) - 1)) == 0) ? t : 0u;
+  }
+#pragma unroll 1
+  for (int k = 5; k < AIWC_NSKIP; ++k) {
+    u32 v = tk[0];
+#pragma unroll
+    for (int q = 1; q < AIWC_NSKIP - 5; ++q) v = (k == 5 + q) ? tk[q] : v;
+    if (v >= 256) big_node(S, G, s, k, v, N);
+  }
+}
+
+// As big_pass, but the nodes are appended to the block's list (their counts
+// stay below 2^24: a staged page has at most HEAVY records).
+__device__ __forceinline__ void big_collect(BucketShared &S, const u32 *cnt, int s) {
+  const int lane = lane_id();
+  const u32 *my = cnt + 16 * lane;
+  const u32 tag = (u32)s << 31;
+#pragma unroll 1
+  for (int k = 0; k <= 4; ++k) {
+#pragma unroll 1
+    for (int j = 0; j < (16 >> k); ++j) {
+      u32 v = 0;
+#pragma unroll 1
+      for (int q = 0; q < (1 << k); ++q) v += my[(j << k) + q];
+      if (v >= 256) S.blist[atomicAdd(&S.nblist, 1u)] = tag | ((u32)k << 24) | v;
+    }
+  }
+  u32 t = 0;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) t += my[q];
+#pragma unroll
+  for (int k = 5; k < AIWC_NSKIP; ++k) {
+    t += __shfl_xor(t, 1 << (k - 5), 64);
+    if ((lane & ((1 << (k - 4)) - 1)) == 0 && t >= 256)
+      S.blist[atomicAdd(&S.nblist, 1u)] = tag | ((u32)k << 24) | t;
   }
 }
 
 // All levels of one page whose byte-offset counts sit in cnt[1024] (LDS,
 // owned by this wavefront) and whose read / write bitmaps in rb[32], wb[32].
-// Level k has 1024 >> k nodes; node i of level k >= 1 is the sum of nodes 2i
-// and 2i+1 of level k-1, reduced in place: within one wavefront every lane's
-// loads of an iteration are issued before its stores, and an iteration only
-// overwrites entries that earlier iterations have already read.
+// Lane l loads counters 16l..16l+15: levels 0..4 are sums inside the lane,
+// levels 5..10 sums across 2, 4, .., 64 lanes (the lowest lane owns the
+// node).  Counts below 256 are accumulated in one pass; if any node reaches
+// 256, a second pass walks the tree again for those nodes only.
+template <bool DEFER>
 __device__ __forceinline__ void page_levels(LaneAcc &L, BucketShared &S, SpecRef G,
-                                            u32 *cnt, const u32 *rb, const u32 *wb, u64 N) {
+                                            const u32 *cnt, const u32 *rb, const u32 *wb,
+                                            u64 N) {
   const int lane = lane_id();
+  const int s = L.space;
+  const uint4 *src = reinterpret_cast<const uint4 *>(cnt + 16 * lane);
+  u32 c[16];
 #pragma unroll
-  for (int k = 0; k < AIWC_NSKIP; ++k) {
-    const u32 nodes = 1024u >> k;
-    for (u32 i = (u32)lane; i < nodes; i += AIWC_WAVE) {
-      u32 c;
-      if (k == 0) {
-        c = cnt[i];
-      } else {
-        c = cnt[2 * i] + cnt[2 * i + 1];
-        cnt[i] = c;
-      }
-      if (c) add_node(L, S, G, k, c, N);
-    }
-    __builtin_amdgcn_wave_barrier();
+  for (int q = 0; q < 4; ++q) {
+    const uint4 x = src[q];
+    c[4 * q] = x.x; c[4 * q + 1] = x.y; c[4 * q + 2] = x.z; c[4 * q + 3] = x.w;
   }
   if (lane < 32) {
     L.ur += __builtin_popcount(rb[lane]);
     L.uw += __builtin_popcount(wb[lane]);
+  }
+  bool anybig = false;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const u32 v = c[j] < 256 ? c[j] : 0u;
+    add_small_node(L, S, 0, v);
+    if (v >= 2) atomicAdd(&S.spec[s][v], 1u);
+    anybig |= c[j] >= 256;
+  }
+#pragma unroll
+  for (int k = 1; k <= 4; ++k) {
+#pragma unroll
+    for (int j = 0; j < (16 >> k); ++j) {
+      c[j] = c[2 * j] + c[2 * j + 1];
+      add_small_node(L, S, k, c[j] < 256 ? c[j] : 0u);
+      anybig |= c[j] >= 256;
+    }
+  }
+  u32 t = c[0];
+#pragma unroll
+  for (int k = 5; k < AIWC_NSKIP; ++k) {
+    t += __shfl_xor(t, 1 << (k - 5), 64);
+    const bool own = (lane & ((1 << (k - 4)) - 1)) == 0;
+    add_small_node(L, S, k, (own && t < 256) ? t : 0u);
+    anybig |= own && t >= 256;
+  }
+  if (__ballot(anybig) != 0) {
+    if constexpr (DEFER) big_collect(S, cnt, s);
+    else big_pass(S, G, cnt, s, N);
   }
 }
 
 // Up to 64 records of one address space, one per lane.  pm: the lanes that
 // hold records of this lane's page (0 for an idle lane).  The level-k node of
 // a lane's record is pm AND the lanes whose byte offsets agree with it on
-// bits k..9; its lowest lane owns it.
-__device__ __forceinline__ void match_levels(LaneAcc &L, BucketShared &S, SpecRef G, u32 off,
-                                             u32 w, u64 pm, u64 N) {
+// bits k..9; its lowest lane owns it.  Counts are at most 64.
+__device__ __forceinline__ void match_levels(LaneAcc &L, BucketShared &S, u32 off, u32 w,
+                                             u64 pm) {
   const int lane = lane_id();
   const u64 below = (1ull << lane) - 1ull;
   u64 P = pm;
@@ -402,7 +509,10 @@ __device__ __forceinline__ void match_levels(LaneAcc &L, BucketShared &S, SpecRe
       const u64 B = __ballot(b);
       P &= b ? B : ~B;
     }
-    if (P != 0 && (P & below) == 0) add_node(L, S, G, k, (u32)__builtin_popcountll(P), N);
+    const bool own = P != 0 && (P & below) == 0;
+    const u32 c = own ? (u32)__builtin_popcountll(P) : 0u;
+    add_small_node(L, S, k, c);
+    if (k == 0 && c >= 2) atomicAdd(&S.spec[L.space][c], 1u);
   }
   // distinct read / written addresses: the lowest read (write) of each level-0 node
   const u64 Bw = __ballot(w != 0);
@@ -431,13 +541,12 @@ __global__ void __launch_bounds__(BK_BLOCK) k_mem_bucket(TraceArgs A0, const Tra
   const u32 sbit = PAGE_BITS - A.pbits;            // space bit position in a page key
   const u64 N0 = A.acc->sp_reads[0] + A.acc->sp_writes[0];
   const u64 N1 = A.acc->sp_reads[1] + A.acc->sp_writes[1];
-  u32 *staging = A.mem_stage;
   const SpecRef G = {A.sp_f, A.sp_m, A.sp_cap};
   for (u32 i = tid; i < PT_SLOTS; i += BK_BLOCK) { S.pkey[i] = EMPTY; S.pcnt[i] = 0; }
   for (u32 i = tid; i < 2 * 256; i += BK_BLOCK) {
     u64 lo, hi;
     term_fx(i & 255u, (i >> 8) ? N1 : N0, lo, hi);
-    S.term[i >> 8][i & 255u] = make_ulonglong2(lo, hi);
+    S.term[i >> 8][i & 255u] = lo;   // below 2^54: hi is 0
     (&S.spec[0][0])[i] = 0;
   }
   for (u32 i = tid; i < 2 * SPEC_SLOTS; i += BK_BLOCK) {
@@ -448,9 +557,7 @@ __global__ void __launch_bounds__(BK_BLOCK) k_mem_bucket(TraceArgs A0, const Tra
     (&S.dist[0][0])[tid] = 0; (&S.elo[0][0])[tid] = 0; (&S.ehi[0][0])[tid] = 0;
   }
   if (tid < 2) { S.ur[tid] = 0; S.uw[tid] = 0; }
-  if (tid == 0) { S.redos = 0; S.npages = 0; S.overflow = 0; }
-  LaneAcc L;
-  lacc_clear(L, 0);
+  if (tid == 0) { S.redos = 0; S.npages = 0; S.overflow = 0; S.nblist = 0; }
   __syncthreads();
 
   while (true) {
@@ -501,23 +608,6 @@ __global__ void __launch_bounds__(BK_BLOCK) k_mem_bucket(TraceArgs A0, const Tra
       }
       __syncthreads();
       const u32 np = S.npages < PT_CAP ? S.npages : PT_CAP;
-      if (S.overflow) {
-        // too many pages for one round: clear and split by one more hash bit
-        for (u32 i = tid; i < PT_SLOTS; i += BK_BLOCK) { S.pkey[i] = EMPTY; S.pcnt[i] = 0; }
-        __syncthreads();
-        if (tid == 0) {
-          S.npages = 0; S.overflow = 0; S.redos += 1;
-          if (M >= (1u << 30) || S.sp_top + 2 > 64) {
-            atomicAdd(&A.acc->bad_mem, 1ull);   // hash bits exhausted: report, never spin
-          } else {
-            S.stack_m[S.sp_top] = 2 * M; S.stack_c[S.sp_top] = C;
-            S.stack_m[S.sp_top + 1] = 2 * M; S.stack_c[S.sp_top + 1] = C + M;
-            S.sp_top += 2;
-          }
-        }
-        __syncthreads();
-        continue;
-      }
       // ---- 2. page classes (small space 0 / small space 1 / other) and
       // staging offsets; order inside a class is free
       if (tid < 3) S.ctot[tid] = 0;
@@ -531,11 +621,11 @@ __global__ void __launch_bounds__(BK_BLOCK) k_mem_bucket(TraceArgs A0, const Tra
           c = S.pcnt[slot];
           const u32 sp = (u32)((S.pkey[slot] >> sbit) & 1ull);
           cl = c <= SMALL ? sp : 2u;
-          S.psz[j] = c;
+          S.psz[j] = (uint16_t)(c < 65535u ? c : 65535u);
           if (c > SMALL) {
             if (sp == 0) S.big[atomicAdd(&S.nbig0, 1u)] = (uint16_t)j;
             else S.big[PT_CAP - 1 - atomicAdd(&S.nbig1, 1u)] = (uint16_t)j;
-            if (c > HEAVY) atomicAdd(&S.nheavy, 1u);
+            if (c > HEAVY) { atomicAdd(&S.nheavy, 1u); cl = 3; }
           }
         }
 #pragma unroll
@@ -545,6 +635,24 @@ __global__ void __launch_bounds__(BK_BLOCK) k_mem_bucket(TraceArgs A0, const Tra
         }
       }
       __syncthreads();
+      if (S.overflow || S.ctot[0] + S.ctot[1] + S.ctot[2] > STAGE_CAP) {
+        // too many pages or records for one round: clear and split by one
+        // more hash bit
+        for (u32 i = tid; i < PT_SLOTS; i += BK_BLOCK) { S.pkey[i] = EMPTY; S.pcnt[i] = 0; }
+        __syncthreads();
+        if (tid == 0) {
+          S.npages = 0; S.overflow = 0; S.redos += 1;
+          if (M >= (1u << 30) || S.sp_top + 2 > 32) {
+            atomicAdd(&A.acc->bad_mem, 1ull);   // hash bits exhausted: report, never spin
+          } else {
+            S.stack_m[S.sp_top] = 2 * M; S.stack_c[S.sp_top] = C;
+            S.stack_m[S.sp_top + 1] = 2 * M; S.stack_c[S.sp_top + 1] = C + M;
+            S.sp_top += 2;
+          }
+        }
+        __syncthreads();
+        continue;
+      }
       if (tid == 0) { S.ccur[0] = 0; S.ccur[1] = S.ctot[0]; S.ccur[2] = S.ctot[0] + S.ctot[1]; }
       __syncthreads();
       for (u32 j0 = 0; j0 < np; j0 += BK_BLOCK) {
@@ -552,7 +660,7 @@ __global__ void __launch_bounds__(BK_BLOCK) k_mem_bucket(TraceArgs A0, const Tra
         u32 c = 0, cl = 3;
         if (j < np) {
           c = S.psz[j];
-          cl = c <= SMALL ? (u32)((S.pkey[S.pslot[j]] >> sbit) & 1ull) : 2u;
+          cl = c <= SMALL ? (u32)((S.pkey[S.pslot[j]] >> sbit) & 1ull) : (c <= HEAVY ? 2u : 3u);
         }
 #pragma unroll
         for (u32 q = 0; q < 3; ++q) {
@@ -584,34 +692,45 @@ __global__ void __launch_bounds__(BK_BLOCK) k_mem_bucket(TraceArgs A0, const Tra
           const u64 pk = rv[u] >> 11;
           if (((u32)pk & (M - 1u)) != C) continue;
           const u32 ci = S.pidx[pt_find(S, pk)];
+          if (S.psz[ci] > HEAVY) continue;
           const u32 pos = atomicAdd(&S.pend[ci], 1u);
-          staging[base + pos] = (ci << 11) | (u32)(rv[u] & 2047ull);
+          S.stage[pos] = (ci << 11) | (u32)(rv[u] & 2047ull);
         }
       }
-      __threadfence_block();
       __syncthreads();
       const u32 nb0 = S.nbig0, nb1 = S.nbig1;
       // ---- 3a. heavy pages: counted by the whole block into dense[0]
       if (S.nheavy) {
         for (u32 bi = 0; bi < nb0 + nb1; ++bi) {
           const u32 ci = S.big[bi < nb0 ? bi : PT_CAP - 1 - (bi - nb0)];
-          const u32 sz = S.psz[ci];
-          if (sz <= HEAVY) continue;
-          const u32 o1 = S.pend[ci], o0 = o1 - sz;
+          if (S.psz[ci] <= HEAVY) continue;
+          const u64 hk = S.pkey[S.pslot[ci]];
           for (u32 i = tid; i < 1024; i += BK_BLOCK) S.dense[0][i] = 0;
           if (tid < 32) { S.rbits[0][tid] = 0; S.wbits[0][tid] = 0; }
           __syncthreads();
-          for (u32 i = o0 + tid; i < o1; i += BK_BLOCK) {
-            const u32 v = staging[base + i];
-            const u32 off = (v >> 1) & 1023u;
-            atomicAdd(&S.dense[0][off], 1u);
-            atomicOr((v & 1u) ? &S.wbits[0][off >> 5] : &S.rbits[0][off >> 5], 1u << (off & 31u));
+          for (u32 i0 = tid; i0 < n; i0 += BK_BLOCK * UNROLL) {
+            u64 rv[UNROLL];
+#pragma unroll
+            for (int u = 0; u < UNROLL; ++u) {
+              const u32 i = i0 + (u32)u * BK_BLOCK;
+              rv[u] = i < n ? A.part_rec[base + i] : EMPTY;
+            }
+#pragma unroll
+            for (int u = 0; u < UNROLL; ++u) {
+              if (rv[u] == EMPTY || (rv[u] >> 11) != hk) continue;
+              const u32 off = (u32)(rv[u] >> 1) & 1023u;
+              atomicAdd(&S.dense[0][off], 1u);
+              atomicOr((rv[u] & 1u) ? &S.wbits[0][off >> 5] : &S.rbits[0][off >> 5],
+                       1u << (off & 31u));
+            }
           }
           __syncthreads();
           if (wave == 0) {
             const int sp = bi < nb0 ? 0 : 1;
-            if (sp != L.space) { lacc_flush(L, S); L.space = sp; }
-            page_levels(L, S, G, S.dense[0], S.rbits[0], S.wbits[0], sp ? N1 : N0);
+            LaneAcc H;
+            lacc_clear(H, sp);
+            page_levels<false>(H, S, G, S.dense[0], S.rbits[0], S.wbits[0], sp ? N1 : N0);
+            lacc_flush(H, S);
           }
           __syncthreads();
         }
@@ -624,6 +743,8 @@ __global__ void __launch_bounds__(BK_BLOCK) k_mem_bucket(TraceArgs A0, const Tra
         const u32 e0 = W0, e1 = e0 + nb0, e2 = e1 + W1, e3 = e2 + nb1;
         u32 *dn = S.dense[wave];
         u32 *rb = S.rbits[wave], *wb = S.wbits[wave];
+        LaneAcc L;
+        lacc_clear(L, 0);
         while (true) {
           u32 it = 0;
           if (lane == 0) it = atomicAdd(&S.next_item, 1u);
@@ -640,12 +761,12 @@ __global__ void __launch_bounds__(BK_BLOCK) k_mem_bucket(TraceArgs A0, const Tra
             u32 v = 0;
             u64 pm = 0;
             if (i < rend) {
-              v = staging[base + i];
+              v = S.stage[i];
               const u32 ci = v >> 11;
               const u32 sz = S.psz[ci], st = S.pend[ci] - sz;
               if (st >= lo && st < lo + SMALL) pm = low_mask(sz) << (st - lo);
             }
-            match_levels(L, S, G, (v >> 1) & 1023u, v & 1u, pm, N);
+            match_levels(L, S, (v >> 1) & 1023u, v & 1u, pm);
             continue;
           }
           const u32 ci = S.big[(it < e1) ? it - e0 : PT_CAP - 1 - (it - e2)];
@@ -653,9 +774,8 @@ __global__ void __launch_bounds__(BK_BLOCK) k_mem_bucket(TraceArgs A0, const Tra
           if (sz > HEAVY) continue;
           const u32 o1 = S.pend[ci], o0 = o1 - sz;
           if (sz <= MEDIUM) {
-            const u32 v = (u32)lane < sz ? staging[base + o0 + lane] : 0u;
-            match_levels(L, S, G, (v >> 1) & 1023u, v & 1u, (u32)lane < sz ? low_mask(sz) : 0ull,
-                         N);
+            const u32 v = (u32)lane < sz ? S.stage[o0 + lane] : 0u;
+            match_levels(L, S, (v >> 1) & 1023u, v & 1u, (u32)lane < sz ? low_mask(sz) : 0ull);
             continue;
           }
           uint4 *z = reinterpret_cast<uint4 *>(dn + 16 * lane);
@@ -668,7 +788,7 @@ __global__ void __launch_bounds__(BK_BLOCK) k_mem_bucket(TraceArgs A0, const Tra
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
               const u32 i = i0 + (u32)u * AIWC_WAVE;
-              vv[u] = i < o1 ? staging[base + i] : ~0u;
+              vv[u] = i < o1 ? S.stage[i] : ~0u;
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
@@ -680,11 +800,20 @@ __global__ void __launch_bounds__(BK_BLOCK) k_mem_bucket(TraceArgs A0, const Tra
           }
           __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
           __builtin_amdgcn_wave_barrier();
-          page_levels(L, S, G, dn, rb, wb, N);
+          page_levels<true>(L, S, G, dn, rb, wb, N);
           __builtin_amdgcn_wave_barrier();
         }
+        lacc_flush(L, S);
       }
       __syncthreads();
+      // ---- the round's dense-tree nodes of count >= 256
+      for (u32 i = tid; i < S.nblist; i += BK_BLOCK) {
+        const u32 e = S.blist[i];
+        const int sp = (int)(e >> 31);
+        big_node(S, G, sp, (int)((e >> 24) & 127u), e & 0xFFFFFFu, sp ? N1 : N0);
+      }
+      __syncthreads();
+      if (tid == 0) S.nblist = 0;
       // ---- release the page table for the next round / partition
       for (u32 j = tid; j < np; j += BK_BLOCK) {
         const u32 slot = S.pslot[j];
@@ -696,13 +825,14 @@ __global__ void __launch_bounds__(BK_BLOCK) k_mem_bucket(TraceArgs A0, const Tra
       __syncthreads();
     }
   }
-  // ---- flush the lanes' and the block's accumulators
-  lacc_flush(L, S);
+  // ---- flush the block's accumulators
   __syncthreads();
   if (tid < 2 * AIWC_NSKIP) {
     const int s = tid / AIWC_NSKIP, k = tid % AIWC_NSKIP;
     if (S.dist[s][k]) atomicAdd(&A.acc->distinct[s][k], S.dist[s][k]);
-    atomic_add_u128(&A.acc->ent_lo[s][k], &A.acc->ent_hi[s][k], S.elo[s][k], S.ehi[s][k]);
+    // 2^-40 units -> the 2^-64 units of the trace accumulators
+    atomic_add_u128(&A.acc->ent_lo[s][k], &A.acc->ent_hi[s][k], S.elo[s][k] << 24,
+                    (S.ehi[s][k] << 24) | (S.elo[s][k] >> 40));
   }
   if (tid < 2) {
     if (S.ur[tid]) atomicAdd(&A.acc->uniq_r[tid], S.ur[tid]);

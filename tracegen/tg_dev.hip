@@ -118,6 +118,7 @@ void *tg_dev_plan(const tg_params *Pin, const uint32_t *zipf_cdf,
       Pin->n_compute_ids == 0 || Pin->n_sites == 0 || Pin->sweep_words == 0 ||
       Pin->random_words == 0 || Pin->local_words == 0 || Pin->stencil_dim < 3)
     return nullptr;
+  (void)hipGetLastError();   // an error left by an earlier, unrelated call is not ours
   DevPlan *d = new DevPlan();
   d->P = *Pin;
   tg_params &P = d->P;
