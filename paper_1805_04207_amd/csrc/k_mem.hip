@@ -254,7 +254,8 @@ struct BucketShared {
   u64 term[2][256];                // c*log2(N_s/c) for c < 256, 2^-40 units
   u32 spec[2][SPEC_LDS];           // level-0 nodes of count c, 2 <= c < SPEC_LDS
   u64 spf[2][SPEC_SLOTS], spm[2][SPEC_SLOTS];
-  u64 dist[2][AIWC_NSKIP], elo[2][AIWC_NSKIP], ehi[2][AIWC_NSKIP];   // entropy: 2^-40 units
+  u64 dist[2][AIWC_NSKIP];
+  u64 el[2][AIWC_NSKIP][3];        // entropy, 2^-40 units: el0 + el1 * 2^32 + el2 * 2^64
   u64 ur[2], uw[2];
   u64 redos;
   uint16_t big[PT_CAP];            // pages > SMALL: space 0 from the front, 1 from the back
@@ -333,24 +334,54 @@ __device__ __forceinline__ void add128(u64 &lo, u64 &hi, u64 tl, u64 th) {
 }
 
 
+// Sum over each row of 16 lanes by DPP butterflies (lane ^ 1, lane ^ 2, half
+// row mirror, row mirror); every lane of the wavefront must be active.
+__device__ __forceinline__ u32 dpp_row_sum(u32 v) {
+  v += (u32)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false);
+  v += (u32)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false);
+  v += (u32)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false);
+  v += (u32)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false);
+  return v;
+}
+
+// Wavefront sum of values below 2^26, as a wave-uniform value.
+__device__ __forceinline__ u32 wave_total(u32 v) {
+  v = dpp_row_sum(v);
+  return (u32)__builtin_amdgcn_readlane((int)v, 0) + (u32)__builtin_amdgcn_readlane((int)v, 16) +
+         (u32)__builtin_amdgcn_readlane((int)v, 32) + (u32)__builtin_amdgcn_readlane((int)v, 48);
+}
+
+// Adds a 2^-40-unit value, given as 32-bit-aligned pieces, to a level's limbs.
+__device__ __forceinline__ void limbs_add(u64 *el, u64 l0, u64 l1, u64 l2) {
+  if (l0) atomicAdd(&el[0], l0);
+  if (l1) atomicAdd(&el[1], l1);
+  if (l2) atomicAdd(&el[2], l2);
+}
+
+// Called by the whole wavefront (no lane masked off).  Lane sums are below
+// 2^63 (terms) and 2^16 (counts); they are cut into 24-bit pieces so that
+// every wavefront sum fits 32 bits.
 __device__ __forceinline__ void lacc_flush(LaneAcc &L, BucketShared &S) {
   const int s = L.space;
   const int lane = lane_id();
   const u64 t1 = S.term[s][1];
 #pragma unroll
   for (int k = 0; k < AIWC_NSKIP; ++k) {
-    u64 lo = wave_sum_u64(L.lo[k]), hi = 0;
-    const u64 dn = wave_sum_u64((u64)(L.dn[k] & 0xFFFFu) | ((u64)(L.dn[k] >> 16) << 32));
-    const u64 d = dn & 0xFFFFFFFFull, n1 = dn >> 32;
+    const u64 lo = L.lo[k];
+    const u64 a0 = wave_total((u32)lo & 0xFFFFFFu);
+    const u64 a1 = wave_total((u32)(lo >> 24) & 0xFFFFFFu);
+    const u64 a2 = wave_total((u32)(lo >> 48));
+    const u64 d = wave_total(L.dn[k] & 0xFFFFu), n1 = wave_total(L.dn[k] >> 16);
+    // a0 + a1 * 2^24 + a2 * 2^48 + n1 * log2(N)
+    const u64 plo = t1 * n1, phi = __umul64hi(t1, n1);
     if (lane == 0) {
-      // + n1 * log2(N): 128-bit product of the fixed-point term and the count
-      add128(lo, hi, t1 * n1, __umul64hi(t1, n1));
-      atomic_add_u128(&S.elo[s][k], &S.ehi[s][k], lo, hi);
+      limbs_add(S.el[s][k], a0 + ((a1 & 0xFFull) << 24) + (plo & 0xFFFFFFFFull),
+                (a1 >> 8) + (a2 << 16) + (plo >> 32), phi);
       if (d) atomicAdd(&S.dist[s][k], d);
       if (k == 0 && n1) atomicAdd(&S.spec[s][1], (u32)n1);
     }
   }
-  const u64 r = wave_sum_u64(L.ur), w = wave_sum_u64(L.uw);
+  const u64 r = wave_total(L.ur), w = wave_total(L.uw);
   if (lane == 0) {
     if (r) atomicAdd(&S.ur[s], r);
     if (w) atomicAdd(&S.uw[s], w);
@@ -372,7 +403,7 @@ __device__ __forceinline__ void big_node(BucketShared &S, SpecRef G, int s, int 
                                          u64 N) {
   u64 lo, hi;
   term_fx(v, N, lo, hi);
-  atomic_add_u128(&S.elo[s][k], &S.ehi[s][k], lo, hi);
+  limbs_add(S.el[s][k], lo & 0xFFFFFFFFull, lo >> 32, hi);
   atomicAdd(&S.dist[s][k], 1ull);
   if (k == 0) spec_cache_add(S, G, (u32)s, v, 1ull);
 }
@@ -554,7 +585,10 @@ __global__ void __launch_bounds__(BK_BLOCK) k_mem_bucket(TraceArgs A0, const Tra
     (&S.spm[0][0])[i] = 0;
   }
   if (tid < 2 * AIWC_NSKIP) {
-    (&S.dist[0][0])[tid] = 0; (&S.elo[0][0])[tid] = 0; (&S.ehi[0][0])[tid] = 0;
+    (&S.dist[0][0])[tid] = 0;
+    S.el[tid / AIWC_NSKIP][tid % AIWC_NSKIP][0] = 0;
+    S.el[tid / AIWC_NSKIP][tid % AIWC_NSKIP][1] = 0;
+    S.el[tid / AIWC_NSKIP][tid % AIWC_NSKIP][2] = 0;
   }
   if (tid < 2) { S.ur[tid] = 0; S.uw[tid] = 0; }
   if (tid == 0) { S.redos = 0; S.npages = 0; S.overflow = 0; S.nblist = 0; }
@@ -830,9 +864,12 @@ __global__ void __launch_bounds__(BK_BLOCK) k_mem_bucket(TraceArgs A0, const Tra
   if (tid < 2 * AIWC_NSKIP) {
     const int s = tid / AIWC_NSKIP, k = tid % AIWC_NSKIP;
     if (S.dist[s][k]) atomicAdd(&A.acc->distinct[s][k], S.dist[s][k]);
-    // 2^-40 units -> the 2^-64 units of the trace accumulators
-    atomic_add_u128(&A.acc->ent_lo[s][k], &A.acc->ent_hi[s][k], S.elo[s][k] << 24,
-                    (S.ehi[s][k] << 24) | (S.elo[s][k] >> 40));
+    // limbs -> 128 bits, then 2^-40 units -> the 2^-64 units of the trace
+    const u64 *el = S.el[s][k];
+    const u64 lo = el[0] + (el[1] << 32);
+    const u64 hi = (el[1] >> 32) + el[2] + (lo < el[0] ? 1ull : 0ull);
+    atomic_add_u128(&A.acc->ent_lo[s][k], &A.acc->ent_hi[s][k], lo << 24,
+                    (hi << 24) | (lo >> 40));
   }
   if (tid < 2) {
     if (S.ur[tid]) atomicAdd(&A.acc->uniq_r[tid], S.ur[tid]);
