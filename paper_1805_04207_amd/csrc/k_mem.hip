@@ -408,6 +408,12 @@ __device__ __forceinline__ void big_node(BucketShared &S, SpecRef G, int s, int 
   if (k == 0) spec_cache_add(S, G, (u32)s, v, 1ull);
 }
 
+// Dense byte-offset counters are stored swizzled: offset o sits at word
+// o ^ (((o >> 5) & 3) << 2), still inside o's group of 16, so that the
+// 16-word groups of eight neighbouring lanes cover all 32 LDS banks (and
+// 16-byte strided offsets spread over 8 banks instead of 2).
+__device__ __forceinline__ u32 cslot(u32 off) { return off ^ (((off >> 5) & 3u) << 2); }
+
 // The nodes of count >= 256 of the dense tree over cnt[1024] (see
 // page_levels).  Few pages have any: plain loops, so that the logarithm is
 // emitted twice rather than once per node (and no call spills registers).
@@ -415,13 +421,14 @@ __device__ __forceinline__ void big_pass(BucketShared &S, SpecRef G, const u32 *
                                          u64 N) {
   const int lane = lane_id();
   const u32 *my = cnt + 16 * lane;
+  const u32 sw = (((u32)lane >> 1) & 3u) << 2;
 #pragma unroll 1
   for (int k = 0; k <= 4; ++k) {
 #pragma unroll 1
     for (int j = 0; j < (16 >> k); ++j) {
       u32 v = 0;
 #pragma unroll 1
-      for (int q = 0; q < (1 << k); ++q) v += my[(j << k) + q];
+      for (int q = 0; q < (1 << k); ++q) v += my[((j << k) + q) ^ sw];
       if (v >= 256) big_node(S, G, s, k, v, N);
     }
   }
@@ -448,6 +455,7 @@ __device__ __forceinline__ void big_pass(BucketShared &S, SpecRef G, const u32 *
 __device__ __forceinline__ void big_collect(BucketShared &S, const u32 *cnt, int s) {
   const int lane = lane_id();
   const u32 *my = cnt + 16 * lane;
+  const u32 sw = (((u32)lane >> 1) & 3u) << 2;
   const u32 tag = (u32)s << 31;
 #pragma unroll 1
   for (int k = 0; k <= 4; ++k) {
@@ -455,7 +463,7 @@ __device__ __forceinline__ void big_collect(BucketShared &S, const u32 *cnt, int
     for (int j = 0; j < (16 >> k); ++j) {
       u32 v = 0;
 #pragma unroll 1
-      for (int q = 0; q < (1 << k); ++q) v += my[(j << k) + q];
+      for (int q = 0; q < (1 << k); ++q) v += my[((j << k) + q) ^ sw];
       if (v >= 256) S.blist[atomicAdd(&S.nblist, 1u)] = tag | ((u32)k << 24) | v;
     }
   }
@@ -472,10 +480,11 @@ __device__ __forceinline__ void big_collect(BucketShared &S, const u32 *cnt, int
 
 // All levels of one page whose byte-offset counts sit in cnt[1024] (LDS,
 // owned by this wavefront) and whose read / write bitmaps in rb[32], wb[32].
-// Lane l loads counters 16l..16l+15: levels 0..4 are sums inside the lane,
-// levels 5..10 sums across 2, 4, .., 64 lanes (the lowest lane owns the
-// node).  Counts below 256 are accumulated in one pass; if any node reaches
-// 256, a second pass walks the tree again for those nodes only.
+// Lane l loads counters 16l..16l+15 (swizzled, see cslot): levels 0..4 are
+// sums inside the lane, levels 5..10 sums across 2, 4, .., 64 lanes (the
+// lowest lane owns the node).  Counts below 256 are accumulated in one pass;
+// if any node reaches 256, a second pass walks the tree again for those
+// nodes only.
 template <bool DEFER>
 __device__ __forceinline__ void page_levels(LaneAcc &L, BucketShared &S, SpecRef G,
                                             const u32 *cnt, const u32 *rb, const u32 *wb,
@@ -483,10 +492,11 @@ __device__ __forceinline__ void page_levels(LaneAcc &L, BucketShared &S, SpecRef
   const int lane = lane_id();
   const int s = L.space;
   const uint4 *src = reinterpret_cast<const uint4 *>(cnt + 16 * lane);
+  const u32 sw = ((u32)lane >> 1) & 3u;
   u32 c[16];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    const uint4 x = src[q];
+    const uint4 x = src[q ^ sw];
     c[4 * q] = x.x; c[4 * q + 1] = x.y; c[4 * q + 2] = x.z; c[4 * q + 3] = x.w;
   }
   if (lane < 32) {
@@ -554,6 +564,14 @@ __device__ __forceinline__ void match_levels(LaneAcc &L, BucketShared &S, u32 of
   }
 }
 
+// Runs of equal keys among the lanes (records of one page often arrive
+// together): returns the lanes that end a run; lane 63 always does.
+__device__ __forceinline__ u64 run_ends(u64 key) {
+  const int lane = lane_id();
+  const u64 next = __shfl_down(key, 1, 64);
+  return __ballot(lane == 63 || next != key);
+}
+
 __device__ __forceinline__ u32 pt_find(const BucketShared &S, u64 pk) {
   u32 slot = hash_slot(pk, PT_SLOTS);
   while (S.pkey[slot] != pk) slot = (slot + 1 == PT_SLOTS) ? 0 : slot + 1;
@@ -607,19 +625,23 @@ __global__ void __launch_bounds__(BK_BLOCK) k_mem_bucket(TraceArgs A0, const Tra
       const u32 M = S.stack_m[S.sp_top - 1], C = S.stack_c[S.sp_top - 1];
       __syncthreads();
       if (tid == 0) S.sp_top -= 1;
-      // ---- 1. page pass (UNROLL records in flight per thread)
-      for (u32 i0 = tid; i0 < n; i0 += BK_BLOCK * UNROLL) {
+      // ---- 1. page pass (UNROLL records in flight per thread; the first
+      // lane of each run of one page's records counts the whole run)
+      const u64 below = (1ull << lane) - 1ull;
+      for (u32 w0 = (u32)(tid - lane); w0 < n; w0 += BK_BLOCK * UNROLL) {
         u64 rv[UNROLL];
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u) {
-          const u32 i = i0 + (u32)u * BK_BLOCK;
+          const u32 i = w0 + (u32)u * BK_BLOCK + (u32)lane;
           rv[u] = i < n ? A.part_rec[base + i] : EMPTY;
         }
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u) {
-          if (rv[u] == EMPTY) continue;
           const u64 pk = rv[u] >> 11;
-          if (((u32)pk & (M - 1u)) != C) continue;
+          const bool valid = rv[u] != EMPTY && ((u32)pk & (M - 1u)) == C;
+          const u64 ends = run_ends(valid ? pk : EMPTY);
+          if (!valid || (lane > 0 && ((ends >> (lane - 1)) & 1ull) == 0)) continue;
+          const u32 run = (u32)__builtin_ctzll(ends & ~below) - (u32)lane + 1u;
           u32 slot = hash_slot(pk, PT_SLOTS);
           while (true) {
             u64 w = S.pkey[slot];
@@ -635,7 +657,7 @@ __global__ void __launch_bounds__(BK_BLOCK) k_mem_bucket(TraceArgs A0, const Tra
                 w = old;
               }
             }
-            if (w == pk) { atomicAdd(&S.pcnt[slot], 1u); break; }
+            if (w == pk) { atomicAdd(&S.pcnt[slot], run); break; }
             slot = (slot + 1 == PT_SLOTS) ? 0 : slot + 1;
           }
         }
@@ -713,22 +735,31 @@ __global__ void __launch_bounds__(BK_BLOCK) k_mem_bucket(TraceArgs A0, const Tra
         }
       }
       __syncthreads();
-      for (u32 i0 = tid; i0 < n; i0 += BK_BLOCK * UNROLL) {
+      // regroup: the first lane of each run reserves the run's positions
+      for (u32 w0 = (u32)(tid - lane); w0 < n; w0 += BK_BLOCK * UNROLL) {
         u64 rv[UNROLL];
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u) {
-          const u32 i = i0 + (u32)u * BK_BLOCK;
+          const u32 i = w0 + (u32)u * BK_BLOCK + (u32)lane;
           rv[u] = i < n ? A.part_rec[base + i] : EMPTY;
         }
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u) {
-          if (rv[u] == EMPTY) continue;
           const u64 pk = rv[u] >> 11;
-          if (((u32)pk & (M - 1u)) != C) continue;
-          const u32 ci = S.pidx[pt_find(S, pk)];
-          if (S.psz[ci] > HEAVY) continue;
-          const u32 pos = atomicAdd(&S.pend[ci], 1u);
-          S.stage[pos] = (ci << 11) | (u32)(rv[u] & 2047ull);
+          const bool valid = rv[u] != EMPTY && ((u32)pk & (M - 1u)) == C;
+          const u64 ends = run_ends(valid ? pk : EMPTY);
+          const bool head = valid && (lane == 0 || ((ends >> (lane - 1)) & 1ull) != 0);
+          u32 ci = 0, pos = ~0u;
+          if (head) {
+            ci = S.pidx[pt_find(S, pk)];
+            if (S.psz[ci] <= HEAVY)
+              pos = atomicAdd(&S.pend[ci], (u32)__builtin_ctzll(ends & ~below) - (u32)lane + 1u);
+          }
+          const u64 H = __ballot(head) & (below | (1ull << lane));
+          const int hl = H ? 63 - __builtin_clzll(H) : lane;
+          const u32 p0 = __shfl(pos, hl, 64), c0 = __shfl(ci, hl, 64);
+          if (valid && p0 != ~0u)
+            S.stage[p0 + (u32)(lane - hl)] = (c0 << 11) | (u32)(rv[u] & 2047ull);
         }
       }
       __syncthreads();
@@ -753,7 +784,7 @@ __global__ void __launch_bounds__(BK_BLOCK) k_mem_bucket(TraceArgs A0, const Tra
             for (int u = 0; u < UNROLL; ++u) {
               if (rv[u] == EMPTY || (rv[u] >> 11) != hk) continue;
               const u32 off = (u32)(rv[u] >> 1) & 1023u;
-              atomicAdd(&S.dense[0][off], 1u);
+              atomicAdd(&S.dense[0][cslot(off)], 1u);
               atomicOr((rv[u] & 1u) ? &S.wbits[0][off >> 5] : &S.rbits[0][off >> 5],
                        1u << (off & 31u));
             }
@@ -828,7 +859,7 @@ __global__ void __launch_bounds__(BK_BLOCK) k_mem_bucket(TraceArgs A0, const Tra
             for (int u = 0; u < 4; ++u) {
               if (vv[u] == ~0u) continue;
               const u32 off = (vv[u] >> 1) & 1023u;
-              atomicAdd(&dn[off], 1u);
+              atomicAdd(&dn[cslot(off)], 1u);
               atomicOr((vv[u] & 1u) ? &wb[off >> 5] : &rb[off >> 5], 1u << (off & 31u));
             }
           }
