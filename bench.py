@@ -19,6 +19,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "trace events/sec and % HBM peak, batched+learned-sizing vs plain, bit-exact"
 HBM_PEAK_GBS = 8000.0
+COPY_BYTES = 1 << 30          # the plain copy that calibrates the traffic counters
+
+
+def workload_tag(n_wi_log2: int) -> str:
+    return f"plain_large_trace_2p{n_wi_log2}"
 
 
 def algorithmic_bytes(name: str, n_ev: int, n_wi: int, n_mem: int, n_br: int, passes: int) -> float:
@@ -116,6 +121,9 @@ def main() -> int:
     ap.add_argument("--batch-traces", type=int, default=512)
     ap.add_argument("--batch-scale", type=float, default=0.05,
                     help="config3 lengths are scaled by this factor")
+    ap.add_argument("--pmc-probe", action="store_true",
+                    help="one characterization, then a plain device copy of 1 GiB, for "
+                         "rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs; prints no JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the multi-GPU sharding "
@@ -144,6 +152,14 @@ def main() -> int:
         r = ctx.characterize(tr, stream).read()
     print(f"# warmup done: H0={r['space'][0]['entropy'][0]:.6f} redos={r['overflow_redos']}",
           file=sys.stderr, flush=True)
+    if args.pmc_probe:
+        src = torch.ones(COPY_BYTES, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"# pmc probe: 1 characterization + {COPY_BYTES}-byte copy", file=sys.stderr)
+        return 0
 
     ctx.profile_enable(True)
     per_kernel = {}
@@ -167,6 +183,9 @@ def main() -> int:
     comp_gbs = compulsory / (ms_step * 1e-3) / 1e9
     print("# per-kernel ms: " + ", ".join(f"{k}={v:.3f}" for k, v in avg.items()),
           file=sys.stderr, flush=True)
+    from paper_1805_04207_amd.profile_summary import read_traffic
+    tpath = os.path.join(ROOT, "profiles", f"traffic_{dom}_{workload_tag(args.n_wi_log2)}.md")
+    trec = read_traffic(tpath, dom, workload_tag(args.n_wi_log2))
 
     batched = None
     if not args.no_batch:
@@ -199,7 +218,10 @@ def main() -> int:
                    "kernel_ms": avg, "partitions": r["partitions"],
                    "overflow_redos": r["overflow_redos"], "batched": batched},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None},
+                     "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                     "traffic": trec["traffic_bytes"] if trec else None,
+                     "algorithmic_bytes": algorithmic_bytes(dom, n_ev, n_wi, n_mem, n_br, passes),
+                     "kernel_ms": avg[dom]},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

@@ -48,6 +48,8 @@ def build_dataset(ctx, n: int, seed: int, wi_lo: float, wi_hi: float, batch: int
             labels.append([np.log2(1.0 + r["space"][0]["distinct"][k]) for k in range(11)])
         feats.append(x)
         del keep, trs
+        if (b0 // batch) % 8 == 7:
+            print(f"# labelled {min(n, b0 + batch)} / {n} traces", file=sys.stderr, flush=True)
     x = torch.cat(feats)
     y = torch.tensor(np.array(labels, dtype=np.float32), device=x.device)
     return x, y
