@@ -116,7 +116,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n-wi-log2", type=int, default=20, help="work-items = 2^x (config2 recipe)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-wi-log2", type=int, default=15)
+    ap.add_argument("--cpu-sample-wi-log2", type=int, default=17)
     ap.add_argument("--no-batch", action="store_true", help="skip the batched legs")
     ap.add_argument("--batch-traces", type=int, default=512)
     ap.add_argument("--batch-scale", type=float, default=0.05,
