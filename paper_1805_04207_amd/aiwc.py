@@ -112,6 +112,10 @@ def load_library(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with __graft_entry__.build()")
+    # torch ships its own HIP runtime under the same soname; load it first so
+    # that the library binds to it and one runtime serves the whole process
+    # (loading ours first would leave torch with a runtime it cannot use)
+    import torch  # noqa: F401
     L = ctypes.CDLL(path)
     vp, u64, sz = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_size_t
     st = ctypes.c_int

@@ -97,6 +97,15 @@ __device__ __forceinline__ const TraceArgs &trace_args(const TraceArgs &A0,
 // ------------------------------------------------------------ device math
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
+// Runs of equal keys among neighbouring lanes: the lanes that end a run
+// (lane 63 always does).  The shuffle runs on every lane: a lane left out of
+// a cross-lane read would hand its neighbour a stale value.
+__device__ __forceinline__ u64 run_ends(u64 key) {
+  const int lane = lane_id();
+  const u64 next = __shfl_down(key, 1, 64);
+  return __ballot(lane == 63 || next != key);
+}
+
 __device__ __forceinline__ u64 wave_sum_u64(u64 v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);

@@ -32,7 +32,7 @@ constexpr int BR_ROUNDS = BR_TILE / BR_BLOCK; // 16
 constexpr int WIN_BLOCK = 1024;
 constexpr u64 WIN_T = 4096;                   // windows work-block size
 constexpr u32 WT_C = 8192;                    // LDS table slots
-constexpr u32 WT_CAP = 6656;
+constexpr u32 WT_CAP = 4096;
 constexpr u64 EMPTY = ~0ull;
 
 // ------------------------------------------------------------------ pack
@@ -256,7 +256,7 @@ struct WinShared {
   uint16_t live[WT_C];
   u64 tlo[256], thi[256];     // Yokota terms for n0, n1 < 16
   u64 minsum, windows, ylo, yhi;
-  u32 live_n, overflow, work;
+  u32 live_n, overflow, next;
   u32 stack_m[64], stack_c[64];
   u32 sp_top;
 };
@@ -278,24 +278,25 @@ __device__ __forceinline__ u64 range_begin(const TraceArgs &A, const u32 *sorted
   return A.seg_end[s];
 }
 
-__device__ __forceinline__ bool win_insert(WinShared &S, u64 key, u32 y) {
+// Adds (a, b) to the counts of key.  Returns the slot, with fresh set when
+// the key was new, or WT_C when the table is over its cap.  The live count
+// lags by at most one block step of insertions (< WT_C - WT_CAP), so the table
+// never fills.
+__device__ __forceinline__ u32 win_insert(WinShared &S, u64 key, u32 a, u32 b, bool &fresh) {
   u32 slot = hash_slot(key, WT_C);
+  fresh = false;
   while (true) {
     u64 w = S.key[slot];
     if (w == EMPTY) {
-      if (S.live_n >= WT_CAP) { S.overflow = 1; return false; }
+      if (S.live_n >= WT_CAP) { S.overflow = 1; return WT_C; }
       u64 old = atomicCAS(&S.key[slot], EMPTY, key);
-      if (old == EMPTY) {
-        u32 idx = atomicAdd(&S.live_n, 1u);
-        if (idx < WT_C) S.live[idx] = (uint16_t)slot;
-        w = key;
-      } else {
-        w = old;
-      }
+      if (old == EMPTY) { fresh = true; w = key; }
+      else w = old;
     }
     if (w == key) {
-      atomicAdd(y ? &S.n1[slot] : &S.n0[slot], 1u);
-      return true;
+      if (a) atomicAdd(&S.n0[slot], a);
+      if (b) atomicAdd(&S.n1[slot], b);
+      return slot;
     }
     slot = (slot + 1 == WT_C) ? 0 : slot + 1;
   }
@@ -310,15 +311,22 @@ __global__ void __launch_bounds__(WIN_BLOCK) k_br_windows(TraceArgs A0, const Tr
   const int tid = threadIdx.x, lane = lane_id(), wave = tid / AIWC_WAVE;
   const u32 m = A.m;
   const u64 hmask = (m >= 64) ? ~0ull : ((1ull << m) - 1ull);
+  const u64 below = (1ull << lane) - 1ull;
   for (u32 i = tid; i < WT_C; i += WIN_BLOCK) { S.key[i] = EMPTY; S.n0[i] = 0; S.n1[i] = 0; }
   if (tid < 256) yterm(tid >> 4, tid & 15, S.tlo[tid], S.thi[tid]);
-  if (tid == 0) { S.minsum = S.windows = S.ylo = S.yhi = 0; S.live_n = 0; S.overflow = 0; }
+  if (tid == 0) {
+    S.minsum = S.windows = S.ylo = S.yhi = 0; S.live_n = 0; S.overflow = 0;
+    S.next = (u32)atomicAdd(&A.acc->br_queue, 1ull);
+  }
+  // per-thread sums over all work blocks, reduced once at the end
+  u64 mins = 0, wins = 0, lo = 0, hi = 0;
   __syncthreads();
   while (true) {
-    if (tid == 0) S.work = (u32)atomicAdd(&A.acc->br_queue, 1ull);
-    __syncthreads();
-    const u64 b = S.work;
+    const u64 b = S.next;
     if (b >= A.br_blocks) break;
+    __syncthreads();
+    // the next work block is fetched while this one is processed
+    if (tid == 0) S.next = (u32)atomicAdd(&A.acc->br_queue, 1ull);
     const u64 r0 = range_begin(A, sorted, b), r1 = range_begin(A, sorted, b + 1);
     if (r1 <= r0) { __syncthreads(); continue; }
     if (tid == 0) { S.sp_top = 1; S.stack_m[0] = 1; S.stack_c[0] = 0; }
@@ -347,17 +355,38 @@ __global__ void __launch_bounds__(WIN_BLOCK) k_br_windows(TraceArgs A0, const Tr
           const u32 v = pv[q], vp = pp[q];
           const u64 B = __ballot(valid && (v & 1u));
           const u64 Bp = __ballot((cb >= AIWC_WAVE) && (vp & 1u));
-          if (!valid || stop) continue;
           const u32 s = v >> 1;
-          if (i - A.seg_start[s] < m) continue;
           const u32 sh = 64u + (u32)lane - m;           // in [32, 127]
           u64 E;
           if (sh >= 64) E = B >> (sh - 64);
           else E = (Bp >> sh) | (B << (64 - sh));
           E &= hmask;
           const u64 key = ((u64)s << m) | E;
-          if (M > 1 && (((u32)((key * 0x9E3779B97F4A7C15ull) >> 40)) & (M - 1u)) != C) continue;
-          if (!win_insert(S, key, v & 1u)) stop = true;
+          const bool use = valid && i - A.seg_start[s] >= m &&
+                           (M == 1 || (((u32)((key * 0x9E3779B97F4A7C15ull) >> 40)) & (M - 1u)) == C);
+          // runs of one key among neighbouring lanes (biased sites repeat
+          // their history) are added once, by their first lane
+          const u64 ends = run_ends(use ? key : EMPTY);
+          const u64 Y = __ballot(use && (v & 1u));
+          const bool head = use && (lane == 0 || ((ends >> (lane - 1)) & 1ull) != 0);
+          bool fresh = false;
+          u32 slot = WT_C;
+          if (head && !stop) {
+            const u32 e = (u32)__builtin_ctzll(ends & ~below);
+            const u64 run = (e == 63 ? ~0ull : ((1ull << (e + 1)) - 1ull)) & ~below;
+            const u32 ones = (u32)__builtin_popcountll(Y & run), len = e - (u32)lane + 1u;
+            slot = win_insert(S, key, len - ones, ones, fresh);
+            if (slot == WT_C) stop = true;
+          }
+          // new keys join the live list: one counter update per wavefront
+          const u64 F = __ballot(fresh);
+          if (F) {
+            u32 base = 0;
+            if (lane == 0) base = atomicAdd(&S.live_n, (u32)__builtin_popcountll(F));
+            base = __shfl(base, 0, 64);
+            const u32 idx = base + (u32)__builtin_popcountll(F & below);
+            if (fresh && idx < WT_C) S.live[idx] = (uint16_t)slot;
+          }
         }
       }
       __syncthreads();
@@ -381,7 +410,6 @@ __global__ void __launch_bounds__(WIN_BLOCK) k_br_windows(TraceArgs A0, const Tr
         __syncthreads();
         continue;
       }
-      u64 mins = 0, wins = 0, lo = 0, hi = 0;
       for (u32 j = tid; j < D; j += WIN_BLOCK) {
         const u32 slot = S.live[j];
         const u32 a = S.n0[slot], c = S.n1[slot];
@@ -393,19 +421,19 @@ __global__ void __launch_bounds__(WIN_BLOCK) k_br_windows(TraceArgs A0, const Tr
         u64 nl = lo + tl; hi += th + (nl < lo); lo = nl;
         S.key[slot] = EMPTY; S.n0[slot] = 0; S.n1[slot] = 0;
       }
-      mins = wave_sum_u64(mins);
-      wins = wave_sum_u64(wins);
-      wave_sum_u128(lo, hi);
-      if (lane == 0) {
-        if (mins) atomicAdd(&S.minsum, mins);
-        if (wins) atomicAdd(&S.windows, wins);
-        atomic_add_u128(&S.ylo, &S.yhi, lo, hi);
-      }
       __syncthreads();
       if (tid == 0) S.live_n = 0;
       __syncthreads();
     }
     __syncthreads();
+  }
+  mins = wave_sum_u64(mins);
+  wins = wave_sum_u64(wins);
+  wave_sum_u128(lo, hi);
+  if (lane == 0) {
+    if (mins) atomicAdd(&S.minsum, mins);
+    if (wins) atomicAdd(&S.windows, wins);
+    atomic_add_u128(&S.ylo, &S.yhi, lo, hi);
   }
   __syncthreads();
   if (tid == 0) {

@@ -564,14 +564,6 @@ __device__ __forceinline__ void match_levels(LaneAcc &L, BucketShared &S, u32 of
   }
 }
 
-// Runs of equal keys among the lanes (records of one page often arrive
-// together): returns the lanes that end a run; lane 63 always does.
-__device__ __forceinline__ u64 run_ends(u64 key) {
-  const int lane = lane_id();
-  const u64 next = __shfl_down(key, 1, 64);
-  return __ballot(lane == 63 || next != key);
-}
-
 __device__ __forceinline__ u32 pt_find(const BucketShared &S, u64 pk) {
   u32 slot = hash_slot(pk, PT_SLOTS);
   while (S.pkey[slot] != pk) slot = (slot + 1 == PT_SLOTS) ? 0 : slot + 1;
