@@ -40,6 +40,13 @@ def algorithmic_bytes(name: str, n_ev: int, n_wi: int, n_mem: int, n_br: int, pa
     }.get(name, 0.0)
 
 
+def strip(d: dict) -> str:
+    """Metrics without the sizing diagnostics, as text (NaN ratios of an
+    empty address space then compare equal)."""
+    return json.dumps({k: v for k, v in d.items() if k not in ("overflow_redos", "partitions")},
+                      sort_keys=True)
+
+
 def batch_legs(ctx, tr, spec, n_ev, args, stream):
     """Batched + learned sizing vs the plain path: (1) the same large trace
     through aiwc_characterize_batch with LEARNED sizing and a replayed
@@ -59,8 +66,7 @@ def batch_legs(ctx, tr, spec, n_ev, args, stream):
     ref = ctx.characterize(tr, stream).read()
     for _ in range(args.warmup):
         got = ctx.characterize_batch([tr], sizing=sizing, use_graph=True, stream=stream)[0].read()
-    same = {k: v for k, v in got.items() if k not in ("overflow_redos", "partitions")} == \
-        {k: v for k, v in ref.items() if k not in ("overflow_redos", "partitions")}
+    same = strip(got) == strip(ref)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -96,7 +102,6 @@ def batch_legs(ctx, tr, spec, n_ev, args, stream):
         got = [m.read() for m in ctx.characterize_batch(trs, **bopts)]
     torch.cuda.synchronize()
     dt_batch = (time.perf_counter() - t0) / max(1, args.steps // 2)
-    strip = lambda d: {k: v for k, v in d.items() if k not in ("overflow_redos", "partitions")}
     st = ctx.batch_stats()
     out["config3"] = {"traces": len(trs), "events": total,
                       "plain_events_per_s": total / dt_plain,
