@@ -110,8 +110,54 @@ def batch_legs(ctx, tr, spec, n_ev, args, stream):
                       "identical": all(strip(a) == strip(b) for a, b in zip(plain, got)),
                       "waves": st["waves"], "redo_partitions": st["redo_partitions"],
                       "total_partitions": st["total_partitions"]}
-    del keep
+    del keep, trs, plain, got
+    if not args.no_stress:
+        out["stress"] = stress_leg(ctx, args, sizing, stream)
     return out
+
+
+def stress_leg(ctx, args, sizing, stream):
+    """The stress batch (config5 recipe: 64 traces, ~2^32 uniform addresses in
+    total, up to 2^28 per trace, 2^16 sites, history 32) in one batched call
+    with learned sizing under a 200 GiB admission cap, vs one plain call per
+    trace."""
+    import torch
+    import tracegen as tg
+    import paper_1805_04207_amd as aiwc
+
+    specs = tg.config5_specs()
+    keep, trs, ev, mem = [], [], 0, 0
+    for sp in specs:
+        d = tg.generate_device(sp, 0)
+        keep.append(d)
+        ev += d["n_events"]
+        mem += d["n_mem"]
+        trs.append(aiwc.device_trace(ctx, d, tg.opcode_table(), sp.n_sites, sp.history_len,
+                                     sp.wg_size))
+    print(f"# stress batch: {len(trs)} traces, {ev} events, {mem} addresses", file=sys.stderr,
+          flush=True)
+    bopts = dict(sizing=sizing, admission_cap_bytes=200 << 30, stream=stream)
+    got = [m.read() for m in ctx.characterize_batch(trs, **bopts)]
+    reps = max(1, args.steps // 3)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        got = [m.read() for m in ctx.characterize_batch(trs, **bopts)]
+    torch.cuda.synchronize()
+    dt_batch = (time.perf_counter() - t0) / reps
+    st = ctx.batch_stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ms = [ctx.characterize(t, stream) for t in trs]
+    plain = [m.read() for m in ms]
+    torch.cuda.synchronize()
+    dt_plain = time.perf_counter() - t0
+    return {"traces": len(trs), "events": ev, "addresses": mem,
+            "batched_events_per_s": ev / dt_batch, "batched_addresses_per_s": mem / dt_batch,
+            "plain_events_per_s": ev / dt_plain, "speedup": dt_plain / dt_batch,
+            "identical": all(strip(a) == strip(b) for a, b in zip(plain, got)),
+            "waves": st["waves"], "redo_partitions": st["redo_partitions"],
+            "total_partitions": st["total_partitions"]}
 
 
 def main() -> int:
@@ -123,6 +169,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-wi-log2", type=int, default=17)
     ap.add_argument("--no-batch", action="store_true", help="skip the batched legs")
+    ap.add_argument("--no-stress", action="store_true", help="skip the stress batch leg")
     ap.add_argument("--batch-traces", type=int, default=512)
     ap.add_argument("--batch-scale", type=float, default=0.05,
                     help="config3 lengths are scaled by this factor")

@@ -86,7 +86,9 @@ struct TraceArgs {
 };
 
 // A kernel either serves one trace (arguments by value) or a whole batch
-// (grid.y = trace index into a device array of TraceArgs).
+// (grid.y = trace index into a device array of TraceArgs).  Kernels copy the
+// result into a local at entry, so that a batch kernel reads its trace's
+// arguments from memory once rather than after every store.
 template <bool BATCH>
 __device__ __forceinline__ const TraceArgs &trace_args(const TraceArgs &A0,
                                                        const TraceArgs *batch) {

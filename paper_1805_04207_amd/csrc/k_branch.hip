@@ -38,7 +38,7 @@ constexpr u64 EMPTY = ~0ull;
 // ------------------------------------------------------------------ pack
 template <bool BATCH>
 __global__ void k_br_pack(TraceArgs A0, const TraceArgs *batch) {
-  const TraceArgs &A = trace_args<BATCH>(A0, batch);
+  const TraceArgs A = trace_args<BATCH>(A0, batch);
   u32 *out = A.br_a;
   u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x;
   const u64 stride = (u64)gridDim.x * blockDim.x;
@@ -58,7 +58,7 @@ template <bool BATCH>
 __global__ void __launch_bounds__(BR_BLOCK) k_br_upsweep(TraceArgs A0, const TraceArgs *batch,
                                                         u32 pass) {
   __shared__ u32 h[256];
-  const TraceArgs &A = trace_args<BATCH>(A0, batch);
+  const TraceArgs A = trace_args<BATCH>(A0, batch);
   if (pass >= A.br_passes || blockIdx.x >= A.br_tiles) return;
   const u32 *in = (pass & 1) ? A.br_b : A.br_a;
   const u64 n = A.n_branch, n_tiles = A.br_tiles;
@@ -87,7 +87,7 @@ __global__ void __launch_bounds__(BR_BLOCK) k_br_downsweep(TraceArgs A0, const T
   __shared__ u32 gofs[256];
   __shared__ u32 running[256];
   __shared__ u32 wcnt[BR_BLOCK / AIWC_WAVE][256];
-  const TraceArgs &A = trace_args<BATCH>(A0, batch);
+  const TraceArgs A = trace_args<BATCH>(A0, batch);
   if (pass >= A.br_passes || blockIdx.x >= A.br_tiles) return;
   const u32 *in = (pass & 1) ? A.br_b : A.br_a;
   u32 *out = (pass & 1) ? A.br_a : A.br_b;
@@ -166,7 +166,7 @@ template <bool BATCH>
 __global__ void __launch_bounds__(SCAN_BLOCK) k_scan_reduce(TraceArgs A0, const TraceArgs *batch,
                                                            u32 pass) {
   __shared__ u32 wsum[16];
-  const TraceArgs &A = trace_args<BATCH>(A0, batch);
+  const TraceArgs A = trace_args<BATCH>(A0, batch);
   const u64 n = 256ull * A.br_tiles;
   if (pass >= A.br_passes || blockIdx.x >= (n + SCAN_TILE - 1) / SCAN_TILE) return;
   const u32 *in = A.br_cnt;
@@ -187,7 +187,7 @@ __global__ void __launch_bounds__(SCAN_BLOCK) k_scan_sums(TraceArgs A0, const Tr
                                                          u32 pass) {
   __shared__ u32 wsum[16];
   __shared__ u32 carry;
-  const TraceArgs &A = trace_args<BATCH>(A0, batch);
+  const TraceArgs A = trace_args<BATCH>(A0, batch);
   if (pass >= A.br_passes) return;
   u32 *sums = A.scan_tmp;
   const u64 nb = (256ull * A.br_tiles + SCAN_TILE - 1) / SCAN_TILE;
@@ -210,7 +210,7 @@ template <bool BATCH>
 __global__ void __launch_bounds__(SCAN_BLOCK) k_scan_apply(TraceArgs A0, const TraceArgs *batch,
                                                           u32 pass) {
   __shared__ u32 wsum[16];
-  const TraceArgs &A = trace_args<BATCH>(A0, batch);
+  const TraceArgs A = trace_args<BATCH>(A0, batch);
   const u64 n = 256ull * A.br_tiles;
   if (pass >= A.br_passes || blockIdx.x >= (n + SCAN_TILE - 1) / SCAN_TILE) return;
   u32 *data = A.br_cnt;
@@ -237,7 +237,7 @@ __global__ void __launch_bounds__(SCAN_BLOCK) k_scan_apply(TraceArgs A0, const T
 // ------------------------------------------------------------- segments
 template <bool BATCH>
 __global__ void k_br_segments(TraceArgs A0, const TraceArgs *batch) {
-  const TraceArgs &A = trace_args<BATCH>(A0, batch);
+  const TraceArgs A = trace_args<BATCH>(A0, batch);
   const u32 *sorted = A.br_sorted;
   u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x;
   const u64 stride = (u64)gridDim.x * blockDim.x;
@@ -305,7 +305,7 @@ __device__ __forceinline__ u32 win_insert(WinShared &S, u64 key, u32 a, u32 b, b
 template <bool BATCH>
 __global__ void __launch_bounds__(WIN_BLOCK) k_br_windows(TraceArgs A0, const TraceArgs *batch) {
   __shared__ WinShared S;
-  const TraceArgs &A = trace_args<BATCH>(A0, batch);
+  const TraceArgs A = trace_args<BATCH>(A0, batch);
   if (A.n_branch == 0) return;
   const u32 *sorted = A.br_sorted;
   const int tid = threadIdx.x, lane = lane_id(), wave = tid / AIWC_WAVE;

@@ -150,7 +150,7 @@ __device__ double median_of(const u64 *hist, const u64 *large, u64 n_large, u64 
 template <bool BATCH>
 __global__ void __launch_bounds__(FB) k_finalize(TraceArgs A0, const TraceArgs *batch) {
   __shared__ FinShared S;
-  const TraceArgs &A = trace_args<BATCH>(A0, batch);
+  const TraceArgs A = trace_args<BATCH>(A0, batch);
   const int tid = threadIdx.x;
   DevAccum *acc = A.acc;
   aiwc_metrics_host *o = A.out;

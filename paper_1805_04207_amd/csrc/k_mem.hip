@@ -52,7 +52,7 @@ template <bool VEC, bool BATCH>
 __global__ void __launch_bounds__(MEM_BLOCK) k_mem_hist(TraceArgs A0, const TraceArgs *batch) {
   extern __shared__ u32 h[];   // [P]
   __shared__ u64 sp_cnt[4];  // reads g, writes g, reads l, writes l
-  const TraceArgs &A = trace_args<BATCH>(A0, batch);
+  const TraceArgs A = trace_args<BATCH>(A0, batch);
   if (A.n_mem == 0 || blockIdx.x >= A.n_hist_blocks) return;
   const u32 P = 1u << A.pbits;
   for (u32 i = threadIdx.x; i < P; i += MEM_BLOCK) h[i] = 0;
@@ -109,7 +109,7 @@ __global__ void __launch_bounds__(MEM_BLOCK) k_mem_hist(TraceArgs A0, const Trac
 // the partition total goes to part_off[b].
 template <bool BATCH>
 __global__ void k_mem_colscan(TraceArgs A0, const TraceArgs *batch) {
-  const TraceArgs &A = trace_args<BATCH>(A0, batch);
+  const TraceArgs A = trace_args<BATCH>(A0, batch);
   const u32 P = 1u << A.pbits;
   const u32 b = blockIdx.x * blockDim.x + threadIdx.x;
   if (A.n_mem == 0 || b >= P) return;
@@ -128,7 +128,7 @@ template <bool BATCH>
 __global__ void __launch_bounds__(1024) k_mem_binscan(TraceArgs A0, const TraceArgs *batch) {
   __shared__ u32 wsum[16];
   __shared__ u32 carry;
-  const TraceArgs &A = trace_args<BATCH>(A0, batch);
+  const TraceArgs A = trace_args<BATCH>(A0, batch);
   if (A.n_mem == 0) return;
   const u32 P = 1u << A.pbits;
   if (threadIdx.x == 0) carry = 0;
@@ -159,7 +159,7 @@ __global__ void __launch_bounds__(1024) k_mem_binscan(TraceArgs A0, const TraceA
 template <bool VEC, bool BATCH>
 __global__ void __launch_bounds__(MEM_BLOCK) k_mem_scatter(TraceArgs A0, const TraceArgs *batch) {
   extern __shared__ u32 cur[];   // [P]
-  const TraceArgs &A = trace_args<BATCH>(A0, batch);
+  const TraceArgs A = trace_args<BATCH>(A0, batch);
   if (A.n_mem == 0 || blockIdx.x >= A.n_hist_blocks) return;
   const u32 P = 1u << A.pbits;
   const u32 *row = A.part_hist + (u64)blockIdx.x * P;
@@ -575,7 +575,7 @@ __device__ __forceinline__ u64 low_mask(u32 n) { return n >= 64 ? ~0ull : (1ull 
 template <bool BATCH>
 __global__ void __launch_bounds__(BK_BLOCK) k_mem_bucket(TraceArgs A0, const TraceArgs *batch) {
   __shared__ BucketShared S;
-  const TraceArgs &A = trace_args<BATCH>(A0, batch);
+  const TraceArgs A = trace_args<BATCH>(A0, batch);
   if (A.n_mem == 0) return;
   const int tid = threadIdx.x, lane = lane_id(), wave = tid / AIWC_WAVE;
   const u32 P = 1u << A.pbits;

@@ -63,7 +63,7 @@ __host__ __device__ __forceinline__ u32 ops_copies(u32 nid) {
 template <bool LDS_IDS, bool BATCH, bool VEC>
 __global__ void __launch_bounds__(OPS_BLOCK) k_ops(TraceArgs A0, const TraceArgs *batch) {
   extern __shared__ u32 lds[];
-  const TraceArgs &A = trace_args<BATCH>(A0, batch);
+  const TraceArgs A = trace_args<BATCH>(A0, batch);
   const u32 nid = A.n_ids;
   const u32 ncopies = LDS_IDS ? ops_copies(nid) : 1u;
   WaveStats *ws = (WaveStats *)lds;                   // [OPS_WAVES]
@@ -253,7 +253,7 @@ __global__ void __launch_bounds__(OPS_BLOCK) k_ops(TraceArgs A0, const TraceArgs
 
 template <bool BATCH>
 __global__ void k_zero(TraceArgs A0, const TraceArgs *batch) {
-  const TraceArgs &A = trace_args<BATCH>(A0, batch);
+  const TraceArgs A = trace_args<BATCH>(A0, batch);
   uint4 *p = (uint4 *)A.zero_base;
   const size_t n16 = A.zero_bytes / 16;
   size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
