@@ -503,9 +503,12 @@ __device__ __forceinline__ void page_levels(LaneAcc &L, BucketShared &S, SpecRef
     L.ur += __builtin_popcount(rb[lane]);
     L.uw += __builtin_popcount(wb[lane]);
   }
+  // a node position empty in every lane (common: strided pages use one
+  // counter in 2^j) is skipped by the whole wavefront
   bool anybig = false;
 #pragma unroll
   for (int j = 0; j < 16; ++j) {
+    if (__ballot(c[j] != 0) == 0) continue;
     const u32 v = c[j] < 256 ? c[j] : 0u;
     add_small_node(L, S, 0, v);
     if (v >= 2) atomicAdd(&S.spec[s][v], 1u);
@@ -516,6 +519,7 @@ __device__ __forceinline__ void page_levels(LaneAcc &L, BucketShared &S, SpecRef
 #pragma unroll
     for (int j = 0; j < (16 >> k); ++j) {
       c[j] = c[2 * j] + c[2 * j + 1];
+      if (__ballot(c[j] != 0) == 0) continue;
       add_small_node(L, S, k, c[j] < 256 ? c[j] : 0u);
       anybig |= c[j] >= 256;
     }
@@ -552,6 +556,10 @@ __device__ __forceinline__ void match_levels(LaneAcc &L, BucketShared &S, u32 of
     }
     const bool own = P != 0 && (P & below) == 0;
     const u32 c = own ? (u32)__builtin_popcountll(P) : 0u;
+    if (__ballot(c >= 2) == 0) {          // only single-record nodes: no table term
+      L.dn[k] += c * 0x10001u;           // c is 0 or 1: one node of count 1
+      continue;
+    }
     add_small_node(L, S, k, c);
     if (k == 0 && c >= 2) atomicAdd(&S.spec[L.space][c], 1u);
   }
