@@ -171,7 +171,7 @@ def main() -> int:
     ap.add_argument("--no-batch", action="store_true", help="skip the batched legs")
     ap.add_argument("--no-stress", action="store_true", help="skip the stress batch leg")
     ap.add_argument("--batch-traces", type=int, default=512)
-    ap.add_argument("--batch-scale", type=float, default=0.05,
+    ap.add_argument("--batch-scale", type=float, default=1.0,
                     help="config3 lengths are scaled by this factor")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="one characterization, then a plain device copy of 1 GiB, for "

@@ -5,6 +5,10 @@
   (oracle/bulk.py) on the byte-identical host trace: every field, the class
   histogram and the level-0 spectrum.  The batched path with learned sizing
   and a replayed graph must give the identical metrics.
+* The uneven batch (512 traces of 1e4..1e8 events, ~5e9 in total) in one
+  batched call with learned sizing, autotuning and a replayed graph: every
+  trace identical to its plain per-trace result, the three smallest against
+  the C oracle and a mid-size one against the vectorised oracle.
 * The stress batch (64 traces, 2^32 addresses in total, up to 2^28 per trace,
   history 32 over 2^16 sites) in one batched call with learned sizing and a
   200 GiB admission cap: the two smallest traces against the C oracle, every
@@ -152,3 +156,46 @@ def test_stress_batch_full_size():
     for i in (int(order[len(order) // 2]), int(order[-1])):
         assert same(ctx.characterize(trs[i]).read(), res[i]), f"trace {i}"
     log("plain path identical on the sample")
+
+
+@pytest.mark.timeout(1200)
+def test_uneven_batch_full_size():
+    import torch
+    import paper_1805_04207_amd as aiwc
+    from paper_1805_04207_amd.train_sizer import DEFAULT_WEIGHTS
+
+    specs = tg.config3_specs(seed=2, n_traces=512, scale=1.0)
+    ctx = aiwc.Context(0)
+    ctx.sizer_load(DEFAULT_WEIGHTS)
+    keep, trs, n_ev, n_mem = [], [], [], []
+    t0 = time.time()
+    for sp in specs:
+        d = tg.generate_device(sp, 0)
+        keep.append(d)
+        n_ev.append(d["n_events"])
+        n_mem.append(d["n_mem"])
+        trs.append(aiwc.device_trace(ctx, d, tg.opcode_table(), sp.n_sites, sp.history_len,
+                                     sp.wg_size))
+    torch.cuda.synchronize()
+    log(f"{len(trs)} traces, {sum(n_ev)} events, generated in {time.time() - t0:.1f}s")
+    opts = dict(sizing=aiwc.SIZING_LEARNED, autotune=aiwc.AUTOTUNE_SEARCH, use_graph=True)
+    res = [m.read() for m in ctx.characterize_batch(trs, **opts)]
+    res2 = [m.read() for m in ctx.characterize_batch(trs, **opts)]     # graph replay
+    st = ctx.batch_stats()
+    log(f"batched: waves {st['waves']}, redo partitions {st['redo_partitions']} of "
+        f"{st['total_partitions']}")
+    for i, t in enumerate(trs):
+        p = ctx.characterize(t).read()
+        assert same(p, res[i]) and same(p, res2[i]), f"trace {i}"
+        loc = p["space"][1]["total_accesses"]
+        invariants(p, (n_mem[i] - loc, loc))
+    log("every trace identical to the plain path")
+    order = np.argsort(n_ev)
+    for i in (int(order[0]), int(order[1]), int(order[2])):
+        bad = compare(res[i], oracle.characterize(tg.generate_host(specs[i])))
+        assert not bad, f"trace {i}:\n" + "\n".join(bad[:20])
+    mid = int(order[len(order) // 2])
+    bad = compare(res[mid], bulk.characterize(tg.generate_host(specs[mid])))
+    assert not bad, f"trace {mid}:\n" + "\n".join(bad[:20])
+    log(f"oracle parity on traces {int(order[0])}, {int(order[1])}, {int(order[2])} and {mid} "
+        f"({n_ev[mid]} events)")
