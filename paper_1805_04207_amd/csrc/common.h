@@ -16,6 +16,7 @@ typedef unsigned int u32;
 // They live at the start of the per-trace zero region (cleared by a fill
 // kernel at the start of every characterization).
 #define SPEC_DENSE 256       // level-0 spectrum kept densely for f < 256
+#define AIWC_STAGE_CAP 16384 // records the bucket kernel stages on chip per round
 #define VAL_DENSE 65536      // ITB / IPT value histograms are dense below this
 struct DevAccum {
   u64 itb_min_inv, itb_max, itb_cnt, itb_sum;   // min stored as max of ~v

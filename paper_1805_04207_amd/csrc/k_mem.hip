@@ -237,7 +237,7 @@ constexpr u32 SMALL = 32;
 constexpr u32 MEDIUM = 64;
 constexpr int UNROLL = 8;                         // records in flight per thread
 constexpr u32 SPEC_LDS = 256;
-constexpr u32 STAGE_CAP = 16384;                  // staged records per round
+constexpr u32 STAGE_CAP = AIWC_STAGE_CAP;         // staged records per round
 // Dense-tree nodes of count >= 256 found by the wavefronts in one round, kept
 // for the block: at most 11 levels * STAGE_CAP / 256 of them.
 constexpr u32 BLIST_CAP = AIWC_NSKIP * STAGE_CAP / 256;

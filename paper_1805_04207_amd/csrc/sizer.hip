@@ -658,8 +658,13 @@ extern "C" aiwc_status aiwc_sizer_load(aiwc_ctx *ctx, const char *path) {
 
 // ------------------------------------------------------------ sizing policy
 // Partitions so that one holds about 1024 pages (1 KiB address blocks).
-static u32 pbits_for_pages(double pages) {
+// Partitions for an expected page count: ~1024 pages per partition (the
+// bucket kernel's page table holds 1536), and on average no more than half
+// the records the kernel stages on chip per round, so that most partitions
+// take a single round.
+static u32 pbits_for_pages(double pages, double records) {
   double want = std::ceil(std::max(1.0, pages) / 1024.0);
+  want = std::max(want, std::ceil(records / (double)(AIWC_STAGE_CAP / 2)));
   u32 b = 0;
   while ((double)(1ull << b) < want) ++b;
   return std::min<u32>(15, std::max<u32>(4, b));
@@ -707,7 +712,7 @@ aiwc_status sizer_plan_pbits(aiwc_ctx *ctx, const aiwc_trace *const *traces, siz
     else
       glob = (std::exp2((double)f[18]) - 1.0) * scale;
     glob = std::min(glob, nmem);
-    pbits[i] = pbits_for_pages(glob + loc);
+    pbits[i] = pbits_for_pages(glob + loc, nmem);
   }
   return AIWC_OK;
 }

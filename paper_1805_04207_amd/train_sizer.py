@@ -1,7 +1,8 @@
 """Train the sizing network on the GPU and save its weights.
 
 Traces of the config2 family (tracegen.config2_family: log-uniform
-work-item counts, per-trace pattern mix, stride and gather range) are
+work-item counts over 2^8..2^16 by default, work-items of 768..1280 events,
+per-trace pattern mix, stride and gather range) are
 generated on the device, characterized exactly by libaiwc (labels =
 log2(1 + distinct_k) of the global space, k = 0..10), featurized by the
 library's prefix-feature kernel, and the 40->64->64->64->11 network is
@@ -10,7 +11,7 @@ added to predictions before sizing is calibrated on a held-out split so that
 at most `--overflow-target` of the held-out traces would be undersized at
 skip 10 (the page count that sizes the partitions).
 
-    python -m paper_1805_04207_amd.train_sizer --traces 4096 --out sizer_weights.bin
+    python -m paper_1805_04207_amd.train_sizer --traces 20000 --out sizer_weights.bin
 """
 from __future__ import annotations
 
@@ -32,7 +33,7 @@ def build_dataset(ctx, n: int, seed: int, wi_lo: float, wi_hi: float, batch: int
     import tracegen as tg
     from . import device_trace
 
-    specs = tg.config2_family(seed, n, wi_lo, wi_hi, len_min=256, len_max=768)
+    specs = tg.config2_family(seed, n, wi_lo, wi_hi, len_min=768, len_max=1280)
     feats, labels = [], []
     for b0 in range(0, n, batch):
         keep, trs = [], []
@@ -55,24 +56,72 @@ def build_dataset(ctx, n: int, seed: int, wi_lo: float, wi_hi: float, batch: int
     return x, y
 
 
+def evaluate(ctx, n: int, seed: int, wi_lo: float, wi_hi: float):
+    """What the network gains: one batch of held-out traces under each sizing
+    mode -- partitions (device memory and work), partitions redone after an
+    overflow, and the time of the batched call; metrics must not change."""
+    import torch
+    import tracegen as tg
+    from . import SIZING_BOUND, SIZING_HEURISTIC, SIZING_LEARNED, device_trace
+
+    specs = tg.config2_family(seed, n, wi_lo, wi_hi, len_min=768, len_max=1280)
+    keep, trs, events = [], [], 0
+    for sp in specs:
+        d = tg.generate_device(sp, ctx.device)
+        keep.append(d)
+        events += d["n_events"]
+        trs.append(device_trace(ctx, d, tg.opcode_table(), sp.n_sites, sp.history_len,
+                                sp.wg_size))
+    out, ref = {"traces": n, "events": events}, None
+    for name, mode in (("bound", SIZING_BOUND), ("heuristic", SIZING_HEURISTIC),
+                       ("learned", SIZING_LEARNED)):
+        ctx.characterize_batch(trs, sizing=mode)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = [m.read() for m in ctx.characterize_batch(trs, sizing=mode)]
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        st = ctx.batch_stats()
+        key = [json.dumps({k: v for k, v in r.items() if k not in ("overflow_redos", "partitions")},
+                          sort_keys=True) for r in res]
+        if ref is None:
+            ref = key
+        out[name] = {"ms": 1e3 * dt, "partitions": st["total_partitions"],
+                     "redo_partitions": st["redo_partitions"], "waves": st["waves"],
+                     "identical_metrics": key == ref}
+        print(f"# eval {name}: {out[name]}", file=sys.stderr, flush=True)
+    return out
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
-    ap.add_argument("--traces", type=int, default=4096)
+    ap.add_argument("--traces", type=int, default=20000)
     ap.add_argument("--val-frac", type=float, default=0.1)
     ap.add_argument("--epochs", type=int, default=60)
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--seed", type=int, default=3)
-    ap.add_argument("--wi-log2", type=float, nargs=2, default=(6.0, 13.0))
+    ap.add_argument("--wi-log2", type=float, nargs=2, default=(8.0, 16.0))
     ap.add_argument("--overflow-target", type=float, default=0.02)
     ap.add_argument("--out", default=DEFAULT_WEIGHTS)
     ap.add_argument("--report", default=None, help="write a JSON report here")
+    ap.add_argument("--eval-traces", type=int, default=256,
+                    help="held-out family traces run under BOUND / HEURISTIC / LEARNED sizing")
+    ap.add_argument("--eval-wi-log2", type=float, nargs=2, default=(10.0, 16.0))
+    ap.add_argument("--eval-only", default=None, metavar="WEIGHTS",
+                    help="load these weights and only run the evaluation")
     args = ap.parse_args(argv)
 
     import torch
     from . import Context
 
     ctx = Context(0)
+    if args.eval_only:
+        ctx.sizer_load(args.eval_only)
+        rep = {"weights": args.eval_only,
+               "eval": evaluate(ctx, args.eval_traces, args.seed + 1, *args.eval_wi_log2)}
+        print(json.dumps(rep))
+        return 0
     t0 = time.time()
     x, y = build_dataset(ctx, args.traces, args.seed, *args.wi_log2)
     t_data = time.time() - t0
@@ -93,6 +142,8 @@ def main(argv=None) -> int:
     rep = {"traces": args.traces, "train_mse_normalized": loss,
            "val_mae_log2": [float(v) for v in np.abs(err).mean(0)],
            "margin_log2": margin, "data_s": t_data, "train_s": t_train, "weights": args.out}
+    if args.eval_traces:
+        rep["eval"] = evaluate(ctx, args.eval_traces, args.seed + 1, *args.eval_wi_log2)
     print(json.dumps(rep))
     if args.report:
         with open(args.report, "w") as f:
