@@ -524,10 +524,16 @@ __device__ __forceinline__ void page_levels(LaneAcc &L, BucketShared &S, SpecRef
       anybig |= c[j] >= 256;
     }
   }
+  // levels 5..8: sums over 2, 4, 8, 16 lanes by DPP (lane ^ 1, lane ^ 2,
+  // half-row and row mirrors); 9 and 10 across rows
   u32 t = c[0];
 #pragma unroll
   for (int k = 5; k < AIWC_NSKIP; ++k) {
-    t += __shfl_xor(t, 1 << (k - 5), 64);
+    if (k == 5) t += (u32)__builtin_amdgcn_update_dpp(0, (int)t, 0xB1, 0xF, 0xF, false);
+    else if (k == 6) t += (u32)__builtin_amdgcn_update_dpp(0, (int)t, 0x4E, 0xF, 0xF, false);
+    else if (k == 7) t += (u32)__builtin_amdgcn_update_dpp(0, (int)t, 0x141, 0xF, 0xF, false);
+    else if (k == 8) t += (u32)__builtin_amdgcn_update_dpp(0, (int)t, 0x140, 0xF, 0xF, false);
+    else t += __shfl_xor(t, 1 << (k - 5), 64);
     const bool own = (lane & ((1 << (k - 4)) - 1)) == 0;
     add_small_node(L, S, k, (own && t < 256) ? t : 0u);
     anybig |= own && t >= 256;
