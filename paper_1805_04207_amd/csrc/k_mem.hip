@@ -351,6 +351,19 @@ __device__ __forceinline__ u32 wave_total(u32 v) {
          (u32)__builtin_amdgcn_readlane((int)v, 32) + (u32)__builtin_amdgcn_readlane((int)v, 48);
 }
 
+// Inclusive prefix sum over the wavefront by DPP: row shifts by 1, 2, 4, 8
+// (sums inside rows of 16), then each row adds the totals of the rows before
+// it (row broadcasts of lanes 15 and 31).  Every lane must be active.
+__device__ __forceinline__ u32 wave_scan(u32 v) {
+  v += (u32)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, true);
+  v += (u32)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, true);
+  v += (u32)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, true);
+  v += (u32)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, true);
+  v += (u32)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false);
+  v += (u32)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false);
+  return v;
+}
+
 // Adds a 2^-40-unit value, given as 32-bit-aligned pieces, to a level's limbs.
 __device__ __forceinline__ void limbs_add(u64 *el, u64 l0, u64 l1, u64 l2) {
   if (l0) atomicAdd(&el[0], l0);
@@ -464,7 +477,10 @@ __device__ __forceinline__ void big_collect(BucketShared &S, const u32 *cnt, int
       u32 v = 0;
 #pragma unroll 1
       for (int q = 0; q < (1 << k); ++q) v += my[((j << k) + q) ^ sw];
-      if (v >= 256) S.blist[atomicAdd(&S.nblist, 1u)] = tag | ((u32)k << 24) | v;
+      if (v >= 256) {
+        const u32 bi = atomicAdd(&S.nblist, 1u);
+        if (bi < BLIST_CAP) S.blist[bi] = tag | ((u32)k << 24) | v;
+      }
     }
   }
   u32 t = 0;
@@ -473,8 +489,10 @@ __device__ __forceinline__ void big_collect(BucketShared &S, const u32 *cnt, int
 #pragma unroll
   for (int k = 5; k < AIWC_NSKIP; ++k) {
     t += __shfl_xor(t, 1 << (k - 5), 64);
-    if ((lane & ((1 << (k - 4)) - 1)) == 0 && t >= 256)
-      S.blist[atomicAdd(&S.nblist, 1u)] = tag | ((u32)k << 24) | t;
+    if ((lane & ((1 << (k - 4)) - 1)) == 0 && t >= 256) {
+      const u32 bi = atomicAdd(&S.nblist, 1u);
+      if (bi < BLIST_CAP) S.blist[bi] = tag | ((u32)k << 24) | t;
+    }
   }
 }
 
@@ -677,23 +695,34 @@ __global__ void __launch_bounds__(BK_BLOCK) k_mem_bucket(TraceArgs A0, const Tra
       __syncthreads();
       for (u32 j0 = 0; j0 < np; j0 += BK_BLOCK) {
         const u32 j = j0 + tid;
-        u32 c = 0, cl = 3;
+        u32 c = 0, cl = 3, sp = 0;
         if (j < np) {
           const u32 slot = S.pslot[j];
           c = S.pcnt[slot];
-          const u32 sp = (u32)((S.pkey[slot] >> sbit) & 1ull);
-          cl = c <= SMALL ? sp : 2u;
+          sp = (u32)((S.pkey[slot] >> sbit) & 1ull);
+          cl = c <= SMALL ? sp : (c <= HEAVY ? 2u : 3u);
           S.psz[j] = (uint16_t)(c < 65535u ? c : 65535u);
-          if (c > SMALL) {
-            if (sp == 0) S.big[atomicAdd(&S.nbig0, 1u)] = (uint16_t)j;
-            else S.big[PT_CAP - 1 - atomicAdd(&S.nbig1, 1u)] = (uint16_t)j;
-            if (c > HEAVY) { atomicAdd(&S.nheavy, 1u); cl = 3; }
-          }
         }
-#pragma unroll
-        for (u32 q = 0; q < 3; ++q) {
-          const u64 t = wave_sum_u64(cl == q ? c : 0u);
-          if (lane == 0 && t) atomicAdd(&S.ctot[q], (u32)t);
+        // pages > SMALL join the space's list: one counter update per wavefront
+        const bool l0 = j < np && c > SMALL && sp == 0, l1 = j < np && c > SMALL && sp == 1;
+        const u64 B0 = __ballot(l0), B1 = __ballot(l1), BH = __ballot(j < np && c > HEAVY);
+        u32 b0 = 0, b1 = 0;
+        if (lane == 0) {
+          if (B0) b0 = atomicAdd(&S.nbig0, (u32)__builtin_popcountll(B0));
+          if (B1) b1 = atomicAdd(&S.nbig1, (u32)__builtin_popcountll(B1));
+          if (BH) atomicAdd(&S.nheavy, (u32)__builtin_popcountll(BH));
+        }
+        b0 = __shfl(b0, 0, 64);
+        b1 = __shfl(b1, 0, 64);
+        if (l0) S.big[b0 + (u32)__builtin_popcountll(B0 & below)] = (uint16_t)j;
+        if (l1) S.big[PT_CAP - 1 - (b1 + (u32)__builtin_popcountll(B1 & below))] = (uint16_t)j;
+        // class totals (classes 0 and 1 share a word: their counts are <= SMALL)
+        const u32 t01 = wave_total((cl == 0 ? c : 0u) | ((cl == 1 ? c : 0u) << 16));
+        const u32 t2 = wave_total(cl == 2 ? c : 0u);
+        if (lane == 0) {
+          if (t01 & 0xFFFFu) atomicAdd(&S.ctot[0], t01 & 0xFFFFu);
+          if (t01 >> 16) atomicAdd(&S.ctot[1], t01 >> 16);
+          if (t2) atomicAdd(&S.ctot[2], t2);
         }
       }
       __syncthreads();
@@ -724,21 +753,25 @@ __global__ void __launch_bounds__(BK_BLOCK) k_mem_bucket(TraceArgs A0, const Tra
           c = S.psz[j];
           cl = c <= SMALL ? (u32)((S.pkey[S.pslot[j]] >> sbit) & 1ull) : (c <= HEAVY ? 2u : 3u);
         }
-#pragma unroll
-        for (u32 q = 0; q < 3; ++q) {
-          const u32 v = cl == q ? c : 0u;
-          u32 x = v;
-#pragma unroll
-          for (int o = 1; o < 64; o <<= 1) {
-            const u32 y = __shfl_up(x, o, 64);
-            if (lane >= o) x += y;
-          }
-          const u32 tot = __shfl(x, 63, 64);
-          u32 b = 0;
-          if (lane == 0 && tot) b = atomicAdd(&S.ccur[q], tot);
-          b = __shfl(b, 0, 64);
-          if (cl == q) S.pend[j] = b + x - v;
+        // per-class inclusive prefixes (a round stages <= STAGE_CAP < 2^16
+        // records, so classes 0 and 1 share a word)
+        const u32 v01 = (cl == 0 ? c : 0u) | ((cl == 1 ? c : 0u) << 16);
+        const u32 v2 = cl == 2 ? c : 0u;
+        const u32 x01 = wave_scan(v01), x2 = wave_scan(v2);
+        const u32 w01 = (u32)__builtin_amdgcn_readlane((int)x01, 63);
+        const u32 w2 = (u32)__builtin_amdgcn_readlane((int)x2, 63);
+        u32 c0 = 0, c1 = 0, c2 = 0;
+        if (lane == 0) {
+          if (w01 & 0xFFFFu) c0 = atomicAdd(&S.ccur[0], w01 & 0xFFFFu);
+          if (w01 >> 16) c1 = atomicAdd(&S.ccur[1], w01 >> 16);
+          if (w2) c2 = atomicAdd(&S.ccur[2], w2);
         }
+        c0 = __shfl(c0, 0, 64);
+        c1 = __shfl(c1, 0, 64);
+        c2 = __shfl(c2, 0, 64);
+        if (cl == 0) S.pend[j] = c0 + (x01 & 0xFFFFu) - c;
+        else if (cl == 1) S.pend[j] = c1 + (x01 >> 16) - c;
+        else if (cl == 2) S.pend[j] = c2 + x2 - c;
       }
       __syncthreads();
       // regroup: the first lane of each run reserves the run's positions
@@ -764,7 +797,7 @@ __global__ void __launch_bounds__(BK_BLOCK) k_mem_bucket(TraceArgs A0, const Tra
           const u64 H = __ballot(head) & (below | (1ull << lane));
           const int hl = H ? 63 - __builtin_clzll(H) : lane;
           const u32 p0 = __shfl(pos, hl, 64), c0 = __shfl(ci, hl, 64);
-          if (valid && p0 != ~0u)
+          if (valid && p0 != ~0u && p0 + (u32)(lane - hl) < STAGE_CAP)
             S.stage[p0 + (u32)(lane - hl)] = (c0 << 11) | (u32)(rv[u] & 2047ull);
         }
       }
@@ -878,7 +911,8 @@ __global__ void __launch_bounds__(BK_BLOCK) k_mem_bucket(TraceArgs A0, const Tra
       }
       __syncthreads();
       // ---- the round's dense-tree nodes of count >= 256
-      for (u32 i = tid; i < S.nblist; i += BK_BLOCK) {
+      const u32 nbl = S.nblist < BLIST_CAP ? S.nblist : BLIST_CAP;
+      for (u32 i = tid; i < nbl; i += BK_BLOCK) {
         const u32 e = S.blist[i];
         const int sp = (int)(e >> 31);
         big_node(S, G, sp, (int)((e >> 24) & 127u), e & 0xFFFFFFu, sp ? N1 : N0);
