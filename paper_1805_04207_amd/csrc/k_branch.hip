@@ -329,7 +329,15 @@ __global__ void __launch_bounds__(WIN_BLOCK) k_br_windows(TraceArgs A0, const Tr
     if (tid == 0) S.next = (u32)atomicAdd(&A.acc->br_queue, 1ull);
     const u64 r0 = range_begin(A, sorted, b), r1 = range_begin(A, sorted, b + 1);
     if (r1 <= r0) { __syncthreads(); continue; }
-    if (tid == 0) { S.sp_top = 1; S.stack_m[0] = 1; S.stack_c[0] = 0; }
+    // a block holds at most r1 - r0 keys: split by key-hash bits up front so
+    // that each pass stays within the table's cap (a pass that still
+    // overflows is split further)
+    if (tid == 0) {
+      u32 M0 = 1;
+      while (M0 < 16 && (u64)M0 * WT_CAP < r1 - r0) M0 <<= 1;
+      for (u32 c = 0; c < M0; ++c) { S.stack_m[c] = M0; S.stack_c[c] = c; }
+      S.sp_top = M0;
+    }
     __syncthreads();
     while (S.sp_top > 0) {
       __syncthreads();
