@@ -101,11 +101,15 @@ __device__ __forceinline__ const TraceArgs &trace_args(const TraceArgs &A0,
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
 // Runs of equal keys among neighbouring lanes: the lanes that end a run
-// (lane 63 always does).  The shuffle runs on every lane: a lane left out of
-// a cross-lane read would hand its neighbour a stale value.
+// (lane 63 always does).  The next lane's key arrives by a whole-wavefront
+// DPP shift (wave_shl:1), which every lane must execute: a lane left out of a
+// cross-lane read would hand its neighbour a stale value.
 __device__ __forceinline__ u64 run_ends(u64 key) {
   const int lane = lane_id();
-  const u64 next = __shfl_down(key, 1, 64);
+  const u32 lo = (u32)__builtin_amdgcn_update_dpp(0, (int)(u32)key, 0x130, 0xF, 0xF, false);
+  const u32 hi = (u32)__builtin_amdgcn_update_dpp(0, (int)(u32)(key >> 32), 0x130, 0xF, 0xF,
+                                                  false);
+  const u64 next = ((u64)hi << 32) | lo;
   return __ballot(lane == 63 || next != key);
 }
 
