@@ -391,7 +391,7 @@ __global__ void __launch_bounds__(WIN_BLOCK) k_br_windows(TraceArgs A0, const Tr
           if (F) {
             u32 base = 0;
             if (lane == 0) base = atomicAdd(&S.live_n, (u32)__builtin_popcountll(F));
-            base = __shfl(base, 0, 64);
+            base = (u32)__builtin_amdgcn_readfirstlane((int)base);
             const u32 idx = base + (u32)__builtin_popcountll(F & below);
             if (fresh && idx < WT_C) S.live[idx] = (uint16_t)slot;
           }

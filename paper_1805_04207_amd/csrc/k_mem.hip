@@ -712,8 +712,8 @@ __global__ void __launch_bounds__(BK_BLOCK) k_mem_bucket(TraceArgs A0, const Tra
           if (B1) b1 = atomicAdd(&S.nbig1, (u32)__builtin_popcountll(B1));
           if (BH) atomicAdd(&S.nheavy, (u32)__builtin_popcountll(BH));
         }
-        b0 = __shfl(b0, 0, 64);
-        b1 = __shfl(b1, 0, 64);
+        b0 = (u32)__builtin_amdgcn_readfirstlane((int)b0);
+        b1 = (u32)__builtin_amdgcn_readfirstlane((int)b1);
         if (l0) S.big[b0 + (u32)__builtin_popcountll(B0 & below)] = (uint16_t)j;
         if (l1) S.big[PT_CAP - 1 - (b1 + (u32)__builtin_popcountll(B1 & below))] = (uint16_t)j;
         // class totals (classes 0 and 1 share a word: their counts are <= SMALL)
@@ -766,9 +766,9 @@ __global__ void __launch_bounds__(BK_BLOCK) k_mem_bucket(TraceArgs A0, const Tra
           if (w01 >> 16) c1 = atomicAdd(&S.ccur[1], w01 >> 16);
           if (w2) c2 = atomicAdd(&S.ccur[2], w2);
         }
-        c0 = __shfl(c0, 0, 64);
-        c1 = __shfl(c1, 0, 64);
-        c2 = __shfl(c2, 0, 64);
+        c0 = (u32)__builtin_amdgcn_readfirstlane((int)c0);
+        c1 = (u32)__builtin_amdgcn_readfirstlane((int)c1);
+        c2 = (u32)__builtin_amdgcn_readfirstlane((int)c2);
         if (cl == 0) S.pend[j] = c0 + (x01 & 0xFFFFu) - c;
         else if (cl == 1) S.pend[j] = c1 + (x01 >> 16) - c;
         else if (cl == 2) S.pend[j] = c2 + x2 - c;
@@ -852,7 +852,7 @@ __global__ void __launch_bounds__(BK_BLOCK) k_mem_bucket(TraceArgs A0, const Tra
         while (true) {
           u32 it = 0;
           if (lane == 0) it = atomicAdd(&S.next_item, 1u);
-          it = __shfl(it, 0, 64);
+          it = (u32)__builtin_amdgcn_readfirstlane((int)it);
           if (it >= e3) break;
           const int sp = (it < e1) ? 0 : 1;
           const u64 N = sp ? N1 : N0;
