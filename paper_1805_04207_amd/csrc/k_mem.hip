@@ -241,6 +241,7 @@ constexpr u32 STAGE_CAP = AIWC_STAGE_CAP;         // staged records per round
 // Dense-tree nodes of count >= 256 found by the wavefronts in one round, kept
 // for the block: at most 11 levels * STAGE_CAP / 256 of them.
 constexpr u32 BLIST_CAP = AIWC_NSKIP * STAGE_CAP / 256;
+static_assert(STAGE_CAP < 0xFFFFu, "staging positions travel in 16 bits");
 
 struct BucketShared {
   u64 pkey[PT_SLOTS];              // page key, EMPTY if free
@@ -788,17 +789,22 @@ __global__ void __launch_bounds__(BK_BLOCK) k_mem_bucket(TraceArgs A0, const Tra
           const bool valid = rv[u] != EMPTY && ((u32)pk & (M - 1u)) == C;
           const u64 ends = run_ends(valid ? pk : EMPTY);
           const bool head = valid && (lane == 0 || ((ends >> (lane - 1)) & 1ull) != 0);
-          u32 ci = 0, pos = ~0u;
+          // head: page index << 16 | first position (positions < STAGE_CAP
+          // <= 2^15; 0xFFFF: heavy page, not staged), broadcast to its run
+          u32 hp = 0xFFFFu;
           if (head) {
-            ci = S.pidx[pt_find(S, pk)];
+            const u32 ci = S.pidx[pt_find(S, pk)];
+            hp = (ci << 16) | 0xFFFFu;
             if (S.psz[ci] <= HEAVY)
-              pos = atomicAdd(&S.pend[ci], (u32)__builtin_ctzll(ends & ~below) - (u32)lane + 1u);
+              hp = (ci << 16) |
+                   atomicAdd(&S.pend[ci], (u32)__builtin_ctzll(ends & ~below) - (u32)lane + 1u);
           }
           const u64 H = __ballot(head) & (below | (1ull << lane));
           const int hl = H ? 63 - __builtin_clzll(H) : lane;
-          const u32 p0 = __shfl(pos, hl, 64), c0 = __shfl(ci, hl, 64);
-          if (valid && p0 != ~0u && p0 + (u32)(lane - hl) < STAGE_CAP)
-            S.stage[p0 + (u32)(lane - hl)] = (c0 << 11) | (u32)(rv[u] & 2047ull);
+          const u32 h0 = __shfl(hp, hl, 64);
+          const u32 p0 = (h0 & 0xFFFFu) + (u32)(lane - hl);
+          if (valid && (h0 & 0xFFFFu) != 0xFFFFu && p0 < STAGE_CAP)
+            S.stage[p0] = ((h0 >> 16) << 11) | (u32)(rv[u] & 2047ull);
         }
       }
       __syncthreads();
