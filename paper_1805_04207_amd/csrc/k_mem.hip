@@ -571,6 +571,9 @@ __device__ __forceinline__ void match_levels(LaneAcc &L, BucketShared &S, u32 of
                                              u64 pm) {
   const int lane = lane_id();
   const u64 below = (1ull << lane) - 1ull;
+  // counts of the owned nodes at every level first (ballots only), then all
+  // table terms in one batch of loads
+  u32 c[AIWC_NSKIP];
   u64 P = pm;
 #pragma unroll
   for (int k = AIWC_NSKIP - 1; k >= 0; --k) {
@@ -580,14 +583,17 @@ __device__ __forceinline__ void match_levels(LaneAcc &L, BucketShared &S, u32 of
       P &= b ? B : ~B;
     }
     const bool own = P != 0 && (P & below) == 0;
-    const u32 c = own ? (u32)__builtin_popcountll(P) : 0u;
-    if (__ballot(c >= 2) == 0) {          // only single-record nodes: no table term
-      L.dn[k] += c * 0x10001u;           // c is 0 or 1: one node of count 1
-      continue;
-    }
-    add_small_node(L, S, k, c);
-    if (k == 0 && c >= 2) atomicAdd(&S.spec[L.space][c], 1u);
+    c[k] = own ? (u32)__builtin_popcountll(P) : 0u;
   }
+  u64 t[AIWC_NSKIP];
+#pragma unroll
+  for (int k = 0; k < AIWC_NSKIP; ++k) t[k] = S.term[L.space][c[k] >= 2 ? c[k] : 0u];
+#pragma unroll
+  for (int k = 0; k < AIWC_NSKIP; ++k) {
+    L.lo[k] += t[k];
+    L.dn[k] += (c[k] != 0 ? 1u : 0u) + (c[k] == 1 ? 0x10000u : 0u);
+  }
+  if (c[0] >= 2) atomicAdd(&S.spec[L.space][c[0]], 1u);
   // distinct read / written addresses: the lowest read (write) of each level-0 node
   const u64 Bw = __ballot(w != 0);
   const u64 Q = P & (w ? Bw : ~Bw);
