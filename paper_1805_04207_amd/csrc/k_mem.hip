@@ -522,8 +522,9 @@ __device__ __forceinline__ void page_levels(LaneAcc &L, BucketShared &S, SpecRef
     L.ur += __builtin_popcount(rb[lane]);
     L.uw += __builtin_popcount(wb[lane]);
   }
-  // a node position empty in every lane (common: strided pages use one
-  // counter in 2^j) is skipped by the whole wavefront
+  // a level-0 position empty in every lane (common: strided pages use one
+  // counter in 2^j) is skipped by the whole wavefront; the coarser levels
+  // load their terms in one batch
   bool anybig = false;
 #pragma unroll
   for (int j = 0; j < 16; ++j) {
@@ -538,7 +539,6 @@ __device__ __forceinline__ void page_levels(LaneAcc &L, BucketShared &S, SpecRef
 #pragma unroll
     for (int j = 0; j < (16 >> k); ++j) {
       c[j] = c[2 * j] + c[2 * j + 1];
-      if (__ballot(c[j] != 0) == 0) continue;
       add_small_node(L, S, k, c[j] < 256 ? c[j] : 0u);
       anybig |= c[j] >= 256;
     }
