@@ -4,6 +4,10 @@
     python -m paper_1805_04207_amd.profile_summary kstats OUT_kernel_stats.csv \\
         --cmd "<the profiled command>" --title "..." -o profiles/kernels_<workload>.md
 
+    # per-kernel counter table from --pmc runs
+    python -m paper_1805_04207_amd.profile_summary counters run1_results.db run2_results.db \\
+        --cmd "<the commands>" --title "..." -o profiles/counters_<workload>.md
+
     # HBM traffic of one kernel from two --pmc runs (FETCH_SIZE, then WRITE_SIZE),
     # scaled by what the same counters read for the plain copy of known size
     # that `bench.py --pmc-probe` issues after the characterization
@@ -137,6 +141,32 @@ def traffic(args) -> int:
     return 0
 
 
+def counters(args) -> int:
+    """Per-kernel table of the counters of one or more --pmc runs."""
+    acc = defaultdict(dict)
+    for db in args.dbs:
+        con = sqlite3.connect(db)
+        for k, c, v, n in con.execute("select kernel_name, counter_name, sum(value), count(*) "
+                                      "from counters_collection group by kernel_name, "
+                                      "counter_name"):
+            acc[short_name(k)][c] = v / n
+    names = sorted({c for d in acc.values() for c in d})
+    out = [f"# {args.title}", "", "Commands:", "", "```", args.cmd, "```", "",
+           f"Kernel sources hash: `{sources_hash()}`.  Values per dispatch (mean over "
+           "dispatches).", "", "| kernel | " + " | ".join(names) + " |",
+           "|---|" + "---|" * len(names)]
+    for k in sorted(acc):
+        if not k.startswith("k_"):
+            continue
+        out.append(f"| {k} | " + " | ".join(f"{acc[k].get(c, float('nan')):.4g}" for c in names)
+                   + " |")
+    text = "\n".join(out) + "\n"
+    with open(args.o, "w") as f:
+        f.write(text)
+    print(text)
+    return 0
+
+
 def read_traffic(path: str, kernel: str, workload: str):
     """bench.py side: the recorded traffic in bytes per launch, or None when the
     summary is missing, for another kernel or workload, or older than the
@@ -169,8 +199,13 @@ def main(argv=None) -> int:
     b.add_argument("--copy-bytes", type=int, required=True)
     b.add_argument("--cmd", required=True)
     b.add_argument("-o", required=True)
+    c = sub.add_parser("counters")
+    c.add_argument("dbs", nargs="+")
+    c.add_argument("--cmd", required=True)
+    c.add_argument("--title", required=True)
+    c.add_argument("-o", required=True)
     args = ap.parse_args(argv)
-    return kstats(args) if args.cmd_name == "kstats" else traffic(args)
+    return {"kstats": kstats, "traffic": traffic, "counters": counters}[args.cmd_name](args)
 
 
 if __name__ == "__main__":
