@@ -66,7 +66,10 @@ class OrcResult(ctypes.Structure):
                 ("total_branches", ctypes.c_uint64), ("unique_branches", ctypes.c_uint64),
                 ("branches_90", ctypes.c_uint64), ("n_windows", ctypes.c_uint64),
                 ("albe_min_sum", ctypes.c_uint64), ("yokota_entropy", ctypes.c_double),
-                ("linear_branch_entropy", ctypes.c_double)]
+                ("linear_branch_entropy", ctypes.c_double), ("granularity", ctypes.c_double),
+                ("barriers_per_instruction", ctypes.c_double),
+                ("instructions_per_operand", ctypes.c_double),
+                ("load_imbalance", ctypes.c_uint64)]
 
 
 _lib = None
@@ -136,6 +139,47 @@ def _struct_to_dict(s) -> Dict:
         else:
             out[name] = v
     return out
+
+
+class MergedTrace:
+    """Several invocations of one kernel as the one trace they form together.
+
+    The paper reports each kernel as the aggregate over all its invocations
+    at a problem size (Evaluation section).  The aggregate is defined here as
+    the metrics of the concatenation, in order, of the invocations' work-items
+    (instruction streams with their offsets moved behind the events before
+    them), memory streams and branch streams; n_sites is the largest of
+    theirs.  The opcode table and history length must be the same."""
+
+    def __init__(self, traces):
+        traces = list(traces)
+        if not traces:
+            raise ValueError("no invocations")
+        t0 = traces[0]
+        tab0 = np.asarray(t0.table)
+        for t in traces[1:]:
+            if int(t.history_len) != int(t0.history_len) or \
+                    not np.array_equal(np.asarray(t.table), tab0):
+                raise ValueError("invocations differ in opcode table or history length")
+        self.table = tab0
+        self.history_len = int(t0.history_len)
+        self.n_sites = max(int(t.n_sites) for t in traces)
+        self.opcode = np.concatenate([_as(t.opcode, np.uint16) for t in traces])
+        offs, base = [np.zeros(1, dtype=np.uint64)], 0
+        for t in traces:
+            o = _as(t.wi_offsets, np.uint64)
+            offs.append(o[1:] + np.uint64(base))
+            base += int(o[-1])
+        self.wi_offsets = np.concatenate(offs)
+        self.addr = np.concatenate([_as(t.addr, np.uint64) for t in traces])
+        self.mem_kind = np.concatenate([_as(t.mem_kind, np.uint8) for t in traces])
+        self.br_site = np.concatenate([_as(t.br_site, np.uint32) for t in traces])
+        self.br_taken = np.concatenate([_as(t.br_taken, np.uint8) for t in traces])
+
+
+def characterize_merged(traces) -> Dict:
+    """Metrics of several invocations taken together (see MergedTrace)."""
+    return characterize(MergedTrace(traces))
 
 
 def characterize(tr) -> Dict:

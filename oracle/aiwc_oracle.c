@@ -289,6 +289,24 @@ static int branch_metrics(const orc_trace *t, orc_result *r) {
   return 0;
 }
 
+/* ---------------------------------------------------------------- derived
+ * LU decomposition analysis (Evaluation section): the parallelism spokes of
+ * the radar diagram are inverses of collected metrics -- granularity =
+ * 1 / work-items, barriers per instruction = 1 / mean ITB, instructions per
+ * operand = 1 / (summed SIMD widths) -- and load imbalance = max IPT - min
+ * IPT.  Reading: "summed SIMD widths" is taken per instruction, i.e. the
+ * mean SIMD width, so instructions per operand = instructions / S1 (the
+ * ratio the name states, in (0, 1] like its sibling spokes).  Mean ITB =
+ * (sum of ITB values) / (number of ITB values), so its inverse is the single
+ * division count / sum.  Divisions by zero follow IEEE (x/0 = inf, 0/0 =
+ * NaN), as the other ratios of the result do.                              */
+static void derived_metrics(orc_result *r) {
+  r->granularity = 1.0 / (double)r->work_items;
+  r->barriers_per_instruction = (double)r->itb_count / (double)r->itb_sum;
+  r->instructions_per_operand = (double)r->total_instructions / (double)r->simd_sum;
+  r->load_imbalance = r->ipt_max - r->ipt_min;
+}
+
 static int check_trace(const orc_trace *t) {
   if (!t || t->history_len < 1 || t->history_len > 32) return 1;
   if (t->n_events && (!t->opcode || !t->table)) return 1;
@@ -314,6 +332,7 @@ int orc_characterize(const orc_trace *t, orc_result *out) {
   if (!rc) rc = space_metrics(t, 0, &r.space[0]);
   if (!rc) rc = space_metrics(t, 1, &r.space[1]);
   if (!rc) rc = branch_metrics(t, &r);
+  if (!rc) derived_metrics(&r);
   if (!rc) *out = r;
   return rc;
 }

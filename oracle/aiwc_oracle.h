@@ -64,6 +64,9 @@ typedef struct orc_result {
   uint64_t total_branches, unique_branches, branches_90;
   uint64_t n_windows, albe_min_sum;
   double yokota_entropy, linear_branch_entropy;
+  /* derived parallelism metrics (LU decomposition analysis) */
+  double granularity, barriers_per_instruction, instructions_per_operand;
+  uint64_t load_imbalance;
 } orc_result;
 
 /* 0 = ok, 1 = invalid trace, 2 = out of memory */

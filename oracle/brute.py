@@ -135,4 +135,11 @@ def characterize(opcode, wi_offsets, table, addr, mem_kind, br_site, br_taken,
     r["albe_min_sum"] = mins
     r["yokota_entropy"] = yok / nw if nw else mpmath.mpf(0)
     r["linear_branch_entropy"] = float(Fraction(2 * mins, nw)) if nw else 0.0
+    # derived parallelism metrics (LU decomposition analysis): exact
+    # rationals rounded once, IEEE conventions for a zero denominator
+    ratio = lambda a, b: float(Fraction(a, b)) if b else (float("inf") if a else float("nan"))
+    r["granularity"] = ratio(1, r["work_items"])
+    r["barriers_per_instruction"] = ratio(r["itb_count"], r["itb_sum"])
+    r["instructions_per_operand"] = ratio(r["total_instructions"], r["simd_sum"])
+    r["load_imbalance"] = r["ipt_max"] - r["ipt_min"]
     return r

@@ -294,4 +294,20 @@ def characterize(tr, threads: int = 16, progress=None) -> Dict:
     say("memory metrics done")
     _branches(tr, r, threads)
     say("branch metrics done")
+    _derived(r)
     return r
+
+
+def _ieee_div(a: int, b: int) -> float:
+    """a / b as one IEEE double division (x/0 = inf, 0/0 = NaN)."""
+    return float(np.float64(a) / np.float64(b)) if b else (float("inf") if a else float("nan"))
+
+
+def _derived(r: Dict) -> None:
+    """Derived parallelism metrics of the LU decomposition analysis
+    (Evaluation section): inverses of work-items, mean ITB and mean SIMD
+    width, and load imbalance = max IPT - min IPT."""
+    r["granularity"] = _ieee_div(1, r["work_items"])
+    r["barriers_per_instruction"] = _ieee_div(r["itb_count"], r["itb_sum"])
+    r["instructions_per_operand"] = _ieee_div(r["total_instructions"], r["simd_sum"])
+    r["load_imbalance"] = r["ipt_max"] - r["ipt_min"]

@@ -16,8 +16,9 @@ from typing import Dict, List
 INT_TOP = ["total_instructions", "unique_opcodes", "opcodes_90", "simd_max", "simd_sum",
            "simd_sumsq_lo", "simd_sumsq_hi", "work_items", "barriers_hit", "itb_count",
            "itb_sum", "itb_min", "itb_max", "ipt_min", "ipt_max", "total_branches",
-           "unique_branches", "branches_90", "n_windows", "albe_min_sum"]
-EXACT_TOP = ["simd_mean", "itb_median", "ipt_median", "linear_branch_entropy"]
+           "unique_branches", "branches_90", "n_windows", "albe_min_sum", "load_imbalance"]
+EXACT_TOP = ["simd_mean", "itb_median", "ipt_median", "linear_branch_entropy", "granularity",
+             "barriers_per_instruction", "instructions_per_operand"]
 INT_SPACE = ["total_accesses", "total_reads", "total_writes", "unique_reads", "unique_writes",
              "footprint", "footprint_90"]
 EXACT_SPACE = ["unique_rw_ratio", "reread_ratio", "rewrite_ratio"]
