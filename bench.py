@@ -110,7 +110,23 @@ def batch_legs(ctx, tr, spec, n_ev, args, stream):
                       "identical": all(strip(a) == strip(b) for a, b in zip(plain, got)),
                       "waves": st["waves"], "redo_partitions": st["redo_partitions"],
                       "total_partitions": st["total_partitions"]}
-    del keep, trs, plain, got
+    # the same traces as the invocations of one kernel: their aggregate in
+    # one merged call (staged concatenation + one pass of the whole path)
+    mg = ctx.characterize_merged(trs, stream).read()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(max(1, args.steps // 2)):
+        mg = ctx.characterize_merged(trs, stream).read()
+    torch.cuda.synchronize()
+    dt_merged = (time.perf_counter() - t0) / max(1, args.steps // 2)
+    sums = all(mg[f] == sum(p[f] for p in plain) for f in
+               ("total_instructions", "work_items", "itb_sum", "total_branches"))
+    out["config3"]["merged"] = {
+        "events_per_s": total / dt_merged, "ms": 1e3 * dt_merged,
+        "global_distinct0": mg["space"][0]["distinct"][0],
+        "sum_of_parts_distinct0": sum(p["space"][0]["distinct"][0] for p in plain),
+        "totals_are_sums_of_parts": bool(sums)}
+    del keep, trs, plain, got, mg
     if not args.no_stress:
         out["stress"] = stress_leg(ctx, args, sizing, stream)
     return out

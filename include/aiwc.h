@@ -188,6 +188,14 @@ typedef struct aiwc_metrics_host {
   uint64_t albe_min_sum;            /* sum over (site, history) of min(n0,n1) */
   double yokota_entropy;            /* H(outcome | site, history), in [0,1]  */
   double linear_branch_entropy;     /* 2 * albe_min_sum / n_windows          */
+  /* derived parallelism metrics (LU decomposition analysis of the paper:
+     the inverted values plotted on the radar diagram, and load imbalance);
+     each is one IEEE operation on the exact integers above               */
+  double granularity;               /* 1 / work_items                        */
+  double barriers_per_instruction;  /* 1 / mean ITB = itb_count / itb_sum    */
+  double instructions_per_operand;  /* total_instructions / simd_sum, i.e.
+                                       1 / mean SIMD width                   */
+  uint64_t load_imbalance;          /* ipt_max - ipt_min                     */
   /* bookkeeping */
   uint32_t overflow_redos;          /* on-chip table overflows redone        */
   uint32_t partitions;              /* memory partitions used (both spaces)  */
@@ -237,6 +245,28 @@ aiwc_status aiwc_trace_destroy(aiwc_trace *trace);
  * Errors: INVALID_ARG, OUT_OF_MEMORY, HIP.                                   */
 aiwc_status aiwc_characterize(aiwc_ctx *ctx, const aiwc_trace *trace,
                               void *stream, aiwc_metrics **out);
+
+/* Metrics of several invocations of one kernel taken together (the paper
+ * reports each kernel as the aggregate over all its invocations at a problem
+ * size: Evaluation section).  The result is, by definition, that of the one
+ * trace formed by concatenating the invocations in the order given: their
+ * work-items and instruction streams, memory streams and branch streams.  So
+ * counts add up, distinct counts are those of the union of the addresses
+ * (an address touched by two invocations counts once, with its accesses
+ * summed), entropies and footprints are over the pooled accesses, ITB and
+ * IPT statistics over the pooled segments and work-items, and a branch
+ * site's history runs on from one invocation into the next.
+ *   traces[n]   n >= 1 handles of this context, all with the same opcode
+ *               table and history_len.  n_sites of the result is the largest
+ *               of theirs.  The summed n_mem and n_branch must stay < 2^32.
+ * The concatenation is staged in device memory owned by the returned handle
+ * (about 2 B per event + 9 B per memory event + 5 B per branch event + 8 B
+ * per work-item), released by aiwc_metrics_destroy.  With n == 1 it is
+ * aiwc_characterize.  Errors: INVALID_ARG (null, empty list, foreign handle,
+ * tables or history lengths differ, sums over the limits), OUT_OF_MEMORY,
+ * HIP.                                                                      */
+aiwc_status aiwc_characterize_merged(aiwc_ctx *ctx, const aiwc_trace *const *traces,
+                                     size_t n, void *stream, aiwc_metrics **out);
 
 /* Sizing policy for the memory partitions and on-chip tables.             */
 typedef enum aiwc_sizing {

@@ -69,7 +69,10 @@ class MetricsHost(ctypes.Structure):
                 ("total_branches", ctypes.c_uint64), ("unique_branches", ctypes.c_uint64),
                 ("branches_90", ctypes.c_uint64), ("n_windows", ctypes.c_uint64),
                 ("albe_min_sum", ctypes.c_uint64), ("yokota_entropy", ctypes.c_double),
-                ("linear_branch_entropy", ctypes.c_double), ("overflow_redos", ctypes.c_uint32),
+                ("linear_branch_entropy", ctypes.c_double), ("granularity", ctypes.c_double),
+                ("barriers_per_instruction", ctypes.c_double),
+                ("instructions_per_operand", ctypes.c_double),
+                ("load_imbalance", ctypes.c_uint64), ("overflow_redos", ctypes.c_uint32),
                 ("partitions", ctypes.c_uint32)]
 
 
@@ -95,7 +98,8 @@ class TrainOpts(ctypes.Structure):
 
 EXPORTS = [
     "aiwc_context_create", "aiwc_context_destroy", "aiwc_last_error", "aiwc_trace_create",
-    "aiwc_trace_destroy", "aiwc_characterize", "aiwc_characterize_batch", "aiwc_batch_last_stats",
+    "aiwc_trace_destroy", "aiwc_characterize", "aiwc_characterize_merged",
+    "aiwc_characterize_batch", "aiwc_batch_last_stats",
     "aiwc_metrics_read", "aiwc_metrics_class_hist", "aiwc_metrics_spectrum", "aiwc_metrics_destroy",
     "aiwc_sizer_features", "aiwc_sizer_train", "aiwc_sizer_predict", "aiwc_sizer_grad",
     "aiwc_sizer_num_params", "aiwc_sizer_get_params", "aiwc_sizer_set_params", "aiwc_sizer_save",
@@ -126,6 +130,7 @@ def load_library(path: str = LIB_PATH):
         "aiwc_trace_create": (st, [vp, ctypes.POINTER(TraceDesc), ctypes.POINTER(vp)]),
         "aiwc_trace_destroy": (st, [vp]),
         "aiwc_characterize": (st, [vp, vp, vp, ctypes.POINTER(vp)]),
+        "aiwc_characterize_merged": (st, [vp, ctypes.POINTER(vp), sz, vp, ctypes.POINTER(vp)]),
         "aiwc_characterize_batch": (st, [vp, ctypes.POINTER(vp), sz, ctypes.POINTER(BatchOpts), vp,
                                          ctypes.POINTER(vp)]),
         "aiwc_batch_last_stats": (st, [vp, ctypes.POINTER(BatchStats)]),
@@ -208,6 +213,15 @@ class Context:
         m = ctypes.c_void_p()
         self.check(self.lib.aiwc_characterize(self.h, trace.h, _stream_ptr(stream),
                                               ctypes.byref(m)))
+        return Metrics(self, m)
+
+    def characterize_merged(self, traces: Sequence["Trace"], stream=None) -> "Metrics":
+        """Metrics of the invocations taken together (their concatenation)."""
+        n = len(traces)
+        arr = (ctypes.c_void_p * max(1, n))(*[t.h.value for t in traces])
+        m = ctypes.c_void_p()
+        self.check(self.lib.aiwc_characterize_merged(self.h, arr, n, _stream_ptr(stream),
+                                                     ctypes.byref(m)))
         return Metrics(self, m)
 
     def characterize_batch(self, traces: Sequence["Trace"], sizing: int = SIZING_BOUND,

@@ -482,6 +482,107 @@ extern "C" aiwc_status aiwc_characterize(aiwc_ctx *ctx, const aiwc_trace *t, voi
   return characterize_planned(ctx, t, pbits, (hipStream_t)stream, out);
 }
 
+// Several invocations as one: their streams are concatenated in a staging
+// block owned by the metrics handle, then reduced by the ordinary path.
+extern "C" aiwc_status aiwc_characterize_merged(aiwc_ctx *ctx, const aiwc_trace *const *traces,
+                                                size_t n, void *stream, aiwc_metrics **out) {
+  if (!ctx || !traces || !out || n == 0) {
+    ctx_error(ctx, "aiwc_characterize_merged: NULL argument or empty list");
+    return AIWC_ERR_INVALID_ARG;
+  }
+  for (size_t i = 0; i < n; ++i)
+    if (!traces[i] || traces[i]->ctx != ctx) {
+      ctx_error(ctx, "aiwc_characterize_merged: trace %zu is NULL or belongs to another context", i);
+      return AIWC_ERR_INVALID_ARG;
+    }
+  const aiwc_trace *t0 = traces[0];
+  if (n == 1) return aiwc_characterize(ctx, t0, stream, out);
+  u64 n_ev = 0, n_wi = 0, n_mem = 0, n_br = 0;
+  u32 n_sites = 0;
+  for (size_t i = 0; i < n; ++i) {
+    const aiwc_trace *t = traces[i];
+    if (t->d.history_len != t0->d.history_len || t->host_info != t0->host_info) {
+      ctx_error(ctx, "aiwc_characterize_merged: trace %zu has another opcode table or history "
+                "length than trace 0", i);
+      return AIWC_ERR_INVALID_ARG;
+    }
+    n_ev += t->d.n_events;
+    n_wi += t->d.n_workitems;
+    n_mem += t->d.n_mem;
+    n_br += t->d.n_branch;
+    n_sites = std::max(n_sites, t->d.n_sites);
+  }
+  if (n_mem >= (1ull << 32) || n_br >= (1ull << 32)) {
+    ctx_error(ctx, "aiwc_characterize_merged: summed n_mem and n_branch must be < 2^32");
+    return AIWC_ERR_INVALID_ARG;
+  }
+  auto al = [](u64 x) { return (x + 255) & ~255ull; };
+  const u64 o_off = al(2 * n_ev), o_addr = o_off + al(8 * (n_wi + 1));
+  const u64 o_kind = o_addr + al(8 * n_mem), o_site = o_kind + al(n_mem);
+  const u64 o_taken = o_site + al(4 * n_br), total = o_taken + al(n_br);
+  HIP_OR(ctx, hipSetDevice(ctx->device));
+  char *stage = nullptr;
+  if (hipMalloc(&stage, total) != hipSuccess) {
+    hipGetLastError();
+    ctx_error(ctx, "out of device memory: %llu bytes to stage the merged trace",
+              (unsigned long long)total);
+    return AIWC_ERR_OUT_OF_MEMORY;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  const hipMemcpyKind D2D = hipMemcpyDeviceToDevice;
+  hipError_t e = hipSuccess;
+  u64 ev = 0, wi = 0, mem = 0, br = 0;
+  for (size_t i = 0; i < n && e == hipSuccess; ++i) {
+    const aiwc_trace_desc &d = traces[i]->d;
+    if (d.n_events) e = hipMemcpyAsync(stage + 2 * ev, d.opcode, 2 * d.n_events, D2D, s);
+    if (e == hipSuccess)
+      e = aiwc_kernels::launch_merge_offsets((u64 *)(stage + o_off) + wi, (const u64 *)d.wi_offsets,
+                                             d.n_workitems, ev, i == 0, s);
+    if (e == hipSuccess && d.n_mem) e = hipMemcpyAsync(stage + o_addr + 8 * mem, d.addr, 8 * d.n_mem, D2D, s);
+    if (e == hipSuccess && d.n_mem) e = hipMemcpyAsync(stage + o_kind + mem, d.mem_kind, d.n_mem, D2D, s);
+    if (e == hipSuccess && d.n_branch) e = hipMemcpyAsync(stage + o_site + 4 * br, d.br_site, 4 * d.n_branch, D2D, s);
+    if (e == hipSuccess && d.n_branch) e = hipMemcpyAsync(stage + o_taken + br, d.br_taken, d.n_branch, D2D, s);
+    ev += d.n_events;
+    wi += d.n_workitems;
+    mem += d.n_mem;
+    br += d.n_branch;
+  }
+  if (e != hipSuccess) {
+    ctx_error(ctx, "staging the merged trace failed: %s", hipGetErrorString(e));
+    hipStreamSynchronize(s);
+    hipFree(stage);
+    return AIWC_ERR_HIP;
+  }
+  // the concatenation, with the first invocation's opcode table (borrowed)
+  aiwc_trace mt;
+  mt.ctx = ctx;
+  mt.d = t0->d;
+  mt.d.flags = 0;
+  mt.d.n_events = n_ev;
+  mt.d.opcode = (const uint16_t *)stage;
+  mt.d.n_workitems = n_wi;
+  mt.d.wi_offsets = (const uint64_t *)(stage + o_off);
+  mt.d.n_mem = n_mem;
+  mt.d.addr = (const uint64_t *)(stage + o_addr);
+  mt.d.mem_kind = (const uint8_t *)(stage + o_kind);
+  mt.d.n_branch = n_br;
+  mt.d.br_site = (const uint32_t *)(stage + o_site);
+  mt.d.br_taken = (const uint8_t *)(stage + o_taken);
+  mt.d.n_sites = n_sites;
+  mt.n_classes = t0->n_classes;
+  mt.dev_info = t0->dev_info;
+  aiwc_metrics *m = nullptr;
+  aiwc_status st = characterize_planned(ctx, &mt, bound_pbits(n_mem), s, &m);
+  if (st != AIWC_OK) {
+    hipStreamSynchronize(s);
+    hipFree(stage);
+    return st;
+  }
+  m->stage = stage;
+  *out = m;
+  return AIWC_OK;
+}
+
 // ------------------------------------------------------------------ metrics
 extern "C" aiwc_status aiwc_metrics_read(aiwc_metrics *m, aiwc_metrics_host *out) {
   if (!m || !out) { ctx_error(m ? m->ctx : nullptr, "aiwc_metrics_read: NULL argument"); return AIWC_ERR_INVALID_ARG; }
@@ -562,6 +663,7 @@ extern "C" aiwc_status aiwc_metrics_destroy(aiwc_metrics *m) {
   } else if (m->buf) {
     hipFree(m->buf);
   }
+  if (m->stage) hipFree(m->stage);
   delete m;
   return AIWC_OK;
 }

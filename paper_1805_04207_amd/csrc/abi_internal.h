@@ -90,6 +90,7 @@ struct aiwc_metrics {
   SharedBuf *shared = nullptr;   // set when buf points into a batch block
   hipEvent_t done = nullptr;
   u32 spec_pairs[2] = {0, 0};
+  void *stage = nullptr;         // concatenated trace of a merged call
 };
 
 void ctx_error(aiwc_ctx *ctx, const char *fmt, ...);

@@ -211,6 +211,8 @@ hipError_t launch_branch(const TraceArgs &a, const BatchDims &d, hipStream_t s, 
 hipError_t launch_finalize(const TraceArgs &a, const BatchDims &d, hipStream_t s, StageMarks *pm);
 u64 scan_blocks_for(u64 n);
 size_t ops_lds_bytes(u32 n_ids);
+hipError_t launch_merge_offsets(u64 *dst, const u64 *src, u64 n_wi, u64 base, bool first,
+                                hipStream_t s);
 }  // namespace aiwc_kernels
 
 #define AIWC_MARK(pm, name, s) \

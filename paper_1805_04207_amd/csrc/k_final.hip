@@ -322,6 +322,13 @@ __global__ void __launch_bounds__(FB) k_finalize(TraceArgs A0, const TraceArgs *
   const double nw = (double)acc->br_windows;
   o->yokota_entropy = acc->br_windows ? fx64_to_double(acc->yok_lo, acc->yok_hi) / nw : 0.0;
   o->linear_branch_entropy = acc->br_windows ? (double)(2 * acc->br_minsum) / nw : 0.0;
+  // derived parallelism metrics of the LU analysis: inverses of work-items,
+  // mean ITB and mean SIMD width as single divisions of the exact integers
+  // (x/0 = inf, 0/0 = NaN), and the spread of instructions per work-item
+  o->granularity = 1.0 / (double)A.n_wi;
+  o->barriers_per_instruction = (double)acc->itb_cnt / (double)acc->itb_sum;
+  o->instructions_per_operand = (double)A.n_events / (double)s1;
+  o->load_imbalance = o->ipt_max - o->ipt_min;
   o->overflow_redos = (uint32_t)acc->redos;
   o->partitions = A.n_mem ? (1u << A.pbits) : 0u;
   // status words: [0] invalid content, [1] inconsistent kinds, [2] spectrum pairs

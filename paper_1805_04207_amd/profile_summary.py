@@ -16,8 +16,9 @@
         --cmd "<the two commands>" -o profiles/traffic_k_mem_bucket_<workload>.md
 
 The traffic summary ends with one machine-readable line
-`traffic-json: {...}` that bench.py reads; it carries a hash of the kernel
-sources so that a stale measurement is not reported for changed kernels.
+`traffic-json: {...}` that bench.py reads; it carries a hash of the source
+files that define the kernel and of the shared headers, so that a stale
+measurement is not reported for a changed kernel.
 """
 from __future__ import annotations
 
@@ -37,13 +38,17 @@ CSRC = os.path.join(HERE, "csrc")
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
 
 
-def sources_hash() -> str:
-    """sha256 over every kernel source and header the library is built from."""
+def sources_hash(kernel: str | None = None) -> str:
+    """sha256 over the kernel sources and headers the library is built from;
+    with `kernel`, over the headers and the source files that name it."""
     h = hashlib.sha256()
     for p in sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.h"))):
-        h.update(os.path.basename(p).encode())
         with open(p, "rb") as f:
-            h.update(f.read())
+            text = f.read()
+        if kernel and p.endswith(".hip") and kernel.encode() not in text:
+            continue
+        h.update(os.path.basename(p).encode())
+        h.update(text)
     return h.hexdigest()[:16]
 
 
@@ -118,7 +123,7 @@ def traffic(args) -> int:
     wb = write[args.kernel][0] * 1024.0 * w_scale
     rec = {"kernel": args.kernel, "workload": args.workload, "fetch_bytes": fb, "write_bytes": wb,
            "traffic_bytes": fb + wb, "fetch_scale": f_scale, "write_scale": w_scale,
-           "sources": sources_hash()}
+           "sources": sources_hash(args.kernel)}
     out = [f"# HBM traffic of {args.kernel}: {args.workload}", "", "Commands:", "", "```",
            args.cmd, "```", "",
            f"Counters are KiB per dispatch, averaged over the dispatches of each kernel; the "
@@ -178,7 +183,7 @@ def read_traffic(path: str, kernel: str, workload: str):
             if line.startswith("traffic-json: "):
                 rec = json.loads(line[len("traffic-json: "):])
                 if rec.get("kernel") == kernel and rec.get("workload") == workload and \
-                        rec.get("sources") == sources_hash():
+                        rec.get("sources") == sources_hash(kernel):
                     return rec
     return None
 

@@ -9,6 +9,12 @@
   batched call with learned sizing, autotuning and a replayed graph: every
   trace identical to its plain per-trace result, the three smallest against
   the C oracle and a mid-size one against the vectorised oracle.
+* The aggregate over invocations: the plain large trace cut into 8
+  invocations (work-items at random boundaries, memory and branch streams at
+  random points) and merged must equal the plain path on the whole; the 512
+  uneven invocations merged must satisfy every relation between an aggregate
+  and its parts, and the 256 smallest merged must match the vectorised oracle
+  on their concatenation.
 * The stress batch (64 traces, 2^32 addresses in total, up to 2^28 per trace,
   history 32 over 2^16 sites) in one batched call with learned sizing and a
   200 GiB admission cap: the two smallest traces against the C oracle, every
@@ -199,3 +205,102 @@ def test_uneven_batch_full_size():
     assert not bad, f"trace {mid}:\n" + "\n".join(bad[:20])
     log(f"oracle parity on traces {int(order[0])}, {int(order[1])}, {int(order[2])} and {mid} "
         f"({n_ev[mid]} events)")
+
+
+@pytest.mark.timeout(1200)
+def test_merged_pieces_of_the_large_trace():
+    import torch
+    import paper_1805_04207_amd as aiwc
+
+    spec = tg.config2(n_wi=1 << 20)
+    d = tg.generate_device(spec, 0)
+    ctx = aiwc.Context(0)
+    tab = tg.opcode_table()
+    whole = aiwc.device_trace(ctx, d, tab, spec.n_sites, spec.history_len, spec.wg_size)
+    plain = ctx.characterize(whole).read()
+    rng = np.random.default_rng(77)
+    k = 8
+    wcut = np.sort(rng.choice(np.arange(1, spec.n_wi), size=k - 1, replace=False))
+    wcut = np.concatenate([[0], wcut, [spec.n_wi]]).astype(np.int64)
+    off = d["wi_offsets"]
+    ecut = off[torch.from_numpy(wcut).to(off.device)].cpu().numpy()
+    mcut = np.concatenate([[0], np.sort(rng.integers(0, d["n_mem"] + 1, size=k - 1)),
+                           [d["n_mem"]]])
+    bcut = np.concatenate([[0], np.sort(rng.integers(0, d["n_branch"] + 1, size=k - 1)),
+                           [d["n_branch"]]])
+    keep, pieces = [], []
+    for i in range(k):
+        p = {"opcode": d["opcode"][ecut[i]:ecut[i + 1]],
+             "wi_offsets": (off[wcut[i]:wcut[i + 1] + 1] - off[wcut[i]]).contiguous(),
+             "addr": d["addr"][mcut[i]:mcut[i + 1]], "mem_kind": d["mem_kind"][mcut[i]:mcut[i + 1]],
+             "br_site": d["br_site"][bcut[i]:bcut[i + 1]],
+             "br_taken": d["br_taken"][bcut[i]:bcut[i + 1]]}
+        keep.append(p)
+        pieces.append(aiwc.device_trace(ctx, p, tab, spec.n_sites, spec.history_len, spec.wg_size))
+    torch.cuda.synchronize()
+    log(f"{k} pieces: work-item cuts {wcut.tolist()}")
+    got = ctx.characterize_merged(pieces).read()
+    assert same(got, plain), "merged pieces differ from the whole"
+    log("merged pieces identical to the plain path on the whole")
+
+
+@pytest.mark.timeout(1200)
+def test_merged_uneven_invocations_full_size():
+    import torch
+    import paper_1805_04207_amd as aiwc
+
+    specs = tg.config3_specs(seed=2, n_traces=512, scale=1.0)
+    ctx = aiwc.Context(0)
+    keep, trs, n_ev = [], [], []
+    for sp in specs:
+        d = tg.generate_device(sp, 0)
+        keep.append(d)
+        n_ev.append(d["n_events"])
+        trs.append(aiwc.device_trace(ctx, d, tg.opcode_table(), sp.n_sites, sp.history_len,
+                                     sp.wg_size))
+    torch.cuda.synchronize()
+    m = ctx.characterize_merged(trs)
+    r = m.read()
+    ncls = int(np.asarray(tg.opcode_table())["op_class"].max()) + 1
+    cls = np.asarray(m.class_hist(ncls))
+    log(f"merged {len(trs)} invocations, {sum(n_ev)} events")
+    parts, pcls = [], np.zeros(ncls, dtype=np.uint64)
+    for t in trs:
+        pm = ctx.characterize(t)
+        parts.append(pm.read())
+        pcls += np.asarray(pm.class_hist(ncls), dtype=np.uint64)
+    # relations between an aggregate and its parts
+    tot = lambda f: sum(p[f] for p in parts)
+    for f in ("total_instructions", "work_items", "barriers_hit", "itb_count", "itb_sum",
+              "simd_sum", "total_branches"):
+        assert r[f] == tot(f), f
+    assert r["simd_max"] == max(p["simd_max"] for p in parts)
+    assert r["itb_min"] == min(p["itb_min"] for p in parts)
+    assert r["itb_max"] == max(p["itb_max"] for p in parts)
+    assert r["ipt_min"] == min(p["ipt_min"] for p in parts)
+    assert r["ipt_max"] == max(p["ipt_max"] for p in parts)
+    assert r["load_imbalance"] == r["ipt_max"] - r["ipt_min"]
+    assert np.array_equal(cls, pcls)
+    assert max(p["unique_branches"] for p in parts) <= r["unique_branches"] <= tot("unique_branches")
+    assert tot("n_windows") <= r["n_windows"] <= r["total_branches"]
+    for s in (0, 1):
+        sp = r["space"][s]
+        for f in ("total_accesses", "total_reads", "total_writes"):
+            assert sp[f] == sum(p["space"][s][f] for p in parts), (s, f)
+        for f in ("unique_reads", "unique_writes"):
+            vals = [p["space"][s][f] for p in parts]
+            assert max(vals) <= sp[f] <= sum(vals), (s, f)
+        for kk in range(11):
+            vals = [p["space"][s]["distinct"][kk] for p in parts]
+            assert max(vals) <= sp["distinct"][kk] <= sum(vals), (s, kk)
+    loc = r["space"][1]["total_accesses"]
+    invariants(r, (r["space"][0]["total_accesses"], loc))
+    log("aggregate consistent with its 512 parts")
+    # exact parity on the 256 smallest invocations merged
+    order = np.argsort(n_ev)[:256]
+    sub = [trs[i] for i in order]
+    got = ctx.characterize_merged(sub).read()
+    want = bulk.characterize(oracle.MergedTrace([tg.generate_host(specs[i]) for i in order]))
+    bad = compare(got, want)
+    assert not bad, "\n".join(bad[:20])
+    log(f"256 smallest merged ({sum(n_ev[i] for i in order)} events) match the oracle")
