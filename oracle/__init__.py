@@ -40,7 +40,11 @@ class OrcTrace(ctypes.Structure):
                 ("addr", ctypes.c_void_p), ("mem_kind", ctypes.c_void_p),
                 ("n_branch", ctypes.c_uint64), ("br_site", ctypes.c_void_p),
                 ("br_taken", ctypes.c_void_p), ("history_len", ctypes.c_uint32),
-                ("pad", ctypes.c_uint32)]
+                ("flags", ctypes.c_uint32)]
+
+# branch-entropy variants (trace attribute `branch_flags`; the values are the
+# interface of the trace flags)
+BR_ZERO_HISTORY, BR_GLOBAL_HISTORY, BR_PATTERN = 2, 4, 8
 
 
 class OrcSpace(ctypes.Structure):
@@ -66,7 +70,8 @@ class OrcResult(ctypes.Structure):
                 ("total_branches", ctypes.c_uint64), ("unique_branches", ctypes.c_uint64),
                 ("branches_90", ctypes.c_uint64), ("n_windows", ctypes.c_uint64),
                 ("albe_min_sum", ctypes.c_uint64), ("yokota_entropy", ctypes.c_double),
-                ("linear_branch_entropy", ctypes.c_double), ("granularity", ctypes.c_double),
+                ("linear_branch_entropy", ctypes.c_double),
+                ("pattern_entropy", ctypes.c_double), ("granularity", ctypes.c_double),
                 ("barriers_per_instruction", ctypes.c_double),
                 ("instructions_per_operand", ctypes.c_double),
                 ("load_imbalance", ctypes.c_uint64)]
@@ -124,6 +129,7 @@ class _Bound:
         t.br_site = self.site.ctypes.data
         t.br_taken = self.taken.ctypes.data
         t.history_len = int(tr.history_len)
+        t.flags = int(getattr(tr, "branch_flags", 0))
         self.t = t
 
 
@@ -159,10 +165,13 @@ class MergedTrace:
         tab0 = np.asarray(t0.table)
         for t in traces[1:]:
             if int(t.history_len) != int(t0.history_len) or \
+                    int(getattr(t, "branch_flags", 0)) != int(getattr(t0, "branch_flags", 0)) or \
                     not np.array_equal(np.asarray(t.table), tab0):
-                raise ValueError("invocations differ in opcode table or history length")
+                raise ValueError("invocations differ in opcode table, history length or "
+                                 "branch variant")
         self.table = tab0
         self.history_len = int(t0.history_len)
+        self.branch_flags = int(getattr(t0, "branch_flags", 0))
         self.n_sites = max(int(t.n_sites) for t in traces)
         self.opcode = np.concatenate([_as(t.opcode, np.uint16) for t in traces])
         offs, base = [np.zeros(1, dtype=np.uint64)], 0

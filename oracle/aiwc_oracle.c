@@ -231,7 +231,21 @@ static int space_metrics(const orc_trace *t, int space, orc_space *s) {
  *   average linear branch entropy = sum_keys n * 2 min(p, 1-p) / N_w
  *                                 = 2 sum_keys min(n0, n1) / N_w
  * (De Pestel's linear entropy weighted by pattern frequency); both 0 when
- * N_w = 0.                                                                  */
+ * N_w = 0.
+ * Variants (trace flags):
+ *   ORC_BR_ZERO_HISTORY   every history starts as m not-taken outcomes and
+ *                         every execution forms a window (N_w = n_branch).
+ *   ORC_BR_GLOBAL_HISTORY one history register over all branches in stream
+ *                         order (the "combined" history of the Implementation
+ *                         section); the key is still (site, h).  Windows
+ *                         start once m earlier outcomes of any site exist
+ *                         (N_w = max(0, n_branch - m)), or at once with
+ *                         ORC_BR_ZERO_HISTORY.
+ *   ORC_BR_PATTERN        Yokota's branch history entropy in its pattern
+ *                         form: E_m = sum_p c_p log2(N_w / c_p) over the
+ *                         m-bit histories p of the windows (whatever their
+ *                         site), reported normalised as E_m / m in [0, 1];
+ *                         0 when N_w = 0, NaN when not requested.          */
 typedef struct { uint64_t key; uint64_t y; } win_t;
 
 static int cmp_win(const void *a, const void *b) {
@@ -246,18 +260,30 @@ static int branch_metrics(const orc_trace *t, orc_result *r) {
   uint64_t *hist = (uint64_t *)calloc(t->n_sites ? t->n_sites : 1, sizeof(uint64_t));
   uint64_t *seen = (uint64_t *)calloc(t->n_sites ? t->n_sites : 1, sizeof(uint64_t));
   win_t *win = (win_t *)malloc((t->n_branch ? t->n_branch : 1) * sizeof(win_t));
-  if (!hist || !seen || !win) { free(hist); free(seen); free(win); return 2; }
+  uint64_t *pat = (uint64_t *)malloc((t->n_branch ? t->n_branch : 1) * sizeof(uint64_t));
+  if (!hist || !seen || !win || !pat) {
+    free(hist); free(seen); free(win); free(pat);
+    return 2;
+  }
+  const int zero = (t->flags & ORC_BR_ZERO_HISTORY) != 0;
+  const int glob = (t->flags & ORC_BR_GLOBAL_HISTORY) != 0;
+  uint64_t gh = 0, gseen = 0;   /* the one register of the global variant */
   size_t nw = 0;
   for (uint64_t i = 0; i < t->n_branch; ++i) {
     uint32_t s = t->br_site[i];
     uint64_t y = t->br_taken[i];
-    if (seen[s] >= m) {
-      win[nw].key = ((uint64_t)s << m) | hist[s];
+    uint64_t h = glob ? gh : hist[s];
+    uint64_t before = glob ? gseen : seen[s];
+    if (zero || before >= m) {
+      win[nw].key = ((uint64_t)s << m) | h;
       win[nw].y = y;
+      pat[nw] = h;
       ++nw;
     }
     hist[s] = ((hist[s] << 1) | y) & mask;
     seen[s]++;
+    gh = ((gh << 1) | y) & mask;
+    gseen++;
   }
   uint64_t uniq = 0;
   for (uint32_t s = 0; s < t->n_sites; ++s) uniq += seen[s] != 0;
@@ -285,7 +311,21 @@ static int branch_metrics(const orc_trace *t, orc_result *r) {
   r->albe_min_sum = minsum;
   r->yokota_entropy = nw ? (double)(yok / (long double)nw) : 0.0;
   r->linear_branch_entropy = nw ? (double)(2 * minsum) / (double)nw : 0.0;
-  free(hist); free(seen); free(win);
+  r->pattern_entropy = NAN;
+  if (t->flags & ORC_BR_PATTERN) {
+    qsort(pat, nw, sizeof(uint64_t), cmp_u64);
+    long double e = 0.0L;
+    size_t a = 0;
+    while (a < nw) {
+      size_t b = a;
+      while (b < nw && pat[b] == pat[a]) ++b;
+      const long double c = (long double)(b - a);
+      e += c * log2l((long double)nw / c);
+      a = b;
+    }
+    r->pattern_entropy = nw ? (double)(e / (long double)nw / (long double)m) : 0.0;
+  }
+  free(hist); free(seen); free(win); free(pat);
   return 0;
 }
 

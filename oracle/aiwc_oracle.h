@@ -38,8 +38,19 @@ typedef struct orc_trace {
   const uint32_t *br_site;
   const uint8_t *br_taken;
   uint32_t history_len;       /* m, 1..32 */
-  uint32_t pad;
+  uint32_t flags;             /* ORC_BR_* branch-entropy variants        */
 } orc_trace;
+
+/* Branch-entropy variants (Related Work: Yokota's branch history entropy,
+ * De Pestel's linear entropy; Implementation: "the full history of combined
+ * branch's taken and not-taken").  The default is a per-site history whose
+ * windows start once m earlier outcomes exist; these bits select the other
+ * readings.  (The values are the interface of the trace flags.)            */
+#define ORC_BR_ZERO_HISTORY 2u    /* histories start as m not-taken outcomes;
+                                     every branch event forms a window     */
+#define ORC_BR_GLOBAL_HISTORY 4u  /* one history of the previous m outcomes
+                                     of all branches, keyed with the site  */
+#define ORC_BR_PATTERN 8u         /* also report the pattern entropy       */
 
 typedef struct orc_space {
   uint64_t total_accesses, total_reads, total_writes;
@@ -64,6 +75,7 @@ typedef struct orc_result {
   uint64_t total_branches, unique_branches, branches_90;
   uint64_t n_windows, albe_min_sum;
   double yokota_entropy, linear_branch_entropy;
+  double pattern_entropy;     /* E_m / m with ORC_BR_PATTERN, else NaN      */
   /* derived parallelism metrics (LU decomposition analysis) */
   double granularity, barriers_per_instruction, instructions_per_operand;
   uint64_t load_imbalance;

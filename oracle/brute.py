@@ -51,7 +51,7 @@ def _entropy(counter: Counter) -> mpmath.mpf:
 
 
 def characterize(opcode, wi_offsets, table, addr, mem_kind, br_site, br_taken,
-                 n_sites: int, m: int) -> Dict:
+                 n_sites: int, m: int, flags: int = 0) -> Dict:
     opcode = [int(x) for x in opcode]
     off = [int(x) for x in wi_offsets]
     cls = [int(table[i]["op_class"]) for i in range(len(table))]
@@ -109,13 +109,19 @@ def characterize(opcode, wi_offsets, table, addr, mem_kind, br_site, br_taken,
         spaces.append(d)
     r["space"] = spaces
     # branches
+    # histories as outcome lists: per site, or one list shared by every site
+    # (flags 4); started with m not-taken outcomes under flags 2, so that
+    # every execution then has a full history
     hist: Dict[int, List[int]] = {}
     win = Counter()
+    patterns = Counter()
+    start = [0] * m if flags & 2 else []
     for s, y in zip(br_site, br_taken):
         s, y = int(s), int(y)
-        h = hist.setdefault(s, [])
+        h = hist.setdefault(-1 if flags & 4 else s, list(start))
         if len(h) >= m:
             win[(s, tuple(h[-m:]), y)] += 1
+            patterns[tuple(h[-m:])] += 1
         h.append(y)
     keys = {(s, h) for (s, h, _) in win}
     nw = sum(win.values())
@@ -135,6 +141,11 @@ def characterize(opcode, wi_offsets, table, addr, mem_kind, br_site, br_taken,
     r["albe_min_sum"] = mins
     r["yokota_entropy"] = yok / nw if nw else mpmath.mpf(0)
     r["linear_branch_entropy"] = float(Fraction(2 * mins, nw)) if nw else 0.0
+    r["pattern_entropy"] = float("nan")
+    if flags & 8:
+        e = sum((c * mpmath.log(mpmath.mpf(nw) / c, 2) for c in patterns.values()),
+                mpmath.mpf(0))
+        r["pattern_entropy"] = float(e / nw / m) if nw else 0.0
     # derived parallelism metrics (LU decomposition analysis): exact
     # rationals rounded once, IEEE conventions for a zero denominator
     ratio = lambda a, b: float(Fraction(a, b)) if b else (float("inf") if a else float("nan"))

@@ -229,32 +229,52 @@ def _memory(tr, r: Dict) -> None:
 def _branches(tr, r: Dict, threads: int) -> None:
     """Per-site history of the previous m outcomes in stream order; a window
     only once m earlier outcomes of its site exist; per (site, history) the
-    outcome counts n0, n1."""
+    outcome counts n0, n1.  Variants (trace attribute branch_flags, same
+    values as the C oracle's ORC_BR_*): zero-initialised histories with a
+    window at every execution; one global history over all branches; the
+    pattern entropy E_m / m over the windows' histories."""
     site = np.asarray(tr.br_site, dtype=np.uint32)
     y = np.asarray(tr.br_taken, dtype=np.uint8).astype(np.uint64) & np.uint64(1)
     m = int(tr.history_len)
     ns = int(tr.n_sites)
     nb = int(site.size)
+    flags = int(getattr(tr, "branch_flags", 0))
+    zero, glob = bool(flags & 2), bool(flags & 4)
     seen = _bincount(site, ns, threads) if nb else np.zeros(ns, dtype=np.int64)
     r["total_branches"] = nb
     r["unique_branches"] = int(np.count_nonzero(seen))
     r["branches_90"] = _coverage90(seen, nb)
+    r["pattern_entropy"] = 0.0 if flags & 8 else float("nan")
     if nb == 0:
         r["n_windows"] = r["albe_min_sum"] = 0
         r["yokota_entropy"] = r["linear_branch_entropy"] = 0.0
         return
-    order = np.argsort(site, kind="stable")
-    s_sorted = site[order].astype(np.uint64)
-    y_sorted = y[order]
-    seg_first = np.ones(nb, dtype=bool)
-    seg_first[1:] = s_sorted[1:] != s_sorted[:-1]
-    seg_start = np.maximum.accumulate(np.where(seg_first, np.arange(nb), 0))
-    pos = np.arange(nb) - seg_start                           # rank within the site
-    valid = pos >= m
+    if glob:
+        # one register over the stream: no grouping by site before the history
+        s_sorted = site.astype(np.uint64)
+        y_sorted = y
+        pos = np.arange(nb)
+    else:
+        order = np.argsort(site, kind="stable")
+        s_sorted = site[order].astype(np.uint64)
+        y_sorted = y[order]
+        seg_first = np.ones(nb, dtype=bool)
+        seg_first[1:] = s_sorted[1:] != s_sorted[:-1]
+        seg_start = np.maximum.accumulate(np.where(seg_first, np.arange(nb), 0))
+        pos = np.arange(nb) - seg_start                       # rank within the site
+    valid = np.ones(nb, dtype=bool) if zero else pos >= m
     hist = np.zeros(nb, dtype=np.uint64)
     for j in range(1, m + 1):                                 # bit j-1 = outcome j back
-        hist[j:] |= y_sorted[:-j] << np.uint64(j - 1)
+        bit = y_sorted[:-j] << np.uint64(j - 1)
+        if zero:
+            bit = np.where(pos[j:] >= j, bit, np.uint64(0))   # before the start: not taken
+        hist[j:] |= bit
     key = (s_sorted[valid] << np.uint64(m)) | hist[valid]
+    if flags & 8 and key.size:
+        _, pc = np.unique(hist[valid], return_counts=True)
+        nwv = int(valid.sum())
+        r["pattern_entropy"] = math.fsum(float(c) * math.log2(nwv / float(c))
+                                         for c in pc.tolist()) / nwv / m
     kk = (key << np.uint64(1)) | y_sorted[valid]
     uk, ck = _runs(kk)
     kid = uk >> np.uint64(1)

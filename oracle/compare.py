@@ -50,6 +50,10 @@ def compare(gpu: Dict, orc: Dict) -> List[str]:
         bad.append(f"simd_sd: gpu {gpu['simd_sd']!r} oracle {orc['simd_sd']!r}")
     if not _rel_ok(gpu["yokota_entropy"], orc["yokota_entropy"], ENTROPY_REL):
         bad.append(f"yokota: gpu {gpu['yokota_entropy']!r} oracle {orc['yokota_entropy']!r}")
+    gp, op = gpu.get("pattern_entropy", math.nan), orc.get("pattern_entropy", math.nan)
+    if not ((math.isnan(gp) and math.isnan(op)) or
+            (not math.isnan(gp) and not math.isnan(op) and _rel_ok(gp, op, ENTROPY_REL))):
+        bad.append(f"pattern_entropy: gpu {gp!r} oracle {op!r}")
     for s in (0, 1):
         g, o = gpu["space"][s], orc["space"][s]
         for f in INT_SPACE:

@@ -55,3 +55,14 @@ def test_long_histories_and_many_sites():
     rng = np.random.default_rng(77)
     s = rng.integers(0, 3000, size=30000).astype(np.uint32)
     agree(branch_trace(s, (rng.random(30000) < 0.3).astype(np.uint8), 3000, 32))
+
+
+@pytest.mark.parametrize("flags", [2, 4, 6, 8, 10, 12, 14])
+def test_branch_variants(flags):
+    # zero-initialised / global histories and the pattern entropy
+    rng = np.random.default_rng(900 + flags)
+    for m in (1, 7, 16):
+        s = rng.integers(0, 40, size=5000).astype(np.uint32)
+        t = branch_trace(s, (rng.random(5000) < 0.4).astype(np.uint8), 40, m)
+        t.branch_flags = flags
+        agree(t)
