@@ -77,8 +77,23 @@ typedef struct aiwc_opcode_info {
 
 /* trace flags */
 enum {
-  AIWC_VALIDATE_ON_DEVICE = 1u  /* aiwc_trace_create runs a validation kernel
+  AIWC_VALIDATE_ON_DEVICE = 1u, /* aiwc_trace_create runs a validation kernel
                                    over every array and synchronizes        */
+  /* Branch-entropy variants.  The paper fixes the history length (16) but
+   * not the history's scope or start-up, and it cites two entropies
+   * (Related Work: Yokota's branch history entropy, De Pestel's linear
+   * entropy).  Default: each site keeps its own history of its previous m
+   * outcomes, and an execution forms a window once m earlier outcomes of its
+   * site exist.                                                            */
+  AIWC_BRANCH_ZERO_HISTORY = 2u,    /* histories start as m not-taken outcomes;
+                                       every execution forms a window       */
+  AIWC_BRANCH_GLOBAL_HISTORY = 4u,  /* one history of the previous m outcomes
+                                       of all branches in stream order (the
+                                       "combined" history of the
+                                       Implementation section), keyed with
+                                       the site; needs history_len <= 31    */
+  AIWC_BRANCH_PATTERN_ENTROPY = 8u  /* also report pattern_entropy; needs
+                                       history_len <= 20                    */
 };
 
 /* One kernel launch's event trace (structure of arrays).
@@ -188,6 +203,13 @@ typedef struct aiwc_metrics_host {
   uint64_t albe_min_sum;            /* sum over (site, history) of min(n0,n1) */
   double yokota_entropy;            /* H(outcome | site, history), in [0,1]  */
   double linear_branch_entropy;     /* 2 * albe_min_sum / n_windows          */
+  double pattern_entropy;           /* with AIWC_BRANCH_PATTERN_ENTROPY:
+                                       Yokota's branch history entropy in its
+                                       pattern form, E_m / m in [0,1], where
+                                       E_m = sum_p c_p log2(N_w / c_p) over
+                                       the m-bit histories p of the windows
+                                       (any site); 0 when N_w = 0.  NaN when
+                                       not requested.                        */
   /* derived parallelism metrics (LU decomposition analysis of the paper:
      the inverted values plotted on the radar diagram, and load imbalance);
      each is one IEEE operation on the exact integers above               */

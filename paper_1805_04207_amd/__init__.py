@@ -3,5 +3,6 @@
 include/aiwc.h, with a thin ctypes binding (aiwc.py)."""
 from .aiwc import (AiwcError, Context, Metrics, Trace, load_library,  # noqa: F401
                    SIZING_BOUND, SIZING_HEURISTIC, SIZING_LEARNED,
-                   AUTOTUNE_OFF, AUTOTUNE_CACHED, AUTOTUNE_SEARCH)
+                   AUTOTUNE_OFF, AUTOTUNE_CACHED, AUTOTUNE_SEARCH,
+                   BRANCH_ZERO_HISTORY, BRANCH_GLOBAL_HISTORY, BRANCH_PATTERN_ENTROPY)
 from .host import device_trace, host_to_device  # noqa: F401

@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(HERE, "libaiwc.so")
 AIWC_OK, AIWC_ERR_INVALID_ARG, AIWC_ERR_INCONSISTENT = 0, 1, 2
 AIWC_ERR_OUT_OF_MEMORY, AIWC_ERR_HIP, AIWC_ERR_UNSUPPORTED = 3, 4, 5
 AIWC_VALIDATE_ON_DEVICE = 1
+BRANCH_ZERO_HISTORY, BRANCH_GLOBAL_HISTORY, BRANCH_PATTERN_ENTROPY = 2, 4, 8
 SIZING_BOUND, SIZING_HEURISTIC, SIZING_LEARNED = 0, 1, 2
 AUTOTUNE_OFF, AUTOTUNE_CACHED, AUTOTUNE_SEARCH = 0, 1, 2
 N_FEATURES, N_TARGETS = 40, 11
@@ -69,7 +70,8 @@ class MetricsHost(ctypes.Structure):
                 ("total_branches", ctypes.c_uint64), ("unique_branches", ctypes.c_uint64),
                 ("branches_90", ctypes.c_uint64), ("n_windows", ctypes.c_uint64),
                 ("albe_min_sum", ctypes.c_uint64), ("yokota_entropy", ctypes.c_double),
-                ("linear_branch_entropy", ctypes.c_double), ("granularity", ctypes.c_double),
+                ("linear_branch_entropy", ctypes.c_double),
+                ("pattern_entropy", ctypes.c_double), ("granularity", ctypes.c_double),
                 ("barriers_per_instruction", ctypes.c_double),
                 ("instructions_per_operand", ctypes.c_double),
                 ("load_imbalance", ctypes.c_uint64), ("overflow_redos", ctypes.c_uint32),
@@ -204,10 +206,11 @@ class Context:
     # ---------------------------------------------------------------- traces
     def trace(self, opcode, wi_offsets, addr, mem_kind, br_site, br_taken, table,
               n_sites: int, history_len: int = 16, wg_size: int = 0,
-              validate: bool = False) -> "Trace":
-        """Describe a trace held in torch CUDA tensors (device memory)."""
+              validate: bool = False, branch_flags: int = 0) -> "Trace":
+        """Describe a trace held in torch CUDA tensors (device memory).
+        branch_flags: BRANCH_* variant bits."""
         return Trace(self, opcode, wi_offsets, addr, mem_kind, br_site, br_taken, table,
-                     n_sites, history_len, wg_size, validate)
+                     n_sites, history_len, wg_size, validate, branch_flags)
 
     def characterize(self, trace: "Trace", stream=None) -> "Metrics":
         m = ctypes.c_void_p()
@@ -321,7 +324,7 @@ class Trace:
     """aiwc_trace: borrows the tensors (kept referenced here)."""
 
     def __init__(self, ctx: Context, opcode, wi_offsets, addr, mem_kind, br_site, br_taken,
-                 table, n_sites, history_len, wg_size, validate):
+                 table, n_sites, history_len, wg_size, validate, branch_flags=0):
         import numpy as np
         self.ctx = ctx
         self._keep = (opcode, wi_offsets, addr, mem_kind, br_site, br_taken)
@@ -332,7 +335,7 @@ class Trace:
         n_wi = int(wi_offsets.numel()) - 1
         d = TraceDesc()
         d.struct_size = ctypes.sizeof(TraceDesc)
-        d.flags = AIWC_VALIDATE_ON_DEVICE if validate else 0
+        d.flags = (AIWC_VALIDATE_ON_DEVICE if validate else 0) | int(branch_flags)
         d.n_events = _n(opcode)
         d.opcode = _ptr(opcode)
         d.n_workitems = n_wi

@@ -93,14 +93,18 @@ void plan_trace(const aiwc_trace *t, u32 pbits, TracePlan &p, const Tune *tune) 
   p.o_sp_m = take(8ull * 2 * p.sp_cap);
   p.o_seg_start = take(4ull * std::max<u32>(1, d.n_sites));
   p.o_seg_end = take(4ull * std::max<u32>(1, d.n_sites));
+  if (d.flags & AIWC_BRANCH_PATTERN_ENTROPY) p.o_pat_hist = take(4ull << d.history_len);
   p.zero_bytes = o;
   p.o_itb_large = take(8ull * p.large_cap);
   p.o_ipt_large = take(8ull * p.large_cap);
   p.o_part_hist = take(4ull * p.n_hist_blocks * P);
   p.o_part_off = take(4ull * (P + 1));
   p.o_part_rec = take(8ull * std::max<u64>(1, d.n_mem));
-  p.o_br_a = take(4ull * std::max<u64>(1, d.n_branch));
-  p.o_br_b = take(4ull * std::max<u64>(1, d.n_branch));
+  // radix records: site << 1 | outcome (u32), or with the global history
+  // site << 33 | history << 1 | outcome (u64)
+  const u64 rec = (d.flags & AIWC_BRANCH_GLOBAL_HISTORY) ? 8 : 4;
+  p.o_br_a = take(rec * std::max<u64>(1, d.n_branch));
+  p.o_br_b = take(rec * std::max<u64>(1, d.n_branch));
   p.o_br_cnt = take(4ull * 256 * std::max<u64>(1, p.br_tiles));
   p.o_scan_tmp = take(4ull * aiwc_kernels::scan_tmp_elems(256 * std::max<u64>(1, p.br_tiles)));
   p.scratch_bytes = o;
@@ -166,6 +170,9 @@ void fill_args(const aiwc_trace *t, const TracePlan &p, char *scratch, char *res
   a.br_a = (u32 *)(scratch + p.o_br_a);
   a.br_b = (u32 *)(scratch + p.o_br_b);
   a.br_cnt = (u32 *)(scratch + p.o_br_cnt);
+  a.pat_hist = (d.flags & AIWC_BRANCH_PATTERN_ENTROPY) ? (u32 *)(scratch + p.o_pat_hist) : nullptr;
+  a.br_flags = d.flags & (AIWC_BRANCH_ZERO_HISTORY | AIWC_BRANCH_GLOBAL_HISTORY |
+                          AIWC_BRANCH_PATTERN_ENTROPY);
   a.scan_tmp = (u32 *)(scratch + p.o_scan_tmp);
   a.out = (aiwc_metrics_host *)(result + p.r_metrics);
   a.out_class_hist = (u64 *)(result + p.r_class);
@@ -192,6 +199,11 @@ void add_dims(const aiwc_trace *t, const TracePlan &p, const TraceArgs &a, Batch
   }
   if (D.n_branch) {
     d.any_branch = true;
+    if (D.flags & AIWC_BRANCH_GLOBAL_HISTORY) d.any_global = true; else d.any_local = true;
+    if (D.flags & AIWC_BRANCH_PATTERN_ENTROPY) {
+      d.any_pattern = true;
+      d.max_pattern_bins = std::max<u32>(d.max_pattern_bins, 1u << D.history_len);
+    }
     d.max_tiles = std::max<u64>(d.max_tiles, p.br_tiles);
     d.max_passes = std::max<u32>(d.max_passes, p.br_passes);
     d.max_br_blocks = std::max<u64>(d.max_br_blocks, p.br_blocks);
@@ -347,6 +359,19 @@ extern "C" aiwc_status aiwc_trace_create(aiwc_ctx *ctx, const aiwc_trace_desc *d
     ctx_error(ctx, "history_len %u outside 1..32", d->history_len);
     return AIWC_ERR_INVALID_ARG;
   }
+  if (d->flags & ~(u32)(AIWC_VALIDATE_ON_DEVICE | AIWC_BRANCH_ZERO_HISTORY |
+                        AIWC_BRANCH_GLOBAL_HISTORY | AIWC_BRANCH_PATTERN_ENTROPY)) {
+    ctx_error(ctx, "unknown trace flag bits 0x%x", d->flags);
+    return AIWC_ERR_INVALID_ARG;
+  }
+  if ((d->flags & AIWC_BRANCH_GLOBAL_HISTORY) && d->history_len > 31) {
+    ctx_error(ctx, "the global branch history supports history_len <= 31");
+    return AIWC_ERR_UNSUPPORTED;
+  }
+  if ((d->flags & AIWC_BRANCH_PATTERN_ENTROPY) && d->history_len > 20) {
+    ctx_error(ctx, "the pattern entropy supports history_len <= 20");
+    return AIWC_ERR_UNSUPPORTED;
+  }
   if (d->max_lsb_skip != 10) {
     ctx_error(ctx, "max_lsb_skip must be 10 (got %u)", d->max_lsb_skip);
     return AIWC_ERR_INVALID_ARG;
@@ -501,9 +526,11 @@ extern "C" aiwc_status aiwc_characterize_merged(aiwc_ctx *ctx, const aiwc_trace 
   u32 n_sites = 0;
   for (size_t i = 0; i < n; ++i) {
     const aiwc_trace *t = traces[i];
-    if (t->d.history_len != t0->d.history_len || t->host_info != t0->host_info) {
-      ctx_error(ctx, "aiwc_characterize_merged: trace %zu has another opcode table or history "
-                "length than trace 0", i);
+    const u32 variant = ~(u32)AIWC_VALIDATE_ON_DEVICE;
+    if (t->d.history_len != t0->d.history_len || t->host_info != t0->host_info ||
+        (t->d.flags & variant) != (t0->d.flags & variant)) {
+      ctx_error(ctx, "aiwc_characterize_merged: trace %zu has another opcode table, history "
+                "length or branch variant than trace 0", i);
       return AIWC_ERR_INVALID_ARG;
     }
     n_ev += t->d.n_events;
@@ -557,7 +584,7 @@ extern "C" aiwc_status aiwc_characterize_merged(aiwc_ctx *ctx, const aiwc_trace 
   aiwc_trace mt;
   mt.ctx = ctx;
   mt.d = t0->d;
-  mt.d.flags = 0;
+  mt.d.flags = t0->d.flags & ~(u32)AIWC_VALIDATE_ON_DEVICE;
   mt.d.n_events = n_ev;
   mt.d.opcode = (const uint16_t *)stage;
   mt.d.n_workitems = n_wi;

@@ -33,7 +33,8 @@ struct DevAccum {
   u64 br_windows, br_minsum, yok_lo, yok_hi;
   u64 br_queue;
   u64 bad_mem;
-  u64 pad[4];
+  u64 pat_lo, pat_hi;        // pattern entropy sum, 2^-64 units
+  u64 pad[2];
 };
 
 // Everything a kernel needs to know about one trace and its scratch.
@@ -48,7 +49,8 @@ struct TraceArgs {
   const u32 *op_info;        // per id: kind | width << 8 | class << 16
   u64 n_events, n_wi, n_mem, n_branch;
   u32 n_ids, n_classes, n_sites, m;
-  u32 wg_size, pad1;
+  u32 wg_size;
+  u32 br_flags;              // AIWC_BRANCH_* variant bits of the trace
   // planning
   u32 pbits;                 // memory partitions P = 2^pbits
   u32 n_hist_blocks;         // blocks of the partition histogram / scatter
@@ -73,6 +75,7 @@ struct TraceArgs {
   u64 *part_rec;             // [n_mem]
   u32 *br_a, *br_b;          // [n_branch] radix ping-pong
   u32 *br_cnt;               // [256 * br_tiles]
+  u32 *pat_hist;             // [2^m] windows per history pattern (pattern entropy)
   u32 *scan_tmp;             // block sums for the generic scan
   // result (device)
   aiwc_metrics_host *out;
@@ -199,6 +202,9 @@ struct BatchDims {
   u32 max_ids = 0, max_passes = 0;
   u64 ops_lds = 0;                    // dynamic LDS of the ops kernel (max over traces)
   bool any_mem = false, any_branch = false;
+  bool any_local = false, any_global = false;   // branch history variants present
+  bool any_pattern = false;                     // some trace wants the pattern entropy
+  u32 max_pattern_bins = 0;
   bool vec = true;                    // every address / kind array 16 / 4 B aligned
   bool ops_vec = true;                // every opcode array 16 B aligned
 };

@@ -22,6 +22,16 @@
 //     (exact 128-bit fixed point sums, so the result is order independent).
 //     A block whose distinct keys overflow the table is split by key hash
 //     bits and redone.
+//
+// Variants (trace flags): zero-initialised histories mask the history bits
+// that precede a site's first execution and keep every execution; the
+// global history is cut from the stream-order outcomes in the pack kernel
+// (k_br_pack_global) and travels with the site through the sort in 64-bit
+// records (site << 33 | history << 1 | outcome, history bit 31 = "no full
+// history yet"); the pattern entropy adds every key's window count to a
+// 2^m-bin histogram of its history, reduced by k_br_pattern.
+#include <type_traits>
+
 #include "common.h"
 
 namespace {
@@ -35,10 +45,21 @@ constexpr u32 WT_C = 8192;                    // LDS table slots
 constexpr u32 WT_CAP = 4096;
 constexpr u64 EMPTY = ~0ull;
 
+__device__ __forceinline__ bool global_history(const TraceArgs &A) {
+  return (A.br_flags & AIWC_BRANCH_GLOBAL_HISTORY) != 0;
+}
+
+// site of a radix record: u32 records are site << 1 | outcome, u64 records
+// site << 33 | history << 1 | outcome
+template <typename R> __device__ __forceinline__ u32 rec_site(R v) {
+  return (u32)(v >> (sizeof(R) == 8 ? 33 : 1));
+}
+
 // ------------------------------------------------------------------ pack
 template <bool BATCH>
 __global__ void k_br_pack(TraceArgs A0, const TraceArgs *batch) {
   const TraceArgs A = trace_args<BATCH>(A0, batch);
+  if (global_history(A)) return;
   u32 *out = A.br_a;
   u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x;
   const u64 stride = (u64)gridDim.x * blockDim.x;
@@ -53,46 +74,89 @@ __global__ void k_br_pack(TraceArgs A0, const TraceArgs *batch) {
   if (lane_id() == 0 && b) atomicAdd(&A.acc->bad_mem, b);
 }
 
-// -------------------------------------------------------------- radix sort
+// Global history: one register over all branches in stream order.  A wave
+// takes 64 consecutive executions; each lane's history is the m outcomes
+// before it, cut from this chunk's and the previous chunk's outcome ballots
+// (bits before the stream start are not-taken).
 template <bool BATCH>
+__global__ void k_br_pack_global(TraceArgs A0, const TraceArgs *batch) {
+  const TraceArgs A = trace_args<BATCH>(A0, batch);
+  if (!global_history(A)) return;
+  u64 *out = reinterpret_cast<u64 *>(A.br_a);
+  const int lane = lane_id();
+  const u32 m = A.m;                                   // 1..31
+  const u64 hmask = (1ull << m) - 1ull;
+  const bool zero = (A.br_flags & AIWC_BRANCH_ZERO_HISTORY) != 0;
+  const u64 wpb = blockDim.x / AIWC_WAVE;
+  const u64 nwaves = (u64)gridDim.x * wpb;
+  u32 bad = 0;
+  for (u64 cb = ((u64)blockIdx.x * wpb + threadIdx.x / AIWC_WAVE) * AIWC_WAVE; cb < A.n_branch;
+       cb += nwaves * AIWC_WAVE) {
+    const u64 i = cb + lane;
+    const bool valid = i < A.n_branch;
+    const u32 s = valid ? A.br_site[i] : 0u;
+    const u32 y = valid ? (u32)A.br_taken[i] : 0u;
+    const u32 yp = (cb >= AIWC_WAVE) ? (u32)A.br_taken[i - AIWC_WAVE] : 0u;
+    const u64 B = __ballot(valid && (y & 1u));
+    const u64 Bp = __ballot((cb >= AIWC_WAVE) && (yp & 1u));
+    const u32 sh = 64u + (u32)lane - m;                // in [33, 126]
+    u64 E = (sh >= 64) ? (B >> (sh - 64)) : ((Bp >> sh) | (B << (64 - sh)));
+    E &= hmask;
+    if (!valid) continue;
+    if (s >= A.n_sites || y > 1u) { bad += 1; out[i] = 0; continue; }
+    const u32 hf = (u32)E | ((!zero && i < m) ? 0x80000000u : 0u);
+    out[i] = ((u64)s << 33) | ((u64)hf << 1) | y;
+  }
+  u64 b = wave_sum_u64(bad);
+  if (lane_id() == 0 && b) atomicAdd(&A.acc->bad_mem, b);
+}
+
+// -------------------------------------------------------------- radix sort
+// R = u32 for per-site histories, u64 for the global history; a launch of
+// either type skips the traces of the other (batches may mix them).
+template <typename R> __device__ __forceinline__ bool rec_matches(const TraceArgs &A) {
+  return (sizeof(R) == 8) == global_history(A);
+}
+
+template <bool BATCH, typename R>
 __global__ void __launch_bounds__(BR_BLOCK) k_br_upsweep(TraceArgs A0, const TraceArgs *batch,
                                                         u32 pass) {
   __shared__ u32 h[256];
   const TraceArgs A = trace_args<BATCH>(A0, batch);
-  if (pass >= A.br_passes || blockIdx.x >= A.br_tiles) return;
-  const u32 *in = (pass & 1) ? A.br_b : A.br_a;
+  if (pass >= A.br_passes || blockIdx.x >= A.br_tiles || !rec_matches<R>(A)) return;
+  const R *in = reinterpret_cast<const R *>((pass & 1) ? A.br_b : A.br_a);
   const u64 n = A.n_branch, n_tiles = A.br_tiles;
-  const u32 shift = 1u + 8u * pass;
+  const u32 shift = (sizeof(R) == 8 ? 33u : 1u) + 8u * pass;
   u32 *cnt = A.br_cnt;
   h[threadIdx.x] = 0;
   const u64 t = blockIdx.x;
   const u64 base = t * BR_TILE;
-  u32 vals[BR_ROUNDS];
+  R vals[BR_ROUNDS];
 #pragma unroll
   for (int r = 0; r < BR_ROUNDS; ++r) {
     const u64 i = base + (u64)r * BR_BLOCK + threadIdx.x;
-    vals[r] = i < n ? in[i] : ~0u;
+    vals[r] = i < n ? in[i] : ~(R)0;
   }
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < BR_ROUNDS; ++r)
-    if (vals[r] != ~0u) atomicAdd(&h[(vals[r] >> shift) & 255u], 1u);
+    if (vals[r] != ~(R)0) atomicAdd(&h[(u32)(vals[r] >> shift) & 255u], 1u);
   __syncthreads();
   cnt[(u64)threadIdx.x * n_tiles + t] = h[threadIdx.x];
 }
 
-template <bool BATCH>
+template <bool BATCH, typename R>
 __global__ void __launch_bounds__(BR_BLOCK) k_br_downsweep(TraceArgs A0, const TraceArgs *batch,
                                                           u32 pass) {
   __shared__ u32 gofs[256];
   __shared__ u32 running[256];
   __shared__ u32 wcnt[BR_BLOCK / AIWC_WAVE][256];
   const TraceArgs A = trace_args<BATCH>(A0, batch);
-  if (pass >= A.br_passes || blockIdx.x >= A.br_tiles) return;
-  const u32 *in = (pass & 1) ? A.br_b : A.br_a;
-  u32 *out = (pass & 1) ? A.br_a : A.br_b;
+  if (pass >= A.br_passes || blockIdx.x >= A.br_tiles || !rec_matches<R>(A)) return;
+  const R *in = reinterpret_cast<const R *>((pass & 1) ? A.br_b : A.br_a);
+  R *out = reinterpret_cast<R *>((pass & 1) ? A.br_a : A.br_b);
   const u64 n = A.n_branch, n_tiles = A.br_tiles;
-  const u32 shift = 1u + 8u * pass;
+  const u32 shift = (sizeof(R) == 8 ? 33u : 1u) + 8u * pass;
   const u32 *ofs = A.br_cnt;
   const int tid = threadIdx.x, lane = lane_id(), wave = tid / AIWC_WAVE;
   const u64 t = blockIdx.x;
@@ -100,11 +164,11 @@ __global__ void __launch_bounds__(BR_BLOCK) k_br_downsweep(TraceArgs A0, const T
   running[tid] = 0;
   const u64 base = t * BR_TILE;
   const u64 lt = (1ull << lane) - 1ull;
-  u32 vals[BR_ROUNDS];
+  R vals[BR_ROUNDS];
 #pragma unroll
   for (int r = 0; r < BR_ROUNDS; ++r) {
     const u64 i = base + (u64)r * BR_BLOCK + tid;
-    vals[r] = i < n ? in[i] : 0u;
+    vals[r] = i < n ? in[i] : (R)0;
   }
 #pragma unroll
   for (int r = 0; r < BR_ROUNDS; ++r) {
@@ -113,8 +177,8 @@ __global__ void __launch_bounds__(BR_BLOCK) k_br_downsweep(TraceArgs A0, const T
     __syncthreads();
     const u64 i = base + (u64)r * BR_BLOCK + tid;
     const bool valid = i < n;
-    const u32 v = vals[r];
-    const u32 d = (v >> shift) & 255u;
+    const R v = vals[r];
+    const u32 d = (u32)(v >> shift) & 255u;
     u64 peers = __ballot(valid);
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
@@ -235,17 +299,18 @@ __global__ void __launch_bounds__(SCAN_BLOCK) k_scan_apply(TraceArgs A0, const T
 }
 
 // ------------------------------------------------------------- segments
-template <bool BATCH>
+template <bool BATCH, typename R>
 __global__ void k_br_segments(TraceArgs A0, const TraceArgs *batch) {
   const TraceArgs A = trace_args<BATCH>(A0, batch);
-  const u32 *sorted = A.br_sorted;
+  if (!rec_matches<R>(A)) return;
+  const R *sorted = reinterpret_cast<const R *>(A.br_sorted);
   u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x;
   const u64 stride = (u64)gridDim.x * blockDim.x;
   const u64 n = A.n_branch;
   for (; i < n; i += stride) {
-    const u32 s = sorted[i] >> 1;
-    if (i == 0 || (sorted[i - 1] >> 1) != s) A.seg_start[s] = (u32)i;
-    if (i + 1 == n || (sorted[i + 1] >> 1) != s) A.seg_end[s] = (u32)(i + 1);
+    const u32 s = rec_site(sorted[i]);
+    if (i == 0 || rec_site(sorted[i - 1]) != s) A.seg_start[s] = (u32)i;
+    if (i + 1 == n || rec_site(sorted[i + 1]) != s) A.seg_end[s] = (u32)(i + 1);
   }
 }
 
@@ -269,12 +334,13 @@ __device__ __forceinline__ void yterm(u32 a, u32 b, u64 &lo, u64 &hi) {
   to_fx64(d, lo, hi);
 }
 
-__device__ __forceinline__ u64 range_begin(const TraceArgs &A, const u32 *sorted, u64 b) {
+template <typename R>
+__device__ __forceinline__ u64 range_begin(const TraceArgs &A, const R *sorted, u64 b) {
   const u64 x = b * WIN_T;
   if (x == 0) return 0;
   if (x >= A.n_branch) return A.n_branch;
-  const u32 s = sorted[x] >> 1;
-  if ((sorted[x - 1] >> 1) != s) return x;
+  const u32 s = rec_site(sorted[x]);
+  if (rec_site(sorted[x - 1]) != s) return x;
   return A.seg_end[s];
 }
 
@@ -302,12 +368,15 @@ __device__ __forceinline__ u32 win_insert(WinShared &S, u64 key, u32 a, u32 b, b
   }
 }
 
-template <bool BATCH>
+template <bool BATCH, bool GLOBAL>
 __global__ void __launch_bounds__(WIN_BLOCK) k_br_windows(TraceArgs A0, const TraceArgs *batch) {
+  using R = typename std::conditional<GLOBAL, u64, u32>::type;
   __shared__ WinShared S;
   const TraceArgs A = trace_args<BATCH>(A0, batch);
-  if (A.n_branch == 0) return;
-  const u32 *sorted = A.br_sorted;
+  if (A.n_branch == 0 || global_history(A) != GLOBAL) return;
+  const R *sorted = reinterpret_cast<const R *>(A.br_sorted);
+  const bool zero = (A.br_flags & AIWC_BRANCH_ZERO_HISTORY) != 0;
+  u32 *const pat = A.pat_hist;
   const int tid = threadIdx.x, lane = lane_id(), wave = tid / AIWC_WAVE;
   const u32 m = A.m;
   const u64 hmask = (m >= 64) ? ~0ull : ((1ull << m) - 1ull);
@@ -347,12 +416,14 @@ __global__ void __launch_bounds__(WIN_BLOCK) k_br_windows(TraceArgs A0, const Tr
       bool stop = false;
       for (u64 cb0 = r0 + (u64)wave * AIWC_WAVE; cb0 < r1; cb0 += 4ull * WIN_BLOCK) {
         // four chunks' loads in flight before any is used
-        u32 pv[4], pp[4];
+        R pv[4];
+        u32 pp[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const u64 cb = cb0 + (u64)q * WIN_BLOCK, i = cb + lane;
-          pv[q] = (i < r1) ? sorted[i] : 0u;
-          pp[q] = (cb >= AIWC_WAVE && cb < r1) ? sorted[i - AIWC_WAVE] : 0u;
+          pv[q] = (i < r1) ? sorted[i] : (R)0;
+          if constexpr (!GLOBAL)
+            pp[q] = (cb >= AIWC_WAVE && cb < r1) ? sorted[i - AIWC_WAVE] : 0u;
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -360,17 +431,34 @@ __global__ void __launch_bounds__(WIN_BLOCK) k_br_windows(TraceArgs A0, const Tr
           if (cb >= r1) break;
           const u64 i = cb + lane;
           const bool valid = i < r1;
-          const u32 v = pv[q], vp = pp[q];
-          const u64 B = __ballot(valid && (v & 1u));
-          const u64 Bp = __ballot((cb >= AIWC_WAVE) && (vp & 1u));
-          const u32 s = v >> 1;
-          const u32 sh = 64u + (u32)lane - m;           // in [32, 127]
-          u64 E;
-          if (sh >= 64) E = B >> (sh - 64);
-          else E = (Bp >> sh) | (B << (64 - sh));
-          E &= hmask;
-          const u64 key = ((u64)s << m) | E;
-          const bool use = valid && i - A.seg_start[s] >= m &&
+          const R v = pv[q];
+          u64 key;
+          bool windowed;
+          if constexpr (GLOBAL) {
+            // the history came with the record; bit 31 marks "no full
+            // history yet" (the first m executions of the stream)
+            const u32 hf = (u32)(v >> 1);
+            key = ((u64)rec_site(v) << m) | (hf & hmask);
+            windowed = valid && !(hf >> 31);
+          } else {
+            const u32 vp = pp[q];
+            const u64 B = __ballot(valid && (v & 1u));
+            const u64 Bp = __ballot((cb >= AIWC_WAVE) && (vp & 1u));
+            const u32 s = v >> 1;
+            const u32 sh = 64u + (u32)lane - m;         // in [32, 127]
+            u64 E;
+            if (sh >= 64) E = B >> (sh - 64);
+            else E = (Bp >> sh) | (B << (64 - sh));
+            E &= hmask;
+            // d earlier executions of this site: bit j of E is the outcome
+            // m - j executions back, so bits j < m - d precede the site's
+            // first execution (not-taken when histories start at zero)
+            const u64 d = i - A.seg_start[s];
+            if (zero && d < m) E &= ~((1ull << (m - d)) - 1ull);
+            key = ((u64)s << m) | E;
+            windowed = valid && (zero || d >= m);
+          }
+          const bool use = windowed &&
                            (M == 1 || (((u32)((key * 0x9E3779B97F4A7C15ull) >> 40)) & (M - 1u)) == C);
           // runs of one key among neighbouring lanes (biased sites repeat
           // their history) are added once, by their first lane
@@ -427,6 +515,7 @@ __global__ void __launch_bounds__(WIN_BLOCK) k_br_windows(TraceArgs A0, const Tr
         if (a < 16 && c < 16) { tl = S.tlo[a * 16 + c]; th = S.thi[a * 16 + c]; }
         else yterm(a, c, tl, th);
         u64 nl = lo + tl; hi += th + (nl < lo); lo = nl;
+        if (pat) atomicAdd(&pat[S.key[slot] & hmask], a + c);
         S.key[slot] = EMPTY; S.n0[slot] = 0; S.n1[slot] = 0;
       }
       __syncthreads();
@@ -451,6 +540,30 @@ __global__ void __launch_bounds__(WIN_BLOCK) k_br_windows(TraceArgs A0, const Tr
   }
 }
 
+// Pattern entropy: sum over the 2^m history patterns of c log2(N_w / c),
+// each term converted to 2^-64 fixed point, so the sum is exact and order
+// independent; N_w is the window count k_br_windows accumulated.
+template <bool BATCH>
+__global__ void __launch_bounds__(256) k_br_pattern(TraceArgs A0, const TraceArgs *batch) {
+  const TraceArgs A = trace_args<BATCH>(A0, batch);
+  if (!A.pat_hist || A.n_branch == 0) return;
+  const u64 nbins = 1ull << A.m;
+  const double N = (double)A.acc->br_windows;
+  u64 lo = 0, hi = 0;
+  for (u64 b = (u64)blockIdx.x * blockDim.x + threadIdx.x; b < nbins;
+       b += (u64)gridDim.x * blockDim.x) {
+    const u32 c = A.pat_hist[b];
+    if (c == 0) continue;
+    u64 tl, th;
+    to_fx64((double)c * log2(N / (double)c), tl, th);
+    const u64 nl = lo + tl;
+    hi += th + (nl < lo);
+    lo = nl;
+  }
+  wave_sum_u128(lo, hi);
+  if (lane_id() == 0) atomic_add_u128(&A.acc->pat_lo, &A.acc->pat_hi, lo, hi);
+}
+
 }  // namespace
 
 namespace aiwc_kernels {
@@ -461,6 +574,8 @@ u64 br_blocks_for(u64 n) { return (n + WIN_T - 1) / WIN_T; }
 
 u64 scan_blocks_for(u64 n) { return (n + SCAN_TILE - 1) / SCAN_TILE; }
 
+// Launches of the per-site (u32 records) and global-history (u64 records)
+// variants; each kernel skips the traces of the other variant.
 template <bool B>
 static void branch_launches(const TraceArgs &a, const BatchDims &d, hipStream_t s,
                             StageMarks *pm) {
@@ -468,22 +583,35 @@ static void branch_launches(const TraceArgs &a, const BatchDims &d, hipStream_t 
   u64 gx = (d.max_tiles * BR_TILE + 255) / 256;
   if (gx > 8192) gx = 8192;
   if (gx == 0) gx = 1;
-  hipLaunchKernelGGL(k_br_pack<B>, dim3((unsigned)gx, d.n), dim3(256), 0, s, a, b);
+  const dim3 gp((unsigned)gx, d.n);
+  if (d.any_local) hipLaunchKernelGGL(k_br_pack<B>, gp, dim3(256), 0, s, a, b);
+  if (d.any_global) hipLaunchKernelGGL(k_br_pack_global<B>, gp, dim3(256), 0, s, a, b);
   AIWC_MARK(pm, "k_br_pack", s);
   const dim3 gt((unsigned)d.max_tiles, d.n), gs((unsigned)d.max_scan_blocks, d.n), g1(1, d.n);
   for (u32 p = 0; p < d.max_passes; ++p) {
-    hipLaunchKernelGGL(k_br_upsweep<B>, gt, dim3(BR_BLOCK), 0, s, a, b, p);
+    if (d.any_local) hipLaunchKernelGGL((k_br_upsweep<B, u32>), gt, dim3(BR_BLOCK), 0, s, a, b, p);
+    if (d.any_global) hipLaunchKernelGGL((k_br_upsweep<B, u64>), gt, dim3(BR_BLOCK), 0, s, a, b, p);
     hipLaunchKernelGGL(k_scan_reduce<B>, gs, dim3(SCAN_BLOCK), 0, s, a, b, p);
     hipLaunchKernelGGL(k_scan_sums<B>, g1, dim3(SCAN_BLOCK), 0, s, a, b, p);
     hipLaunchKernelGGL(k_scan_apply<B>, gs, dim3(SCAN_BLOCK), 0, s, a, b, p);
-    hipLaunchKernelGGL(k_br_downsweep<B>, gt, dim3(BR_BLOCK), 0, s, a, b, p);
+    if (d.any_local) hipLaunchKernelGGL((k_br_downsweep<B, u32>), gt, dim3(BR_BLOCK), 0, s, a, b, p);
+    if (d.any_global) hipLaunchKernelGGL((k_br_downsweep<B, u64>), gt, dim3(BR_BLOCK), 0, s, a, b, p);
   }
   AIWC_MARK(pm, "k_br_sort", s);
-  hipLaunchKernelGGL(k_br_segments<B>, dim3((unsigned)gx, d.n), dim3(256), 0, s, a, b);
+  if (d.any_local) hipLaunchKernelGGL((k_br_segments<B, u32>), gp, dim3(256), 0, s, a, b);
+  if (d.any_global) hipLaunchKernelGGL((k_br_segments<B, u64>), gp, dim3(256), 0, s, a, b);
   AIWC_MARK(pm, "k_br_segments", s);
   u64 nb = d.max_br_blocks < 256 ? d.max_br_blocks : 256;
-  hipLaunchKernelGGL(k_br_windows<B>, dim3((unsigned)nb, d.n), dim3(WIN_BLOCK), 0, s, a, b);
+  const dim3 gw((unsigned)nb, d.n);
+  if (d.any_local) hipLaunchKernelGGL((k_br_windows<B, false>), gw, dim3(WIN_BLOCK), 0, s, a, b);
+  if (d.any_global) hipLaunchKernelGGL((k_br_windows<B, true>), gw, dim3(WIN_BLOCK), 0, s, a, b);
   AIWC_MARK(pm, "k_br_windows", s);
+  if (d.any_pattern) {
+    u64 pb = (d.max_pattern_bins + 255) / 256;
+    if (pb > 1024) pb = 1024;
+    hipLaunchKernelGGL(k_br_pattern<B>, dim3((unsigned)pb, d.n), dim3(256), 0, s, a, b);
+    AIWC_MARK(pm, "k_br_pattern", s);
+  }
 }
 
 hipError_t launch_branch(const TraceArgs &a, const BatchDims &d, hipStream_t s, StageMarks *pm) {

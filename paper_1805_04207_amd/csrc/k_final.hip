@@ -322,6 +322,13 @@ __global__ void __launch_bounds__(FB) k_finalize(TraceArgs A0, const TraceArgs *
   const double nw = (double)acc->br_windows;
   o->yokota_entropy = acc->br_windows ? fx64_to_double(acc->yok_lo, acc->yok_hi) / nw : 0.0;
   o->linear_branch_entropy = acc->br_windows ? (double)(2 * acc->br_minsum) / nw : 0.0;
+  // pattern form of the branch history entropy, normalised by m; NaN when
+  // the trace did not ask for it
+  o->pattern_entropy = (A.br_flags & AIWC_BRANCH_PATTERN_ENTROPY)
+                           ? (acc->br_windows
+                                  ? fx64_to_double(acc->pat_lo, acc->pat_hi) / nw / (double)A.m
+                                  : 0.0)
+                           : __builtin_nan("");
   // derived parallelism metrics of the LU analysis: inverses of work-items,
   // mean ITB and mean SIMD width as single divisions of the exact integers
   // (x/0 = inf, 0/0 = NaN), and the spread of instructions per work-item

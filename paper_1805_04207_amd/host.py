@@ -24,7 +24,7 @@ def host_to_device(tr, device: int = 0):
 
 
 def device_trace(ctx, tensors, table, n_sites: int, history_len: int, wg_size: int = 0,
-                 validate: bool = False):
+                 validate: bool = False, branch_flags: int = 0):
     """aiwc_trace over a dict of device tensors (opcode, wi_offsets, addr,
     mem_kind, br_site, br_taken); empty streams may be omitted / empty."""
     g = tensors.get
@@ -39,4 +39,4 @@ def device_trace(ctx, tensors, table, n_sites: int, history_len: int, wg_size: i
     if g("n_branch") is not None:
         site, taken = site[:g("n_branch")], taken[:g("n_branch")]
     return ctx.trace(op, g("wi_offsets"), addr, kind, site, taken, table, n_sites,
-                     history_len, wg_size, validate)
+                     history_len, wg_size, validate, branch_flags)

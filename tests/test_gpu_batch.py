@@ -7,6 +7,7 @@ import pytest
 import oracle
 import tracegen as tg
 from oracle.compare import compare
+from gpu_util import same
 
 pytestmark = pytest.mark.gpu
 
@@ -38,7 +39,7 @@ def test_batch_equals_single_and_oracle(batch12):
     got = [m.read() for m in c.characterize_batch(trs)]
     single = [c.characterize(t).read() for t in trs]
     for g, s in zip(got, single):
-        assert g == s
+        assert same(g, s, drop=())
     for h, g in list(zip(hosts, got))[:6]:
         bad = compare(g, oracle.characterize(h))
         assert not bad, "\n".join(bad[:10])
@@ -51,7 +52,7 @@ def test_graph_replays_are_identical(batch12):
     ref = [m.read() for m in c.characterize_batch(trs)]
     for rep in range(3):
         got = [m.read() for m in c.characterize_batch(trs, use_graph=True)]
-        assert got == ref, f"replay {rep}"
+        assert all(same(g, r, drop=()) for g, r in zip(got, ref)), f"replay {rep}"
         # eager work between replays
         c.characterize(trs[0]).read()
 
@@ -62,7 +63,7 @@ def test_admission_waves_and_forced_redo(batch12):
     c = ctx()
     ref = [m.read() for m in c.characterize_batch(trs)]
     got = [m.read() for m in c.characterize_batch(trs, admission_cap_bytes=8 << 20)]
-    assert got == ref
+    assert all(same(g, r, drop=()) for g, r in zip(got, ref))
     assert c.batch_stats()["waves"] >= 2
     # add a trace with ~6e5 memory events: 16 forced partitions overflow
     import paper_1805_04207_amd as aiwc
@@ -73,10 +74,7 @@ def test_admission_waves_and_forced_redo(batch12):
     ref = [m.read() for m in c.characterize_batch(trs2)]
     got = [m.read() for m in c.characterize_batch(trs2, force_partition_log2=4)]
     for g, r in zip(got, ref):
-        g = dict(g); r = dict(r)
-        for f in ("overflow_redos", "partitions"):
-            g.pop(f); r.pop(f)
-        assert g == r
+        assert same(g, r)
     assert c.batch_stats()["redo_partitions"] > 0
 
 
@@ -89,7 +87,4 @@ def test_autotune_search_keeps_results(batch12, tmp_path, monkeypatch):
     ref = [m.read() for m in c.characterize_batch(trs)]
     got = [m.read() for m in c.characterize_batch(trs, autotune=aiwc.AUTOTUNE_SEARCH)]
     for g, r in zip(got, ref):
-        g = dict(g); r = dict(r)
-        for f in ("overflow_redos", "partitions"):
-            g.pop(f); r.pop(f)
-        assert g == r
+        assert same(g, r)

@@ -21,7 +21,8 @@ def on_device(trs):
     for tr in trs:
         dev = aiwc.host_to_device(tr, 0)
         keep.append(dev)
-        hs.append(aiwc.device_trace(c, dev, tr.table, int(tr.n_sites), int(tr.history_len)))
+        hs.append(aiwc.device_trace(c, dev, tr.table, int(tr.n_sites), int(tr.history_len),
+                                    branch_flags=int(getattr(tr, "branch_flags", 0))))
     return c, keep, hs
 
 
@@ -89,3 +90,11 @@ def test_mismatched_invocations_are_rejected():
         c.characterize_merged(hs)
     with pytest.raises(aiwc.AiwcError):
         c.characterize_merged([])
+
+
+def test_merged_with_a_branch_variant():
+    rng = np.random.default_rng(41)
+    trs = [random_trace(rng, int(rng.integers(1, 20)), 1500, 30, 6) for _ in range(3)]
+    for t in trs:
+        t.branch_flags = 4 | 8
+    check(trs)
