@@ -132,6 +132,43 @@ def batch_legs(ctx, tr, spec, n_ev, args, stream):
     return out
 
 
+def variants_leg(ctx, dev, spec, n_ev, args, stream):
+    """The large trace under the branch-entropy variants (zero-initialised
+    histories, the global history, the pattern entropy): whole-path time,
+    the branch stage's kernel time and the resulting entropies."""
+    import numpy as np
+    import torch
+    import tracegen as tg
+    import paper_1805_04207_amd as aiwc
+
+    out = {}
+    Z, G, P = aiwc.BRANCH_ZERO_HISTORY, aiwc.BRANCH_GLOBAL_HISTORY, aiwc.BRANCH_PATTERN_ENTROPY
+    for name, flags in (("local+pattern", P), ("zero+pattern", Z | P), ("global+pattern", G | P),
+                        ("global+zero", G | Z)):
+        tr = aiwc.device_trace(ctx, dev, tg.opcode_table(), spec.n_sites, spec.history_len,
+                               spec.wg_size, branch_flags=flags)
+        r = ctx.characterize(tr, stream).read()
+        ctx.profile_enable(True)
+        br = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        steps = max(1, args.steps // 2)
+        for _ in range(steps):
+            r = ctx.characterize(tr, stream).read()
+            br.append(sum(ms for k, ms in ctx.profile_read() if k.startswith("k_br_")))
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        ctx.profile_enable(False)
+        out[name] = {"flags": flags, "ms_per_step": 1e3 * dt, "events_per_s": n_ev / dt,
+                     "branch_stage_ms": float(np.mean(br)), "n_windows": r["n_windows"],
+                     "yokota_entropy": r["yokota_entropy"],
+                     "linear_branch_entropy": r["linear_branch_entropy"],
+                     "pattern_entropy": r["pattern_entropy"]}
+        print(f"# branch variant {name}: {1e3 * dt:.2f} ms, branch stage "
+              f"{out[name]['branch_stage_ms']:.3f} ms", file=sys.stderr, flush=True)
+    return out
+
+
 def stress_leg(ctx, args, sizing, stream):
     """The stress batch (config5 recipe: 64 traces, ~2^32 uniform addresses in
     total, up to 2^28 per trace, 2^16 sites, history 32) in one batched call
@@ -189,6 +226,8 @@ def main() -> int:
     ap.add_argument("--batch-traces", type=int, default=512)
     ap.add_argument("--batch-scale", type=float, default=1.0,
                     help="config3 lengths are scaled by this factor")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the branch-entropy variant leg")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="one characterization, then a plain device copy of 1 GiB, for "
                          "rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs; prints no JSON")
@@ -255,6 +294,12 @@ def main() -> int:
     tpath = os.path.join(ROOT, "profiles", f"traffic_{dom}_{workload_tag(args.n_wi_log2)}.md")
     trec = read_traffic(tpath, dom, workload_tag(args.n_wi_log2))
 
+    variants = None
+    if not args.no_variants:
+        variants = variants_leg(ctx, dev, spec, n_ev, args, stream)
+        variants["default"] = {"branch_stage_ms": sum(v for k, v in avg.items()
+                                                      if k.startswith("k_br_"))}
+
     batched = None
     if not args.no_batch:
         batched = batch_legs(ctx, tr, spec, n_ev, args, stream)
@@ -284,7 +329,8 @@ def main() -> int:
                    "compulsory_bytes": compulsory, "compulsory_gbps": comp_gbs,
                    "compulsory_hbm_frac": comp_gbs / HBM_PEAK_GBS,
                    "kernel_ms": avg, "partitions": r["partitions"],
-                   "overflow_redos": r["overflow_redos"], "batched": batched},
+                   "overflow_redos": r["overflow_redos"], "branch_variants": variants,
+                   "batched": batched},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
                      "traffic": trec["traffic_bytes"] if trec else None,
