@@ -169,6 +169,53 @@ def variants_leg(ctx, dev, spec, n_ev, args, stream):
     return out
 
 
+def stream_leg(ctx, dev, spec, n_ev, args, stream, ref):
+    """The large trace appended in 16 chunks of whole work-items (memory and
+    branch streams cut at matching points) and finished: time per pass,
+    the retained bytes, and identity with the plain path."""
+    import torch
+    import tracegen as tg
+    import paper_1805_04207_amd as aiwc
+
+    k = 16
+    off = dev["wi_offsets"]
+    wcut = [spec.n_wi * i // k for i in range(k + 1)]
+    ecut = off[torch.tensor(wcut, device=off.device)].cpu().tolist()
+    mcut = [dev["n_mem"] * i // k for i in range(k + 1)]
+    bcut = [dev["n_branch"] * i // k for i in range(k + 1)]
+    tab = tg.opcode_table()
+    chunks = []
+    for i in range(k):
+        p = {"opcode": dev["opcode"][ecut[i]:ecut[i + 1]],
+             "wi_offsets": (off[wcut[i]:wcut[i + 1] + 1] - off[wcut[i]]).contiguous(),
+             "addr": dev["addr"][mcut[i]:mcut[i + 1]],
+             "mem_kind": dev["mem_kind"][mcut[i]:mcut[i + 1]],
+             "br_site": dev["br_site"][bcut[i]:bcut[i + 1]],
+             "br_taken": dev["br_taken"][bcut[i]:bcut[i + 1]]}
+        chunks.append(aiwc.device_trace(ctx, p, tab, spec.n_sites, spec.history_len, spec.wg_size))
+
+    def one():
+        st = ctx.stream()
+        for c in chunks:
+            st.append(c, stream)
+        r = st.finish(stream).read()
+        st.close()
+        return r
+
+    got = one()
+    torch.cuda.synchronize()
+    steps = max(1, args.steps // 2)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        got = one()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    return {"chunks": k, "ms": 1e3 * dt, "events_per_s": n_ev / dt,
+            "retained_bytes": 9 * dev["n_mem"] + 5 * dev["n_branch"],
+            "input_bytes": 2 * n_ev + 8 * (spec.n_wi + 1) + 9 * dev["n_mem"] + 5 * dev["n_branch"],
+            "identical_to_plain": strip(got) == strip(ref)}
+
+
 def stress_leg(ctx, args, sizing, stream):
     """The stress batch (config5 recipe: 64 traces, ~2^32 uniform addresses in
     total, up to 2^28 per trace, 2^16 sites, history 32) in one batched call
@@ -294,6 +341,10 @@ def main() -> int:
     tpath = os.path.join(ROOT, "profiles", f"traffic_{dom}_{workload_tag(args.n_wi_log2)}.md")
     trec = read_traffic(tpath, dom, workload_tag(args.n_wi_log2))
 
+    streamed = stream_leg(ctx, dev, spec, n_ev, args, stream, r)
+    print(f"# stream of 16 chunks: {streamed['ms']:.2f} ms, identical "
+          f"{streamed['identical_to_plain']}", file=sys.stderr, flush=True)
+
     variants = None
     if not args.no_variants:
         variants = variants_leg(ctx, dev, spec, n_ev, args, stream)
@@ -329,7 +380,8 @@ def main() -> int:
                    "compulsory_bytes": compulsory, "compulsory_gbps": comp_gbs,
                    "compulsory_hbm_frac": comp_gbs / HBM_PEAK_GBS,
                    "kernel_ms": avg, "partitions": r["partitions"],
-                   "overflow_redos": r["overflow_redos"], "branch_variants": variants,
+                   "overflow_redos": r["overflow_redos"], "streamed": streamed,
+                   "branch_variants": variants,
                    "batched": batched},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,

@@ -290,6 +290,39 @@ aiwc_status aiwc_characterize(aiwc_ctx *ctx, const aiwc_trace *trace,
 aiwc_status aiwc_characterize_merged(aiwc_ctx *ctx, const aiwc_trace *const *traces,
                                      size_t n, void *stream, aiwc_metrics **out);
 
+/* ---------------------------------------------------------- streaming
+ * A trace that arrives in chunks.  The paper names the memory footprint of
+ * full recorded traces as its tool's main limit on large applications
+ * (Conclusions; Evaluation: kernels it could not characterize at large
+ * sizes).  A chunk is a trace handle holding a run of whole work-items with
+ * the memory and branch events they issued, in order.  The result of
+ * aiwc_stream_finish is, exactly, that of aiwc_characterize on the
+ * concatenation of the chunks (the aggregate of aiwc_characterize_merged).
+ * On append, a chunk's instruction stream is reduced into the stream's
+ * state (opcodes and work-item offsets are not kept); its memory and branch
+ * streams are copied into device buffers the stream owns (9 B per memory
+ * event, 5 B per branch event), which finish reduces with the ordinary
+ * memory and branch stages.                                                 */
+typedef struct aiwc_stream aiwc_stream;
+/* An empty stream of this context.  Errors: INVALID_ARG (null).            */
+aiwc_status aiwc_stream_create(aiwc_ctx *ctx, aiwc_stream **out);
+/* Append one chunk, a trace handle of the stream's context.  The first
+ * chunk fixes the opcode table, history_len and branch flags; later chunks
+ * must match.  Asynchronous on `stream`: the chunk's device arrays are read
+ * by work enqueued there, so keep them until that work completes (the chunk
+ * handle itself may be destroyed at once).  Errors: INVALID_ARG (null,
+ * foreign handle, mismatch, finished stream, summed n_mem or n_branch
+ * reaching 2^32), OUT_OF_MEMORY, HIP.                                       */
+aiwc_status aiwc_stream_append(aiwc_stream *st, const aiwc_trace *chunk, void *stream);
+/* Reduce everything appended and return its metrics handle (as
+ * aiwc_characterize does); the stream then takes no more chunks.  The
+ * stream must outlive the returned handle's work (aiwc_stream_destroy
+ * waits for the device).  Errors: INVALID_ARG (null, nothing appended,
+ * already finished), OUT_OF_MEMORY, HIP.                                    */
+aiwc_status aiwc_stream_finish(aiwc_stream *st, void *stream, aiwc_metrics **out);
+/* Release the stream's buffers (waits for the device).  NULL is a no-op. */
+aiwc_status aiwc_stream_destroy(aiwc_stream *st);
+
 /* Sizing policy for the memory partitions and on-chip tables.             */
 typedef enum aiwc_sizing {
   AIWC_SIZING_BOUND = 0,      /* distinct <= accesses: never undersized     */

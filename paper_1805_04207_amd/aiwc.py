@@ -101,6 +101,7 @@ class TrainOpts(ctypes.Structure):
 EXPORTS = [
     "aiwc_context_create", "aiwc_context_destroy", "aiwc_last_error", "aiwc_trace_create",
     "aiwc_trace_destroy", "aiwc_characterize", "aiwc_characterize_merged",
+    "aiwc_stream_create", "aiwc_stream_append", "aiwc_stream_finish", "aiwc_stream_destroy",
     "aiwc_characterize_batch", "aiwc_batch_last_stats",
     "aiwc_metrics_read", "aiwc_metrics_class_hist", "aiwc_metrics_spectrum", "aiwc_metrics_destroy",
     "aiwc_sizer_features", "aiwc_sizer_train", "aiwc_sizer_predict", "aiwc_sizer_grad",
@@ -133,6 +134,10 @@ def load_library(path: str = LIB_PATH):
         "aiwc_trace_destroy": (st, [vp]),
         "aiwc_characterize": (st, [vp, vp, vp, ctypes.POINTER(vp)]),
         "aiwc_characterize_merged": (st, [vp, ctypes.POINTER(vp), sz, vp, ctypes.POINTER(vp)]),
+        "aiwc_stream_create": (st, [vp, ctypes.POINTER(vp)]),
+        "aiwc_stream_append": (st, [vp, vp, vp]),
+        "aiwc_stream_finish": (st, [vp, vp, ctypes.POINTER(vp)]),
+        "aiwc_stream_destroy": (st, [vp]),
         "aiwc_characterize_batch": (st, [vp, ctypes.POINTER(vp), sz, ctypes.POINTER(BatchOpts), vp,
                                          ctypes.POINTER(vp)]),
         "aiwc_batch_last_stats": (st, [vp, ctypes.POINTER(BatchStats)]),
@@ -227,6 +232,10 @@ class Context:
                                                      ctypes.byref(m)))
         return Metrics(self, m)
 
+    def stream(self) -> "Stream":
+        """A trace that arrives in chunks (aiwc_stream_*)."""
+        return Stream(self)
+
     def characterize_batch(self, traces: Sequence["Trace"], sizing: int = SIZING_BOUND,
                            autotune: int = AUTOTUNE_OFF, use_graph: bool = False,
                            admission_cap_bytes: int = 0, force_partition_log2: int = 0,
@@ -320,6 +329,40 @@ def _stream_ptr(stream) -> Optional[int]:
     return int(stream)
 
 
+class Stream:
+    """aiwc_stream: append chunk traces, then finish into one Metrics.  The
+    chunks' tensors are kept referenced until the stream is closed, since
+    the appends read them asynchronously."""
+
+    def __init__(self, ctx: "Context"):
+        self.ctx = ctx
+        self.h = ctypes.c_void_p()
+        self._keep = []
+        ctx.check(ctx.lib.aiwc_stream_create(ctx.h, ctypes.byref(self.h)))
+
+    def append(self, chunk: "Trace", stream=None):
+        self._keep.append(chunk)
+        self.ctx.check(self.ctx.lib.aiwc_stream_append(self.h, chunk.h, _stream_ptr(stream)))
+
+    def finish(self, stream=None) -> "Metrics":
+        m = ctypes.c_void_p()
+        self.ctx.check(self.ctx.lib.aiwc_stream_finish(self.h, _stream_ptr(stream),
+                                                       ctypes.byref(m)))
+        return Metrics(self.ctx, m, keep=self)
+
+    def close(self):
+        if self.h:
+            self.ctx.lib.aiwc_stream_destroy(self.h)
+            self.h = ctypes.c_void_p()
+            self._keep = []
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Trace:
     """aiwc_trace: borrows the tensors (kept referenced here)."""
 
@@ -380,9 +423,10 @@ def _ptr(t) -> Optional[int]:
 class Metrics:
     """aiwc_metrics: a pending result on the device."""
 
-    def __init__(self, ctx: Context, h):
+    def __init__(self, ctx: Context, h, keep=None):
         self.ctx = ctx
         self.h = h
+        self._keep = keep   # an object whose buffers the pending work reads
 
     def read(self) -> Dict:
         r = MetricsHost()

@@ -1,0 +1,267 @@
+// stream.hip -- characterization of a trace that arrives in chunks.
+//
+// The paper names the memory footprint of full recorded traces as the main
+// limit of its tool on large applications (Conclusions) and lists kernels it
+// could not characterize at large sizes for that reason (Evaluation).  Here a
+// chunk (a run of whole work-items with the memory and branch events they
+// issued) is reduced as far as it can be on arrival: its instruction stream
+// goes through k_ops into per-stream state (counters, the id histogram, the
+// ITB / IPT histograms and large-value lists), so opcodes and work-item
+// offsets are never kept; its memory and branch streams are appended to
+// device buffers owned by the stream.  aiwc_stream_finish then runs the
+// ordinary memory and branch stages and k_finalize over the whole, so the
+// result is exactly that of the concatenated trace.
+#include <algorithm>
+#include <cstring>
+
+#include "abi_internal.h"
+
+#define ST_HIP_OR(ctx, call)                                                    \
+  do {                                                                          \
+    hipError_t e__ = (call);                                                    \
+    if (e__ != hipSuccess) {                                                    \
+      ctx_error(ctx, "%s failed: %s", #call, hipGetErrorString(e__));           \
+      return AIWC_ERR_HIP;                                                      \
+    }                                                                           \
+  } while (0)
+
+namespace {
+
+// A device buffer that grows by doubling; `used` bytes survive a move.
+struct GrowBuf {
+  char *p = nullptr;
+  u64 cap = 0, used = 0;
+};
+
+aiwc_status grow(aiwc_ctx *ctx, GrowBuf &b, u64 need, hipStream_t s) {
+  if (need <= b.cap) return AIWC_OK;
+  const u64 nc = std::max<u64>(need, std::max<u64>(2 * b.cap, 1ull << 16));
+  char *np = nullptr;
+  if (hipMalloc(&np, nc) != hipSuccess) {
+    hipGetLastError();
+    ctx_error(ctx, "out of device memory: a stream buffer of %llu bytes", (unsigned long long)nc);
+    return AIWC_ERR_OUT_OF_MEMORY;
+  }
+  if (b.p) {
+    if (b.used) ST_HIP_OR(ctx, hipMemcpyAsync(np, b.p, b.used, hipMemcpyDeviceToDevice, s));
+    ST_HIP_OR(ctx, hipStreamSynchronize(s));
+    hipFree(b.p);
+  }
+  b.p = np;
+  b.cap = nc;
+  return AIWC_OK;
+}
+
+aiwc_status append_bytes(aiwc_ctx *ctx, GrowBuf &b, const void *src, u64 bytes, hipStream_t s) {
+  if (!bytes) return AIWC_OK;
+  aiwc_status st = grow(ctx, b, b.used + bytes, s);
+  if (st != AIWC_OK) return st;
+  ST_HIP_OR(ctx, hipMemcpyAsync(b.p + b.used, src, bytes, hipMemcpyDeviceToDevice, s));
+  b.used += bytes;
+  return AIWC_OK;
+}
+
+constexpr u32 VARIANT_FLAGS =
+    AIWC_BRANCH_ZERO_HISTORY | AIWC_BRANCH_GLOBAL_HISTORY | AIWC_BRANCH_PATTERN_ENTROPY;
+
+}  // namespace
+
+struct aiwc_stream {
+  aiwc_ctx *ctx = nullptr;
+  bool started = false, finished = false;
+  aiwc_trace proto;                 // opcode table, history length, variant flags
+  u64 n_events = 0, n_wi = 0;
+  u32 n_sites = 0;
+  // instruction-stream state: DevAccum | id_hist | itb_hist | ipt_hist
+  char *core = nullptr;
+  u64 o_id = 0, o_itb = 0, o_ipt = 0, core_bytes = 0;
+  GrowBuf itb_large, ipt_large;     // values >= VAL_DENSE, 8 B each
+  GrowBuf addr, kind, site, taken;  // retained memory and branch streams
+};
+
+extern "C" aiwc_status aiwc_stream_create(aiwc_ctx *ctx, aiwc_stream **out) {
+  if (!ctx || !out) { ctx_error(ctx, "aiwc_stream_create: NULL argument"); return AIWC_ERR_INVALID_ARG; }
+  aiwc_stream *st = new aiwc_stream();
+  st->ctx = ctx;
+  *out = st;
+  return AIWC_OK;
+}
+
+// The first chunk fixes the table, history length and variant: copy them
+// (the chunk's own handle may go away) and set up the zeroed state.
+static aiwc_status stream_start(aiwc_stream *st, const aiwc_trace *t, hipStream_t s) {
+  aiwc_ctx *ctx = st->ctx;
+  st->proto.ctx = ctx;
+  st->proto.d = t->d;
+  st->proto.d.flags = t->d.flags & VARIANT_FLAGS;
+  st->proto.n_classes = t->n_classes;
+  st->proto.host_info = t->host_info;
+  const u64 ids = t->host_info.size();
+  if (hipMalloc(&st->proto.dev_info, 4 * ids) != hipSuccess) {
+    hipGetLastError();
+    ctx_error(ctx, "out of device memory for the stream's opcode table");
+    return AIWC_ERR_OUT_OF_MEMORY;
+  }
+  ST_HIP_OR(ctx, hipMemcpy(st->proto.dev_info, t->host_info.data(), 4 * ids,
+                           hipMemcpyHostToDevice));
+  auto al = [](u64 x) { return (x + 255) & ~255ull; };
+  st->o_id = al(sizeof(DevAccum));
+  st->o_itb = st->o_id + al(8 * ids);
+  st->o_ipt = st->o_itb + al(8ull * VAL_DENSE);
+  st->core_bytes = st->o_ipt + al(8ull * VAL_DENSE);
+  if (hipMalloc(&st->core, st->core_bytes) != hipSuccess) {
+    hipGetLastError();
+    ctx_error(ctx, "out of device memory for the stream state");
+    return AIWC_ERR_OUT_OF_MEMORY;
+  }
+  TraceArgs z;
+  memset(&z, 0, sizeof z);
+  z.zero_base = st->core;
+  z.zero_bytes = st->core_bytes;
+  BatchDims d;
+  d.max_zero16 = st->core_bytes / 16;
+  ST_HIP_OR(ctx, aiwc_kernels::launch_zero(z, d, s));
+  st->started = true;
+  return AIWC_OK;
+}
+
+// Pointers of the instruction-stream state in a TraceArgs.
+static void point_at_state(const aiwc_stream *st, TraceArgs &a) {
+  a.acc = (DevAccum *)st->core;
+  a.id_hist = (u64 *)(st->core + st->o_id);
+  a.itb_hist = (u64 *)(st->core + st->o_itb);
+  a.ipt_hist = (u64 *)(st->core + st->o_ipt);
+  a.itb_large = (u64 *)st->itb_large.p;
+  a.ipt_large = (u64 *)st->ipt_large.p;
+  a.large_cap = st->itb_large.cap / 8;
+}
+
+extern "C" aiwc_status aiwc_stream_append(aiwc_stream *st, const aiwc_trace *t, void *stream) {
+  aiwc_ctx *ctx = st ? st->ctx : nullptr;
+  if (!st || !t) { ctx_error(ctx, "aiwc_stream_append: NULL argument"); return AIWC_ERR_INVALID_ARG; }
+  if (t->ctx != ctx) { ctx_error(ctx, "aiwc_stream_append: chunk belongs to another context"); return AIWC_ERR_INVALID_ARG; }
+  if (st->finished) { ctx_error(ctx, "aiwc_stream_append: the stream is finished"); return AIWC_ERR_INVALID_ARG; }
+  if (st->started && (t->d.history_len != st->proto.d.history_len ||
+                      (t->d.flags & VARIANT_FLAGS) != st->proto.d.flags ||
+                      t->host_info != st->proto.host_info)) {
+    ctx_error(ctx, "aiwc_stream_append: chunk has another opcode table, history length or "
+              "branch variant than the stream");
+    return AIWC_ERR_INVALID_ARG;
+  }
+  const aiwc_trace_desc &d = t->d;
+  if (st->addr.used / 8 + d.n_mem >= (1ull << 32) || st->taken.used + d.n_branch >= (1ull << 32)) {
+    ctx_error(ctx, "aiwc_stream_append: the stream's n_mem and n_branch must stay < 2^32");
+    return AIWC_ERR_INVALID_ARG;
+  }
+  ST_HIP_OR(ctx, hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  aiwc_status rc = AIWC_OK;
+  if (!st->started && (rc = stream_start(st, t, s)) != AIWC_OK) return rc;
+  // large ITB / IPT values: at most one per VAL_DENSE instructions, so this
+  // capacity can never be exceeded by the stream so far
+  // (the device holds the fill counts, so a move copies the whole old list)
+  const u64 large = 8 * ((st->n_events + d.n_events) / VAL_DENSE + 1);
+  st->itb_large.used = st->itb_large.cap;
+  st->ipt_large.used = st->ipt_large.cap;
+  if ((rc = grow(ctx, st->itb_large, large, s)) != AIWC_OK) return rc;
+  if ((rc = grow(ctx, st->ipt_large, large, s)) != AIWC_OK) return rc;
+  // the instruction stream, reduced into the state
+  TracePlan p;
+  plan_trace(t, 4, p);
+  TraceArgs a;
+  memset(&a, 0, sizeof a);
+  a.opcode = d.opcode;
+  a.wi_off = (const u64 *)d.wi_offsets;
+  a.op_info = st->proto.dev_info;
+  a.n_events = d.n_events;
+  a.n_wi = d.n_workitems;
+  a.n_ids = d.n_opcode_ids;
+  a.ops_task = p.ops_task;
+  a.ops_tasks = p.ops_tasks;
+  point_at_state(st, a);
+  BatchDims dims;
+  dims.max_ops_tasks = p.ops_tasks;
+  dims.max_ids = d.n_opcode_ids;
+  dims.ops_lds = aiwc_kernels::ops_lds_bytes(d.n_opcode_ids);
+  dims.ops_vec = ((uintptr_t)d.opcode % 16) == 0;
+  ST_HIP_OR(ctx, aiwc_kernels::launch_ops(a, dims, s, nullptr));
+  // the memory and branch streams, kept for finish
+  if ((rc = append_bytes(ctx, st->addr, d.addr, 8 * d.n_mem, s)) != AIWC_OK) return rc;
+  if ((rc = append_bytes(ctx, st->kind, d.mem_kind, d.n_mem, s)) != AIWC_OK) return rc;
+  if ((rc = append_bytes(ctx, st->site, d.br_site, 4 * d.n_branch, s)) != AIWC_OK) return rc;
+  if ((rc = append_bytes(ctx, st->taken, d.br_taken, d.n_branch, s)) != AIWC_OK) return rc;
+  st->n_events += d.n_events;
+  st->n_wi += d.n_workitems;
+  st->n_sites = std::max(st->n_sites, d.n_sites);
+  return AIWC_OK;
+}
+
+extern "C" aiwc_status aiwc_stream_finish(aiwc_stream *st, void *stream, aiwc_metrics **out) {
+  aiwc_ctx *ctx = st ? st->ctx : nullptr;
+  if (!st || !out) { ctx_error(ctx, "aiwc_stream_finish: NULL argument"); return AIWC_ERR_INVALID_ARG; }
+  if (st->finished) { ctx_error(ctx, "aiwc_stream_finish: the stream is finished"); return AIWC_ERR_INVALID_ARG; }
+  if (!st->started) { ctx_error(ctx, "aiwc_stream_finish: no chunk was appended"); return AIWC_ERR_INVALID_ARG; }
+  ST_HIP_OR(ctx, hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  // the whole trace as the later stages see it: no instruction stream (it
+  // is already reduced), the retained memory and branch streams
+  aiwc_trace mt;
+  mt.ctx = ctx;
+  mt.d = st->proto.d;
+  mt.d.n_events = st->n_events;
+  mt.d.opcode = nullptr;
+  mt.d.n_workitems = st->n_wi;
+  mt.d.wi_offsets = nullptr;
+  mt.d.n_mem = st->kind.used;
+  mt.d.addr = (const uint64_t *)st->addr.p;
+  mt.d.mem_kind = (const uint8_t *)st->kind.p;
+  mt.d.n_branch = st->taken.used;
+  mt.d.br_site = (const uint32_t *)st->site.p;
+  mt.d.br_taken = (const uint8_t *)st->taken.p;
+  mt.d.n_sites = st->n_sites;
+  mt.n_classes = st->proto.n_classes;
+  mt.dev_info = st->proto.dev_info;
+  TracePlan p;
+  plan_trace(&mt, bound_pbits(mt.d.n_mem), p);
+  aiwc_status rc = ensure_arena(ctx, p.scratch_bytes);
+  if (rc != AIWC_OK) { mt.dev_info = nullptr; return rc; }
+  aiwc_metrics *m = nullptr;
+  rc = new_metrics(ctx, &mt, p, &m);
+  if (rc != AIWC_OK) { mt.dev_info = nullptr; return rc; }
+  if (ctx->last_done) ST_HIP_OR(ctx, hipStreamWaitEvent(s, ctx->last_done, 0));
+  TraceArgs a;
+  fill_args(&mt, p, ctx->arena, (char *)m->buf, a);
+  point_at_state(st, a);
+  BatchDims dims;
+  add_dims(&mt, p, a, dims);
+  StageMarks *pm = nullptr;
+  if (ctx->prof.on) { ctx->prof.begin(s); pm = &ctx->prof; }
+  hipError_t e = aiwc_kernels::launch_zero(a, dims, s);
+  if (e == hipSuccess) e = aiwc_kernels::launch_mem(a, dims, s, pm);
+  if (e == hipSuccess) e = aiwc_kernels::launch_branch(a, dims, s, pm);
+  if (e == hipSuccess) e = aiwc_kernels::launch_finalize(a, dims, s, pm);
+  mt.dev_info = nullptr;
+  if (e != hipSuccess) {
+    ctx_error(ctx, "kernel launch failed: %s", hipGetErrorString(e));
+    aiwc_metrics_destroy(m);
+    return AIWC_ERR_HIP;
+  }
+  ST_HIP_OR(ctx, hipEventRecord(m->done, s));
+  if (!ctx->last_done) ST_HIP_OR(ctx, hipEventCreateWithFlags(&ctx->last_done, hipEventDisableTiming));
+  ST_HIP_OR(ctx, hipEventRecord(ctx->last_done, s));
+  st->finished = true;
+  *out = m;
+  return AIWC_OK;
+}
+
+extern "C" aiwc_status aiwc_stream_destroy(aiwc_stream *st) {
+  if (!st) return AIWC_OK;
+  hipSetDevice(st->ctx->device);
+  hipDeviceSynchronize();
+  for (GrowBuf *b : {&st->itb_large, &st->ipt_large, &st->addr, &st->kind, &st->site, &st->taken})
+    if (b->p) hipFree(b->p);
+  if (st->core) hipFree(st->core);
+  if (st->proto.dev_info) hipFree(st->proto.dev_info);
+  delete st;
+  return AIWC_OK;
+}

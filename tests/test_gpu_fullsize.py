@@ -15,6 +15,8 @@
   uneven invocations merged must satisfy every relation between an aggregate
   and its parts, and the 256 smallest merged must match the vectorised oracle
   on their concatenation.
+* Streaming: the plain large trace appended in 16 chunks and finished must
+  equal the plain path on the whole.
 * The stress batch (64 traces, 2^32 addresses in total, up to 2^28 per trace,
   history 32 over 2^16 sites) in one batched call with learned sizing and a
   200 GiB admission cap: the two smallest traces against the C oracle, every
@@ -304,3 +306,33 @@ def test_merged_uneven_invocations_full_size():
     bad = compare(got, want)
     assert not bad, "\n".join(bad[:20])
     log(f"256 smallest merged ({sum(n_ev[i] for i in order)} events) match the oracle")
+
+
+@pytest.mark.timeout(1200)
+def test_stream_of_the_large_trace():
+    import torch
+    import paper_1805_04207_amd as aiwc
+
+    spec = tg.config2(n_wi=1 << 20)
+    d = tg.generate_device(spec, 0)
+    ctx = aiwc.Context(0)
+    tab = tg.opcode_table()
+    plain = ctx.characterize(aiwc.device_trace(ctx, d, tab, spec.n_sites, spec.history_len,
+                                               spec.wg_size)).read()
+    k = 16
+    wcut = np.linspace(0, spec.n_wi, k + 1).astype(np.int64)
+    off = d["wi_offsets"]
+    ecut = off[torch.from_numpy(wcut).to(off.device)].cpu().numpy()
+    mcut = np.linspace(0, d["n_mem"], k + 1).astype(np.int64)
+    bcut = np.linspace(0, d["n_branch"], k + 1).astype(np.int64)
+    st = ctx.stream()
+    for i in range(k):
+        p = {"opcode": d["opcode"][ecut[i]:ecut[i + 1]],
+             "wi_offsets": (off[wcut[i]:wcut[i + 1] + 1] - off[wcut[i]]).contiguous(),
+             "addr": d["addr"][mcut[i]:mcut[i + 1]], "mem_kind": d["mem_kind"][mcut[i]:mcut[i + 1]],
+             "br_site": d["br_site"][bcut[i]:bcut[i + 1]],
+             "br_taken": d["br_taken"][bcut[i]:bcut[i + 1]]}
+        st.append(aiwc.device_trace(ctx, p, tab, spec.n_sites, spec.history_len, spec.wg_size))
+    got = st.finish().read()
+    assert same(got, plain), "stream of 16 chunks differs from the whole"
+    log("stream of 16 chunks identical to the plain path on the whole")
