@@ -195,7 +195,7 @@ def stream_leg(ctx, dev, spec, n_ev, args, stream, ref):
         chunks.append(aiwc.device_trace(ctx, p, tab, spec.n_sites, spec.history_len, spec.wg_size))
 
     def one():
-        st = ctx.stream()
+        st = ctx.stream(dev["n_mem"], dev["n_branch"])
         for c in chunks:
             st.append(c, stream)
         r = st.finish(stream).read()

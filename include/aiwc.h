@@ -304,8 +304,13 @@ aiwc_status aiwc_characterize_merged(aiwc_ctx *ctx, const aiwc_trace *const *tra
  * event, 5 B per branch event), which finish reduces with the ordinary
  * memory and branch stages.                                                 */
 typedef struct aiwc_stream aiwc_stream;
-/* An empty stream of this context.  Errors: INVALID_ARG (null).            */
-aiwc_status aiwc_stream_create(aiwc_ctx *ctx, aiwc_stream **out);
+/* An empty stream of this context.  mem_hint / branch_hint: expected total
+ * memory and branch events (0 = unknown); the retained buffers are reserved
+ * for them up front and otherwise grow by doubling (each move copies what
+ * is held and synchronizes the stream).  Errors: INVALID_ARG (null),
+ * OUT_OF_MEMORY.                                                            */
+aiwc_status aiwc_stream_create(aiwc_ctx *ctx, uint64_t mem_hint, uint64_t branch_hint,
+                               aiwc_stream **out);
 /* Append one chunk, a trace handle of the stream's context.  The first
  * chunk fixes the opcode table, history_len and branch flags; later chunks
  * must match.  Asynchronous on `stream`: the chunk's device arrays are read

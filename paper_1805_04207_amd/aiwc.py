@@ -134,7 +134,7 @@ def load_library(path: str = LIB_PATH):
         "aiwc_trace_destroy": (st, [vp]),
         "aiwc_characterize": (st, [vp, vp, vp, ctypes.POINTER(vp)]),
         "aiwc_characterize_merged": (st, [vp, ctypes.POINTER(vp), sz, vp, ctypes.POINTER(vp)]),
-        "aiwc_stream_create": (st, [vp, ctypes.POINTER(vp)]),
+        "aiwc_stream_create": (st, [vp, u64, u64, ctypes.POINTER(vp)]),
         "aiwc_stream_append": (st, [vp, vp, vp]),
         "aiwc_stream_finish": (st, [vp, vp, ctypes.POINTER(vp)]),
         "aiwc_stream_destroy": (st, [vp]),
@@ -232,9 +232,10 @@ class Context:
                                                      ctypes.byref(m)))
         return Metrics(self, m)
 
-    def stream(self) -> "Stream":
-        """A trace that arrives in chunks (aiwc_stream_*)."""
-        return Stream(self)
+    def stream(self, mem_hint: int = 0, branch_hint: int = 0) -> "Stream":
+        """A trace that arrives in chunks (aiwc_stream_*); the hints reserve
+        the retained buffers for that many memory / branch events."""
+        return Stream(self, mem_hint, branch_hint)
 
     def characterize_batch(self, traces: Sequence["Trace"], sizing: int = SIZING_BOUND,
                            autotune: int = AUTOTUNE_OFF, use_graph: bool = False,
@@ -334,11 +335,11 @@ class Stream:
     chunks' tensors are kept referenced until the stream is closed, since
     the appends read them asynchronously."""
 
-    def __init__(self, ctx: "Context"):
+    def __init__(self, ctx: "Context", mem_hint: int = 0, branch_hint: int = 0):
         self.ctx = ctx
         self.h = ctypes.c_void_p()
         self._keep = []
-        ctx.check(ctx.lib.aiwc_stream_create(ctx.h, ctypes.byref(self.h)))
+        ctx.check(ctx.lib.aiwc_stream_create(ctx.h, mem_hint, branch_hint, ctypes.byref(self.h)))
 
     def append(self, chunk: "Trace", stream=None):
         self._keep.append(chunk)

@@ -79,10 +79,24 @@ struct aiwc_stream {
   GrowBuf addr, kind, site, taken;  // retained memory and branch streams
 };
 
-extern "C" aiwc_status aiwc_stream_create(aiwc_ctx *ctx, aiwc_stream **out) {
+extern "C" aiwc_status aiwc_stream_destroy(aiwc_stream *st);
+
+extern "C" aiwc_status aiwc_stream_create(aiwc_ctx *ctx, uint64_t mem_hint, uint64_t branch_hint,
+                                          aiwc_stream **out) {
   if (!ctx || !out) { ctx_error(ctx, "aiwc_stream_create: NULL argument"); return AIWC_ERR_INVALID_ARG; }
+  ST_HIP_OR(ctx, hipSetDevice(ctx->device));
   aiwc_stream *st = new aiwc_stream();
   st->ctx = ctx;
+  const u64 mh = std::min<u64>(mem_hint, 1ull << 32), bh = std::min<u64>(branch_hint, 1ull << 32);
+  aiwc_status rc = AIWC_OK;
+  if (mh && rc == AIWC_OK) rc = grow(ctx, st->addr, 8 * mh, nullptr);
+  if (mh && rc == AIWC_OK) rc = grow(ctx, st->kind, mh, nullptr);
+  if (bh && rc == AIWC_OK) rc = grow(ctx, st->site, 4 * bh, nullptr);
+  if (bh && rc == AIWC_OK) rc = grow(ctx, st->taken, bh, nullptr);
+  if (rc != AIWC_OK) {
+    aiwc_stream_destroy(st);
+    return rc;
+  }
   *out = st;
   return AIWC_OK;
 }

@@ -325,7 +325,7 @@ def test_stream_of_the_large_trace():
     ecut = off[torch.from_numpy(wcut).to(off.device)].cpu().numpy()
     mcut = np.linspace(0, d["n_mem"], k + 1).astype(np.int64)
     bcut = np.linspace(0, d["n_branch"], k + 1).astype(np.int64)
-    st = ctx.stream()
+    st = ctx.stream(d["n_mem"] // 3)     # reserved below the need: moves happen too
     for i in range(k):
         p = {"opcode": d["opcode"][ecut[i]:ecut[i + 1]],
              "wi_offsets": (off[wcut[i]:wcut[i + 1] + 1] - off[wcut[i]]).contiguous(),

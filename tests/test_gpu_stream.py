@@ -11,11 +11,12 @@ from helpers import mk, random_trace
 pytestmark = pytest.mark.gpu
 
 
-def stream_of(trs, merged_too=True):
+def stream_of(trs, hint=False):
     import paper_1805_04207_amd as aiwc
     from gpu_util import ctx
     c = ctx()
-    st = c.stream()
+    st = c.stream(sum(t.addr.size for t in trs), sum(t.br_site.size for t in trs)) if hint \
+        else c.stream()
     keep = []
     for tr in trs:
         dev = aiwc.host_to_device(tr, 0)
@@ -28,9 +29,9 @@ def stream_of(trs, merged_too=True):
     return c, m, keep
 
 
-def check(trs):
+def check(trs, hint=False):
     from gpu_util import same
-    c, m, keep = stream_of(trs)
+    c, m, keep = stream_of(trs, hint)
     got = m.read()
     mt = oracle.MergedTrace(trs)
     bad = compare(got, oracle.characterize(mt))
@@ -63,6 +64,7 @@ def test_many_chunks_grow_the_buffers():
     trs = [random_trace(rng, 8, 2000, 50, 10, addr_bits=20) for _ in range(60)]
     print("memory events", sum(t.addr.size for t in trs), flush=True)
     check(trs)
+    check(trs, hint=True)
 
 
 def test_large_values_across_chunks():
