@@ -116,8 +116,13 @@ static aiwc_status stream_start(aiwc_stream *st, const aiwc_trace *t, hipStream_
     ctx_error(ctx, "out of device memory for the stream's opcode table");
     return AIWC_ERR_OUT_OF_MEMORY;
   }
-  ST_HIP_OR(ctx, hipMemcpy(st->proto.dev_info, t->host_info.data(), 4 * ids,
-                           hipMemcpyHostToDevice));
+  if (hipMemcpy(st->proto.dev_info, t->host_info.data(), 4 * ids, hipMemcpyHostToDevice) !=
+      hipSuccess) {
+    hipFree(st->proto.dev_info);
+    st->proto.dev_info = nullptr;
+    ctx_error(ctx, "copying the stream's opcode table failed");
+    return AIWC_ERR_HIP;
+  }
   auto al = [](u64 x) { return (x + 255) & ~255ull; };
   st->o_id = al(sizeof(DevAccum));
   st->o_itb = st->o_id + al(8 * ids);
@@ -125,6 +130,9 @@ static aiwc_status stream_start(aiwc_stream *st, const aiwc_trace *t, hipStream_
   st->core_bytes = st->o_ipt + al(8ull * VAL_DENSE);
   if (hipMalloc(&st->core, st->core_bytes) != hipSuccess) {
     hipGetLastError();
+    hipFree(st->proto.dev_info);
+    st->proto.dev_info = nullptr;
+    st->core = nullptr;
     ctx_error(ctx, "out of device memory for the stream state");
     return AIWC_ERR_OUT_OF_MEMORY;
   }
