@@ -275,6 +275,8 @@ def main() -> int:
                     help="config3 lengths are scaled by this factor")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the branch-entropy variant leg")
+    ap.add_argument("--no-stream", action="store_true",
+                    help="skip the streamed (16 appended chunks) leg")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="one characterization, then a plain device copy of 1 GiB, for "
                          "rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs; prints no JSON")
@@ -341,9 +343,11 @@ def main() -> int:
     tpath = os.path.join(ROOT, "profiles", f"traffic_{dom}_{workload_tag(args.n_wi_log2)}.md")
     trec = read_traffic(tpath, dom, workload_tag(args.n_wi_log2))
 
-    streamed = stream_leg(ctx, dev, spec, n_ev, args, stream, r)
-    print(f"# stream of 16 chunks: {streamed['ms']:.2f} ms, identical "
-          f"{streamed['identical_to_plain']}", file=sys.stderr, flush=True)
+    streamed = None
+    if not args.no_stream:
+        streamed = stream_leg(ctx, dev, spec, n_ev, args, stream, r)
+        print(f"# stream of 16 chunks: {streamed['ms']:.2f} ms, identical "
+              f"{streamed['identical_to_plain']}", file=sys.stderr, flush=True)
 
     variants = None
     if not args.no_variants:
