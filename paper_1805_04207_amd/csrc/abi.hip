@@ -212,13 +212,43 @@ void add_dims(const aiwc_trace *t, const TracePlan &p, const TraceArgs &a, Batch
   }
 }
 
+// The context's side stream, created on first use (default priority,
+// non-blocking so that a caller on the null stream does not serialize it).
+const SideStream *side_stream(aiwc_ctx *ctx) {
+  SideStream &S = ctx->side;
+  if (!S.s) {
+    if (hipStreamCreateWithFlags(&S.s, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&S.fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&S.join, hipEventDisableTiming) != hipSuccess) {
+      hipGetLastError();
+      return nullptr;
+    }
+  }
+  return &S;
+}
+
+// The stages of a characterization.  The memory stage and the instruction +
+// branch stages touch disjoint data (they meet only in k_finalize), so with
+// a side stream the latter run beside the former: the memory kernels are
+// bound by latency and the radix passes need little LDS, so they overlap.
 hipError_t enqueue_stages(const TraceArgs &a, const BatchDims &d, hipStream_t s,
-                          StageMarks *pm) {
+                          StageMarks *pm, const SideStream *side) {
   hipError_t e = aiwc_kernels::launch_zero(a, d, s);
   AIWC_MARK(pm, "k_zero", s);
-  if (e == hipSuccess) e = aiwc_kernels::launch_ops(a, d, s, pm);
+  hipStream_t t = s;
+  if (e == hipSuccess && side) {
+    e = hipEventRecord(side->fork, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(side->s, side->fork, 0);
+    if (pm) pm->fork(s, side->s);
+    t = side->s;
+  }
+  if (e == hipSuccess) e = aiwc_kernels::launch_ops(a, d, t, pm);
+  if (e == hipSuccess) e = aiwc_kernels::launch_branch(a, d, t, pm);
   if (e == hipSuccess) e = aiwc_kernels::launch_mem(a, d, s, pm);
-  if (e == hipSuccess) e = aiwc_kernels::launch_branch(a, d, s, pm);
+  if (e == hipSuccess && side) {
+    e = hipEventRecord(side->join, side->s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, side->join, 0);
+  }
   if (e == hipSuccess) e = aiwc_kernels::launch_finalize(a, d, s, pm);
   return e;
 }
@@ -227,8 +257,17 @@ hipError_t enqueue_stages(const TraceArgs &a, const BatchDims &d, hipStream_t s,
 void Profiler::begin(hipStream_t s) {
   used = 0;
   marks.clear();
+  last.clear();
   if (!start) hipEventCreate(&start);
   hipEventRecord(start, s);
+  last.emplace_back(s, start);
+}
+
+hipEvent_t &Profiler::last_of(hipStream_t s) {
+  for (auto &l : last)
+    if (l.first == s) return l.second;
+  last.emplace_back(s, start);
+  return last.back().second;
 }
 
 void Profiler::mark(const char *name, hipStream_t s) {
@@ -239,7 +278,14 @@ void Profiler::mark(const char *name, hipStream_t s) {
   }
   hipEvent_t e = pool[used++];
   hipEventRecord(e, s);
-  marks.emplace_back(name, e);
+  hipEvent_t &prev = last_of(s);
+  marks.push_back({name, e, prev});
+  prev = e;
+}
+
+void Profiler::fork(hipStream_t from, hipStream_t to) {
+  const hipEvent_t e = last_of(from);
+  last_of(to) = e;
 }
 
 void Profiler::release() {
@@ -263,15 +309,13 @@ extern "C" aiwc_status aiwc_profile_read(aiwc_ctx *ctx, char *names, size_t name
   std::string csv;
   size_t n = 0;
   if (P.start && !P.marks.empty()) {
-    HIP_OR(ctx, hipEventSynchronize(P.marks.back().second));
-    hipEvent_t prev = P.start;
+    for (auto &m : P.marks) HIP_OR(ctx, hipEventSynchronize(m.end));
     for (auto &m : P.marks) {
       float t = 0.f;
-      HIP_OR(ctx, hipEventElapsedTime(&t, prev, m.second));
+      HIP_OR(ctx, hipEventElapsedTime(&t, m.begin, m.end));
       if (n < max_stages && ms) ms[n] = t;
       if (!csv.empty()) csv += ",";
-      csv += m.first;
-      prev = m.second;
+      csv += m.name;
       ++n;
     }
   }
@@ -315,6 +359,9 @@ extern "C" aiwc_status aiwc_context_destroy(aiwc_ctx *ctx) {
   hipDeviceSynchronize();
   if (ctx->arena) hipFree(ctx->arena);
   if (ctx->last_done) hipEventDestroy(ctx->last_done);
+  if (ctx->side.s) hipStreamDestroy(ctx->side.s);
+  if (ctx->side.fork) hipEventDestroy(ctx->side.fork);
+  if (ctx->side.join) hipEventDestroy(ctx->side.join);
   ctx->prof.release();
   sizer_free(ctx);
   batch_free(ctx);
@@ -479,7 +526,7 @@ aiwc_status characterize_planned(aiwc_ctx *ctx, const aiwc_trace *t, u32 pbits,
   if (ctx->prof.on) { ctx->prof.begin(s); pm = &ctx->prof; }
   BatchDims dims;
   add_dims(t, p, a, dims);
-  hipError_t e = enqueue_stages(a, dims, s, pm);
+  hipError_t e = enqueue_stages(a, dims, s, pm, side_stream(ctx));
   if (e != hipSuccess) {
     ctx_error(ctx, "kernel launch failed: %s", hipGetErrorString(e));
     aiwc_metrics_destroy(m);

@@ -40,16 +40,29 @@ struct TracePlan {
 struct SizerState;
 struct BatchState;
 
-// Per-context stage timer (instrumentation; see aiwc_profile_*).
+// Per-context stage timer (instrumentation; see aiwc_profile_*).  A stage's
+// time runs from the previous mark on the same stream to its own mark, so
+// stages on the side stream are timed on their own chain.
 struct Profiler : StageMarks {
   bool on = false;
   hipEvent_t start = nullptr;
-  std::vector<std::pair<std::string, hipEvent_t>> marks;
+  struct Mark { std::string name; hipEvent_t end, begin; };
+  std::vector<Mark> marks;
+  std::vector<std::pair<hipStream_t, hipEvent_t>> last;   // latest mark per stream
   std::vector<hipEvent_t> pool;
   size_t used = 0;
   void begin(hipStream_t s);
   void mark(const char *name, hipStream_t s) override;
+  void fork(hipStream_t from, hipStream_t to) override;
   void release();
+  hipEvent_t &last_of(hipStream_t s);
+};
+
+// A second stream of the context: the instruction and branch stages run on
+// it, beside the memory stage, between a fork and a join event.
+struct SideStream {
+  hipStream_t s = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
 };
 
 struct aiwc_ctx {
@@ -64,6 +77,7 @@ struct aiwc_ctx {
   BatchState *batch = nullptr;
   aiwc_batch_stats last_stats{};
   Profiler prof;
+  SideStream side;
   std::vector<std::pair<std::string, Tune>> tune_cache;  // class key -> best shape
   bool tune_loaded = false;
 };
@@ -99,7 +113,8 @@ u32 bound_pbits(u64 n_mem);
 void fill_args(const aiwc_trace *t, const TracePlan &p, char *scratch, char *result,
                TraceArgs &a);
 hipError_t enqueue_stages(const TraceArgs &a, const BatchDims &d, hipStream_t s,
-                          StageMarks *pm);
+                          StageMarks *pm, const SideStream *side = nullptr);
+const SideStream *side_stream(aiwc_ctx *ctx);
 void add_dims(const aiwc_trace *t, const TracePlan &p, const TraceArgs &a, BatchDims &d);
 aiwc_status ensure_arena(aiwc_ctx *ctx, u64 bytes);
 aiwc_status new_metrics(aiwc_ctx *ctx, const aiwc_trace *t, const TracePlan &p,

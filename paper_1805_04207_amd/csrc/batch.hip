@@ -232,7 +232,8 @@ extern "C" aiwc_status aiwc_characterize_batch(aiwc_ctx *ctx, const aiwc_trace *
       }
       if (hipGraphLaunch(w.exec, s) != hipSuccess) { ctx_error(ctx, "hipGraphLaunch failed"); return AIWC_ERR_HIP; }
     } else {
-      hipError_t e = enqueue_stages(dummy, w.dims, s, ctx->prof.on ? &ctx->prof : nullptr);
+      hipError_t e = enqueue_stages(dummy, w.dims, s, ctx->prof.on ? &ctx->prof : nullptr,
+                                    side_stream(ctx));
       if (e != hipSuccess) { ctx_error(ctx, "batch launch failed: %s", hipGetErrorString(e)); return AIWC_ERR_HIP; }
     }
     // this wave's results into the call's block (the stable region is

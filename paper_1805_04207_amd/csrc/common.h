@@ -189,6 +189,7 @@ __device__ __forceinline__ u32 hash_slot(u64 key, u32 cap) {
 // after every kernel launch, tagged with the kernel's name.
 struct StageMarks {
   virtual void mark(const char *name, hipStream_t s) = 0;
+  virtual void fork(hipStream_t from, hipStream_t to) = 0;   // `to` continues from `from`
   virtual ~StageMarks() {}
 };
 
