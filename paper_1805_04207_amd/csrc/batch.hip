@@ -222,7 +222,9 @@ extern "C" aiwc_status aiwc_characterize_batch(aiwc_ctx *ctx, const aiwc_trace *
           ctx_error(ctx, "hipStreamBeginCapture failed");
           return AIWC_ERR_HIP;
         }
-        hipError_t e = enqueue_stages(dummy, w.dims, B.cap_stream, nullptr);
+        // the side stream joins the capture through the fork event and
+        // leaves it through the join event, so the graph holds both chains
+        hipError_t e = enqueue_stages(dummy, w.dims, B.cap_stream, nullptr, side_stream(ctx));
         hipError_t e2 = hipStreamEndCapture(B.cap_stream, &w.graph);
         if (e != hipSuccess || e2 != hipSuccess ||
             hipGraphInstantiate(&w.exec, w.graph, nullptr, nullptr, 0) != hipSuccess) {
