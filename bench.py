@@ -29,7 +29,8 @@ def workload_tag(n_wi_log2: int) -> str:
 
 
 def algorithmic_bytes(name: str, n_ev: int, n_wi: int, n_mem: int, n_br: int, passes: int) -> float:
-    """Bytes each kernel must move for one trace (documented in the design doc)."""
+    """Bytes each kernel must move for one trace: its compulsory reads and
+    writes per event, memory event, branch event and work-item."""
     return {
         "k_ops": 2.0 * n_ev + 8.0 * (n_wi + 1),
         "k_mem_hist": 9.0 * n_mem,
@@ -279,7 +280,7 @@ def main() -> int:
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the multi-GPU sharding "
-                                   "is a design (see DESIGN.md), not a launched path"}))
+                                   "is a design, not a launched path"}))
         return 2
 
     import numpy as np
