@@ -213,6 +213,7 @@ extern "C" aiwc_status aiwc_characterize_batch(aiwc_ctx *ctx, const aiwc_trace *
   if (ctx->last_done) hipStreamWaitEvent(s, ctx->last_done, 0);
   TraceArgs dummy;
   memset(&dummy, 0, sizeof dummy);
+  if (ctx->prof.on && !graph) ctx->prof.begin(s);   // stage marks of this call only
   for (Wave &w : B.waves) {
     if (graph) {
       if (!w.exec) {
