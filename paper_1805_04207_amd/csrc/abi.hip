@@ -242,7 +242,15 @@ hipError_t enqueue_stages(const TraceArgs &a, const BatchDims &d, hipStream_t s,
     if (pm) pm->fork(s, side->s);
     t = side->s;
   }
-  if (e == hipSuccess) e = aiwc_kernels::launch_ops(a, d, t, pm);
+  if (side) {
+    // two ops blocks per CU (13 KiB of LDS each) leave room for a partition
+    // histogram or scatter block (128 KiB) beside them
+    BatchDims ds = d;
+    ds.ops_max_blocks = 512;
+    if (e == hipSuccess) e = aiwc_kernels::launch_ops(a, ds, t, pm);
+  } else if (e == hipSuccess) {
+    e = aiwc_kernels::launch_ops(a, d, t, pm);
+  }
   if (e == hipSuccess) e = aiwc_kernels::launch_branch(a, d, t, pm);
   if (e == hipSuccess) e = aiwc_kernels::launch_mem(a, d, s, pm);
   if (e == hipSuccess && side) {

@@ -202,6 +202,7 @@ struct BatchDims {
   u64 max_br_blocks = 0, max_scan_blocks = 0, max_zero16 = 0;
   u32 max_ids = 0, max_passes = 0;
   u64 ops_lds = 0;                    // dynamic LDS of the ops kernel (max over traces)
+  u32 ops_max_blocks = 0;             // cap on the ops grid (0 = none)
   bool any_mem = false, any_branch = false;
   bool any_local = false, any_global = false;   // branch history variants present
   bool any_pattern = false;                     // some trace wants the pattern entropy

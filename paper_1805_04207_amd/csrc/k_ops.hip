@@ -22,7 +22,9 @@ namespace {
 
 constexpr int OPS_BLOCK = 256;
 constexpr int OPS_WAVES = OPS_BLOCK / AIWC_WAVE;
-constexpr u32 LDS_VALS = 4096;   // ITB / IPT values below this counted in LDS
+constexpr u32 LDS_VALS = 1024;   // ITB / IPT values below this counted in LDS
+                                  // (13 KiB per block: two fit beside a 128 KiB
+                                  // partition-histogram block)
 constexpr u32 KIND_BARRIER = AIWC_KIND_BARRIER;
 
 __device__ __forceinline__ u64 lower_bound(const u64 *a, u64 n, u64 x) {
@@ -285,6 +287,7 @@ hipError_t launch_ops(const TraceArgs &a, const BatchDims &d, hipStream_t s, Sta
   if (d.max_ops_tasks == 0) return hipSuccess;
   u64 waves = d.max_ops_tasks < 4096 ? d.max_ops_tasks : 4096;
   unsigned gx = (unsigned)((waves + OPS_WAVES - 1) / OPS_WAVES);
+  if (d.ops_max_blocks && gx > d.ops_max_blocks) gx = d.ops_max_blocks;
   size_t tail = OPS_WAVES * sizeof(WaveStats) + 2 * LDS_VALS * 4;
   const dim3 g(gx, d.n), blk(OPS_BLOCK);
   const TraceArgs *b = d.batch;
