@@ -12,14 +12,12 @@ namespace {
 constexpr int FB = 512;
 
 constexpr u32 SPEC_LDS = 4096;   // spectrum pairs compacted into LDS
-constexpr u32 GROUPS = VAL_DENSE / AIWC_WAVE;   // 64-bin groups of a value histogram
 
 struct FinShared {
   u64 red[FB / AIWC_WAVE];
   u64 red2[FB / AIWC_WAVE];
   u64 bcast[4];
   u64 cf[SPEC_LDS], cm[SPEC_LDS];  // compacted (f, m_f) pairs of one space
-  u64 gsum[GROUPS];                // group sums of the value histogram being searched
   u32 nc;
 };
 
@@ -89,70 +87,40 @@ __device__ u64 coverage90(u64 n_items, u64 total, Get get, FinShared &S) {
   return above_n + (u64)((need + per - 1) / per);
 }
 
-// Sums of the 64-bin groups of a value histogram into S.gsum, one coalesced
-// wavefront load per group; returns their total.
-__device__ u64 group_sums(const u64 *hist, FinShared &S) {
-  const int lane = lane_id(), wave = threadIdx.x / AIWC_WAVE;
-  for (u32 g = wave; g < GROUPS; g += FB / AIWC_WAVE) {
-    const u64 v = wave_sum_u64(hist[(u64)g * AIWC_WAVE + lane]);
-    if (lane == 0) S.gsum[g] = v;
+// k-th smallest (0-based) value of the sample held as a dense histogram of
+// values < VAL_DENSE plus a list of the larger values.
+__device__ u64 select_kth(const u64 *hist, const u64 *large, u64 n_large, u64 k, FinShared &S) {
+  constexpr int PER = VAL_DENSE / FB;  // 64 bins per thread
+  u64 mine = 0;
+  const u64 b0 = (u64)threadIdx.x * PER;
+  for (int j = 0; j < PER; ++j) mine += hist[b0 + j];
+  // exclusive prefix of 'mine' over threads
+  u64 x = mine;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    u64 y = __shfl_up(x, o, 64);
+    if (lane_id() >= o) x += y;
   }
   __syncthreads();
-  u64 t = 0;
-  for (u32 g = threadIdx.x; g < GROUPS; g += FB) t += S.gsum[g];
-  return block_sum(t, S);
-}
-
-// k-th smallest (0-based) value of the sample held as a dense histogram of
-// values < VAL_DENSE (group sums in S.gsum, dense_total of them) plus a list
-// of the larger values.
-__device__ u64 select_kth(const u64 *hist, u64 dense_total, const u64 *large, u64 n_large, u64 k,
-                          FinShared &S) {
+  if (lane_id() == 63) S.red2[threadIdx.x / AIWC_WAVE] = x;
+  if (threadIdx.x == 0) S.bcast[0] = ~0ull;
+  __syncthreads();
+  u64 before = 0, dense_total = 0;
+  for (int w = 0; w < FB / AIWC_WAVE; ++w) {
+    if (w < (int)(threadIdx.x / AIWC_WAVE)) before += S.red2[w];
+    dense_total += S.red2[w];
+  }
+  before += x - mine;
   if (k < dense_total) {
-    // the group holding rank k: prefix over the group sums, two per thread
-    constexpr int PER = GROUPS / FB;
-    const u32 g0 = threadIdx.x * PER;
-    u64 mine = 0;
-    for (int j = 0; j < PER; ++j) mine += S.gsum[g0 + j];
-    u64 x = mine;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      u64 y = __shfl_up(x, o, 64);
-      if (lane_id() >= o) x += y;
-    }
-    __syncthreads();
-    if (lane_id() == 63) S.red2[threadIdx.x / AIWC_WAVE] = x;
-    __syncthreads();
-    u64 before = x - mine;
-    for (int w = 0; w < (int)(threadIdx.x / AIWC_WAVE); ++w) before += S.red2[w];
     if (k >= before && k < before + mine) {
       u64 c = before;
       for (int j = 0; j < PER; ++j) {
-        const u64 gs = S.gsum[g0 + j];
-        if (k < c + gs) { S.bcast[0] = g0 + j; S.bcast[3] = c; break; }
-        c += gs;
+        c += hist[b0 + j];
+        if (k < c) { S.bcast[0] = b0 + j; break; }
       }
     }
     __syncthreads();
-    // within the group: one wavefront scans its 64 bins
-    if (threadIdx.x < AIWC_WAVE) {
-      const u64 g = S.bcast[0], c0 = S.bcast[3];
-      const int lane = lane_id();
-      const u64 v = hist[g * AIWC_WAVE + lane];
-      u64 incl = v;
-#pragma unroll
-      for (int o = 1; o < 64; o <<= 1) {
-        u64 y = __shfl_up(incl, o, 64);
-        if (lane >= o) incl += y;
-      }
-      incl += c0;
-      const u64 bin = g * AIWC_WAVE + lane;
-      if (k >= incl - v && k < incl) S.bcast[2] = bin;
-    }
-    __syncthreads();
-    const u64 r = S.bcast[2];
-    __syncthreads();
-    return r;
+    return S.bcast[0];
   }
   __syncthreads();
   // among the large values: smallest v with #{x <= v} > k'
@@ -173,10 +141,9 @@ __device__ u64 select_kth(const u64 *hist, u64 dense_total, const u64 *large, u6
 __device__ double median_of(const u64 *hist, const u64 *large, u64 n_large, u64 count,
                             FinShared &S) {
   if (count == 0) return 0.0;
-  const u64 dense = group_sums(hist, S);
-  if (count & 1) return (double)select_kth(hist, dense, large, n_large, count / 2, S);
-  const u64 a = select_kth(hist, dense, large, n_large, count / 2 - 1, S);
-  const u64 b = select_kth(hist, dense, large, n_large, count / 2, S);
+  if (count & 1) return (double)select_kth(hist, large, n_large, count / 2, S);
+  const u64 a = select_kth(hist, large, n_large, count / 2 - 1, S);
+  const u64 b = select_kth(hist, large, n_large, count / 2, S);
   return ((double)a + (double)b) * 0.5;
 }
 
