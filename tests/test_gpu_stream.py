@@ -124,3 +124,26 @@ def test_stream_errors():
     with pytest.raises(aiwc.AiwcError):
         st.finish()
     st.close()
+
+
+def test_appends_interleaved_with_other_work():
+    # the context's scratch arena serves other calls between the appends
+    # (and the finish reuses it): the stream's state is its own
+    import paper_1805_04207_amd as aiwc
+    from gpu_util import ctx, run
+    c = ctx()
+    rng = np.random.default_rng(61)
+    trs = [random_trace(rng, 10, 2000, 30, 8, addr_bits=18) for _ in range(3)]
+    other = random_trace(rng, 20, 3000, 50, 8, addr_bits=24)
+    st = c.stream()
+    keep = []
+    for t in trs:
+        dev = aiwc.host_to_device(t, 0)
+        h = aiwc.device_trace(c, dev, t.table, int(t.n_sites), 8)
+        keep += [dev, h]
+        st.append(h)
+        got_other = run(other)[0]
+        assert not compare(got_other, oracle.characterize(other))
+    got = st.finish().read()
+    bad = compare(got, oracle.characterize(oracle.MergedTrace(trs)))
+    assert not bad, "\n".join(bad[:20])
