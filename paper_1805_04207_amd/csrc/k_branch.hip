@@ -40,7 +40,7 @@ constexpr int BR_BLOCK = 256;
 constexpr int BR_TILE = 4096;                 // elements per radix tile
 constexpr int BR_ROUNDS = BR_TILE / BR_BLOCK; // 16
 constexpr int WIN_BLOCK = 1024;
-constexpr u64 WIN_T = 4096;                   // windows work-block size
+constexpr u64 WIN_T = 8192;                   // windows work-block size
 constexpr u32 WT_C = 8192;                    // LDS table slots
 constexpr u32 WT_CAP = 4096;
 constexpr u64 EMPTY = ~0ull;
