@@ -207,7 +207,18 @@ def stream_leg(ctx, dev, spec, n_ev, args, stream, ref):
         got = one()
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
+    # the same with the retained streams held in pinned host memory (their
+    # trip over PCIe and back included)
+    st = ctx.stream(dev["n_mem"], dev["n_branch"], host_retain=True)
+    t0 = time.perf_counter()
+    for c in chunks:
+        st.append(c, stream)
+    got_h = st.finish(stream).read()
+    torch.cuda.synchronize()
+    dt_h = time.perf_counter() - t0
+    st.close()
     return {"chunks": k, "ms": 1e3 * dt, "events_per_s": n_ev / dt,
+            "host_retained_ms": 1e3 * dt_h, "host_retained_identical": strip(got_h) == strip(ref),
             "retained_bytes": 9 * dev["n_mem"] + 5 * dev["n_branch"],
             "input_bytes": 2 * n_ev + 8 * (spec.n_wi + 1) + 9 * dev["n_mem"] + 5 * dev["n_branch"],
             "identical_to_plain": strip(got) == strip(ref)}

@@ -304,13 +304,23 @@ aiwc_status aiwc_characterize_merged(aiwc_ctx *ctx, const aiwc_trace *const *tra
  * event, 5 B per branch event), which finish reduces with the ordinary
  * memory and branch stages.                                                 */
 typedef struct aiwc_stream aiwc_stream;
+/* stream flags */
+enum {
+  AIWC_STREAM_HOST_RETAIN = 1u  /* keep the retained memory and branch streams
+                                   in pinned host memory until finish (the
+                                   paper's remedy for the footprint: keep
+                                   the recorded traces out of the working
+                                   memory); finish copies them to the device
+                                   once.  Appends then hold only the
+                                   instruction-stream state on the device.  */
+};
 /* An empty stream of this context.  mem_hint / branch_hint: expected total
  * memory and branch events (0 = unknown); the retained buffers are reserved
  * for them up front and otherwise grow by doubling (each move copies what
- * is held and synchronizes the stream).  Errors: INVALID_ARG (null),
- * OUT_OF_MEMORY.                                                            */
+ * is held and synchronizes the stream).  flags: AIWC_STREAM_*.
+ * Errors: INVALID_ARG (null, unknown flags), OUT_OF_MEMORY.                 */
 aiwc_status aiwc_stream_create(aiwc_ctx *ctx, uint64_t mem_hint, uint64_t branch_hint,
-                               aiwc_stream **out);
+                               uint32_t flags, aiwc_stream **out);
 /* Append one chunk, a trace handle of the stream's context.  The first
  * chunk fixes the opcode table, history_len and branch flags; later chunks
  * must match.  Asynchronous on `stream`: the chunk's device arrays are read
@@ -320,7 +330,9 @@ aiwc_status aiwc_stream_create(aiwc_ctx *ctx, uint64_t mem_hint, uint64_t branch
  * reaching 2^32), OUT_OF_MEMORY, HIP.                                       */
 aiwc_status aiwc_stream_append(aiwc_stream *st, const aiwc_trace *chunk, void *stream);
 /* Reduce everything appended and return its metrics handle (as
- * aiwc_characterize does); the stream then takes no more chunks.  The
+ * aiwc_characterize does); the stream then takes no more chunks.  Call it on
+ * the stream the appends used (or synchronize that stream first): the
+ * retained copies are ordered only on it.  The
  * stream must outlive the returned handle's work (aiwc_stream_destroy
  * waits for the device).  Errors: INVALID_ARG (null, nothing appended,
  * already finished), OUT_OF_MEMORY, HIP.                                    */

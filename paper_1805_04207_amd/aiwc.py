@@ -17,6 +17,7 @@ AIWC_OK, AIWC_ERR_INVALID_ARG, AIWC_ERR_INCONSISTENT = 0, 1, 2
 AIWC_ERR_OUT_OF_MEMORY, AIWC_ERR_HIP, AIWC_ERR_UNSUPPORTED = 3, 4, 5
 AIWC_VALIDATE_ON_DEVICE = 1
 BRANCH_ZERO_HISTORY, BRANCH_GLOBAL_HISTORY, BRANCH_PATTERN_ENTROPY = 2, 4, 8
+STREAM_HOST_RETAIN = 1
 SIZING_BOUND, SIZING_HEURISTIC, SIZING_LEARNED = 0, 1, 2
 AUTOTUNE_OFF, AUTOTUNE_CACHED, AUTOTUNE_SEARCH = 0, 1, 2
 N_FEATURES, N_TARGETS = 40, 11
@@ -134,7 +135,7 @@ def load_library(path: str = LIB_PATH):
         "aiwc_trace_destroy": (st, [vp]),
         "aiwc_characterize": (st, [vp, vp, vp, ctypes.POINTER(vp)]),
         "aiwc_characterize_merged": (st, [vp, ctypes.POINTER(vp), sz, vp, ctypes.POINTER(vp)]),
-        "aiwc_stream_create": (st, [vp, u64, u64, ctypes.POINTER(vp)]),
+        "aiwc_stream_create": (st, [vp, u64, u64, ctypes.c_uint32, ctypes.POINTER(vp)]),
         "aiwc_stream_append": (st, [vp, vp, vp]),
         "aiwc_stream_finish": (st, [vp, vp, ctypes.POINTER(vp)]),
         "aiwc_stream_destroy": (st, [vp]),
@@ -232,10 +233,12 @@ class Context:
                                                      ctypes.byref(m)))
         return Metrics(self, m)
 
-    def stream(self, mem_hint: int = 0, branch_hint: int = 0) -> "Stream":
+    def stream(self, mem_hint: int = 0, branch_hint: int = 0,
+               host_retain: bool = False) -> "Stream":
         """A trace that arrives in chunks (aiwc_stream_*); the hints reserve
-        the retained buffers for that many memory / branch events."""
-        return Stream(self, mem_hint, branch_hint)
+        the retained buffers for that many memory / branch events; with
+        host_retain they are kept in pinned host memory until finish."""
+        return Stream(self, mem_hint, branch_hint, STREAM_HOST_RETAIN if host_retain else 0)
 
     def characterize_batch(self, traces: Sequence["Trace"], sizing: int = SIZING_BOUND,
                            autotune: int = AUTOTUNE_OFF, use_graph: bool = False,
@@ -335,11 +338,12 @@ class Stream:
     chunks' tensors are kept referenced until the stream is closed, since
     the appends read them asynchronously."""
 
-    def __init__(self, ctx: "Context", mem_hint: int = 0, branch_hint: int = 0):
+    def __init__(self, ctx: "Context", mem_hint: int = 0, branch_hint: int = 0, flags: int = 0):
         self.ctx = ctx
         self.h = ctypes.c_void_p()
         self._keep = []
-        ctx.check(ctx.lib.aiwc_stream_create(ctx.h, mem_hint, branch_hint, ctypes.byref(self.h)))
+        ctx.check(ctx.lib.aiwc_stream_create(ctx.h, mem_hint, branch_hint, flags,
+                                             ctypes.byref(self.h)))
 
     def append(self, chunk: "Trace", stream=None):
         self._keep.append(chunk)

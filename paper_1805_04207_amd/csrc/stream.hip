@@ -27,25 +27,39 @@
 
 namespace {
 
-// A device buffer that grows by doubling; `used` bytes survive a move.
+// A buffer that grows by doubling; `used` bytes survive a move.  It lives in
+// device memory, or in pinned host memory for a stream that keeps its
+// retained streams off the device until finish.
 struct GrowBuf {
   char *p = nullptr;
   u64 cap = 0, used = 0;
+  bool host = false;
 };
+
+void release(GrowBuf &b) {
+  if (b.p) { if (b.host) hipHostFree(b.p); else hipFree(b.p); }
+  b.p = nullptr;
+  b.cap = b.used = 0;
+}
 
 aiwc_status grow(aiwc_ctx *ctx, GrowBuf &b, u64 need, hipStream_t s) {
   if (need <= b.cap) return AIWC_OK;
   const u64 nc = std::max<u64>(need, std::max<u64>(2 * b.cap, 1ull << 16));
   char *np = nullptr;
-  if (hipMalloc(&np, nc) != hipSuccess) {
+  const hipError_t e = b.host ? hipHostMalloc((void **)&np, nc, hipHostMallocDefault)
+                              : hipMalloc((void **)&np, nc);
+  if (e != hipSuccess) {
     hipGetLastError();
-    ctx_error(ctx, "out of device memory: a stream buffer of %llu bytes", (unsigned long long)nc);
+    ctx_error(ctx, "out of %s memory: a stream buffer of %llu bytes", b.host ? "pinned host" : "device",
+              (unsigned long long)nc);
     return AIWC_ERR_OUT_OF_MEMORY;
   }
   if (b.p) {
-    if (b.used) ST_HIP_OR(ctx, hipMemcpyAsync(np, b.p, b.used, hipMemcpyDeviceToDevice, s));
+    if (b.used) ST_HIP_OR(ctx, hipMemcpyAsync(np, b.p, b.used, hipMemcpyDefault, s));
     ST_HIP_OR(ctx, hipStreamSynchronize(s));
-    hipFree(b.p);
+    const u64 used = b.used;
+    release(b);
+    b.used = used;
   }
   b.p = np;
   b.cap = nc;
@@ -56,7 +70,7 @@ aiwc_status append_bytes(aiwc_ctx *ctx, GrowBuf &b, const void *src, u64 bytes, 
   if (!bytes) return AIWC_OK;
   aiwc_status st = grow(ctx, b, b.used + bytes, s);
   if (st != AIWC_OK) return st;
-  ST_HIP_OR(ctx, hipMemcpyAsync(b.p + b.used, src, bytes, hipMemcpyDeviceToDevice, s));
+  ST_HIP_OR(ctx, hipMemcpyAsync(b.p + b.used, src, bytes, hipMemcpyDefault, s));
   b.used += bytes;
   return AIWC_OK;
 }
@@ -77,16 +91,23 @@ struct aiwc_stream {
   u64 o_id = 0, o_itb = 0, o_ipt = 0, core_bytes = 0;
   GrowBuf itb_large, ipt_large;     // values >= VAL_DENSE, 8 B each
   GrowBuf addr, kind, site, taken;  // retained memory and branch streams
+  GrowBuf staged;                   // device copy of host-held streams at finish
 };
 
 extern "C" aiwc_status aiwc_stream_destroy(aiwc_stream *st);
 
 extern "C" aiwc_status aiwc_stream_create(aiwc_ctx *ctx, uint64_t mem_hint, uint64_t branch_hint,
-                                          aiwc_stream **out) {
+                                          uint32_t flags, aiwc_stream **out) {
   if (!ctx || !out) { ctx_error(ctx, "aiwc_stream_create: NULL argument"); return AIWC_ERR_INVALID_ARG; }
+  if (flags & ~(u32)AIWC_STREAM_HOST_RETAIN) {
+    ctx_error(ctx, "aiwc_stream_create: unknown flag bits 0x%x", flags);
+    return AIWC_ERR_INVALID_ARG;
+  }
   ST_HIP_OR(ctx, hipSetDevice(ctx->device));
   aiwc_stream *st = new aiwc_stream();
   st->ctx = ctx;
+  const bool host = (flags & AIWC_STREAM_HOST_RETAIN) != 0;
+  st->addr.host = st->kind.host = st->site.host = st->taken.host = host;
   const u64 mh = std::min<u64>(mem_hint, 1ull << 32), bh = std::min<u64>(branch_hint, 1ull << 32);
   aiwc_status rc = AIWC_OK;
   if (mh && rc == AIWC_OK) rc = grow(ctx, st->addr, 8 * mh, nullptr);
@@ -240,6 +261,24 @@ extern "C" aiwc_status aiwc_stream_finish(aiwc_stream *st, void *stream, aiwc_me
   mt.d.n_branch = st->taken.used;
   mt.d.br_site = (const uint32_t *)st->site.p;
   mt.d.br_taken = (const uint8_t *)st->taken.p;
+  if (st->addr.host) {
+    // the retained streams come onto the device now, 256-byte aligned
+    auto al = [](u64 x) { return (x + 255) & ~255ull; };
+    const u64 o_kind = al(st->addr.used), o_site = o_kind + al(st->kind.used);
+    const u64 o_taken = o_site + al(st->site.used), total = o_taken + al(st->taken.used);
+    aiwc_status rc0 = grow(ctx, st->staged, total, s);
+    if (rc0 != AIWC_OK) return rc0;
+    char *b = st->staged.p;
+    const GrowBuf *src[4] = {&st->addr, &st->kind, &st->site, &st->taken};
+    const u64 off[4] = {0, o_kind, o_site, o_taken};
+    for (int i = 0; i < 4; ++i)
+      if (src[i]->used)
+        ST_HIP_OR(ctx, hipMemcpyAsync(b + off[i], src[i]->p, src[i]->used, hipMemcpyHostToDevice, s));
+    mt.d.addr = (const uint64_t *)b;
+    mt.d.mem_kind = (const uint8_t *)(b + o_kind);
+    mt.d.br_site = (const uint32_t *)(b + o_site);
+    mt.d.br_taken = (const uint8_t *)(b + o_taken);
+  }
   mt.d.n_sites = st->n_sites;
   mt.n_classes = st->proto.n_classes;
   mt.dev_info = st->proto.dev_info;
@@ -280,8 +319,9 @@ extern "C" aiwc_status aiwc_stream_destroy(aiwc_stream *st) {
   if (!st) return AIWC_OK;
   hipSetDevice(st->ctx->device);
   hipDeviceSynchronize();
-  for (GrowBuf *b : {&st->itb_large, &st->ipt_large, &st->addr, &st->kind, &st->site, &st->taken})
-    if (b->p) hipFree(b->p);
+  for (GrowBuf *b : {&st->itb_large, &st->ipt_large, &st->addr, &st->kind, &st->site, &st->taken,
+                     &st->staged})
+    release(*b);
   if (st->core) hipFree(st->core);
   if (st->proto.dev_info) hipFree(st->proto.dev_info);
   delete st;

@@ -336,3 +336,15 @@ def test_stream_of_the_large_trace():
     got = st.finish().read()
     assert same(got, plain), "stream of 16 chunks differs from the whole"
     log("stream of 16 chunks identical to the plain path on the whole")
+    st.close()
+    st = ctx.stream(host_retain=True)
+    for i in range(k):
+        p = {"opcode": d["opcode"][ecut[i]:ecut[i + 1]],
+             "wi_offsets": (off[wcut[i]:wcut[i + 1] + 1] - off[wcut[i]]).contiguous(),
+             "addr": d["addr"][mcut[i]:mcut[i + 1]], "mem_kind": d["mem_kind"][mcut[i]:mcut[i + 1]],
+             "br_site": d["br_site"][bcut[i]:bcut[i + 1]],
+             "br_taken": d["br_taken"][bcut[i]:bcut[i + 1]]}
+        st.append(aiwc.device_trace(ctx, p, tab, spec.n_sites, spec.history_len, spec.wg_size))
+    got = st.finish().read()
+    assert same(got, plain), "host-retained stream differs from the whole"
+    log("host-retained stream identical to the plain path on the whole")

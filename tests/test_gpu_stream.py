@@ -11,12 +11,12 @@ from helpers import mk, random_trace
 pytestmark = pytest.mark.gpu
 
 
-def stream_of(trs, hint=False):
+def stream_of(trs, hint=False, host=False):
     import paper_1805_04207_amd as aiwc
     from gpu_util import ctx
     c = ctx()
-    st = c.stream(sum(t.addr.size for t in trs), sum(t.br_site.size for t in trs)) if hint \
-        else c.stream()
+    st = c.stream(sum(t.addr.size for t in trs), sum(t.br_site.size for t in trs),
+                  host_retain=host) if hint else c.stream(host_retain=host)
     keep = []
     for tr in trs:
         dev = aiwc.host_to_device(tr, 0)
@@ -29,9 +29,9 @@ def stream_of(trs, hint=False):
     return c, m, keep
 
 
-def check(trs, hint=False):
+def check(trs, hint=False, host=False):
     from gpu_util import same
-    c, m, keep = stream_of(trs, hint)
+    c, m, keep = stream_of(trs, hint, host)
     got = m.read()
     mt = oracle.MergedTrace(trs)
     bad = compare(got, oracle.characterize(mt))
@@ -147,3 +147,12 @@ def test_appends_interleaved_with_other_work():
     got = st.finish().read()
     bad = compare(got, oracle.characterize(oracle.MergedTrace(trs)))
     assert not bad, "\n".join(bad[:20])
+
+
+@pytest.mark.parametrize("hint", [False, True])
+def test_streams_retained_in_host_memory(hint):
+    # the memory and branch streams kept in pinned host memory until finish
+    rng = np.random.default_rng(83)
+    trs = [random_trace(rng, 8, 2000, 40, 12, addr_bits=22) for _ in range(40)]
+    trs[3] = mk(np.zeros(0, dtype=np.uint16), [], m=12)
+    check(trs, hint=hint, host=True)
