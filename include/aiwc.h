@@ -387,7 +387,11 @@ typedef struct aiwc_batch_stats {
 aiwc_status aiwc_batch_last_stats(const aiwc_ctx *ctx, aiwc_batch_stats *out);
 
 /* Wait for the metrics' work and copy the result to the host (one D2H copy).
- * Errors: INVALID_ARG (null), INCONSISTENT (see aiwc_trace_create), HIP.    */
+ * Errors: INVALID_ARG (null, or trace content found invalid on the device:
+ * opcode ids >= n_opcode_ids, sites >= n_sites, outcomes > 1),
+ * INCONSISTENT (see aiwc_trace_create), UNSUPPORTED (an internal capacity
+ * limit: an on-chip table round could not be split further by hash bits, so
+ * the metrics would be incomplete; not a fault of the trace), HIP.          */
 aiwc_status aiwc_metrics_read(aiwc_metrics *m, aiwc_metrics_host *out);
 /* Per-class instruction counts (index = op_class), len entries (host).     */
 aiwc_status aiwc_metrics_class_hist(aiwc_metrics *m, uint64_t *out, size_t len);
@@ -412,8 +416,11 @@ aiwc_status aiwc_profile_read(aiwc_ctx *ctx, char *names, size_t names_cap,
 /* ----------------------------------------------------- learned sizing (MLP)
  * A 40 -> 64 -> 64 -> 64 -> 11 perceptron (exact-erf GELU, bf16 weights,
  * fp32 accumulation) predicts log2 of the global-space distinct counts at
- * skips 0..10 from features of a 65,536-event prefix.  The predictions size
- * the memory partitions; overflow is redone, so results never depend on them.
+ * skips 0..10 from 40 features of the trace's first 8,192 memory events
+ * (exact prefix distinct counts per space and skip, the growth of the
+ * distinct count over the prefix, spans, alignment and locality fractions,
+ * and the trace's sizes).  The predictions size the memory partitions;
+ * overflow is redone, so results never depend on them.
  */
 #define AIWC_N_FEATURES 40
 #define AIWC_N_TARGETS 11

@@ -87,6 +87,7 @@ def _load():
             build()
         L = ctypes.CDLL(LIB)
         L.orc_characterize.argtypes = [ctypes.POINTER(OrcTrace), ctypes.POINTER(OrcResult)]
+        L.orc_kinds_consistent.argtypes = [ctypes.POINTER(OrcTrace)]
         L.orc_class_hist.argtypes = [ctypes.POINTER(OrcTrace), ctypes.c_void_p, ctypes.c_size_t]
         L.orc_spectrum.argtypes = [ctypes.POINTER(OrcTrace), ctypes.c_int, ctypes.c_int,
                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
@@ -200,6 +201,17 @@ def characterize(tr) -> Dict:
     if rc != 0:
         raise ValueError(f"oracle rejected the trace (rc={rc})")
     return _struct_to_dict(r)
+
+
+def consistent(tr) -> bool:
+    """Whether the opcode kinds announce the trace's memory and branch events
+    (an atomic read-modify-write is one instruction with two memory events)."""
+    L = _load()
+    b = _Bound(tr)
+    rc = L.orc_kinds_consistent(ctypes.byref(b.t))
+    if rc < 0:
+        raise ValueError("oracle rejected the trace")
+    return rc == 1
 
 
 def class_hist(tr, n_classes: int) -> np.ndarray:

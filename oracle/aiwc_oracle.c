@@ -377,6 +377,28 @@ int orc_characterize(const orc_trace *t, orc_result *out) {
   return rc;
 }
 
+/* Whether the opcode kinds announce exactly the memory and branch events the
+ * trace carries.  The plugin interface of the Implementation section has
+ * separate callbacks for plain loads and stores and for the load and the
+ * store of an atomic; reading: an atomic read-modify-write instruction is
+ * one instruction with two memory events, a read and a write of one
+ * address.  So #LOAD + #STORE + 2 #ATOMIC must equal the memory events and
+ * #BRANCH_COND the branch events.  1 = consistent, 0 = not, -1 = invalid.  */
+int orc_kinds_consistent(const orc_trace *t) {
+  if (check_trace(t)) return -1;
+  uint64_t loads = 0, stores = 0, atomics = 0, branches = 0;
+  for (uint64_t e = 0; e < t->n_events; ++e) {
+    switch (t->table[t->opcode[e]].kind) {
+      case K_LOAD: ++loads; break;
+      case K_STORE: ++stores; break;
+      case K_ATOMIC: ++atomics; break;
+      case K_BRANCH: ++branches; break;
+      default: break;
+    }
+  }
+  return (loads + stores + 2 * atomics == t->n_mem && branches == t->n_branch) ? 1 : 0;
+}
+
 int orc_class_hist(const orc_trace *t, uint64_t *out, size_t len) {
   if (!out || check_trace(t)) return 1;
   memset(out, 0, len * sizeof(uint64_t));

@@ -83,6 +83,10 @@ typedef struct orc_result {
 
 /* 0 = ok, 1 = invalid trace, 2 = out of memory */
 int orc_characterize(const orc_trace *t, orc_result *out);
+/* 1 when #LOAD + #STORE + 2 #ATOMIC_RMW == n_mem and #BRANCH_COND ==
+ * n_branch (an atomic is one instruction with a read and a write event),
+ * 0 when not, -1 for an invalid trace.                                      */
+int orc_kinds_consistent(const orc_trace *t);
 /* Per-class instruction counts into out[len] (zeros beyond the classes). */
 int orc_class_hist(const orc_trace *t, uint64_t *out, size_t len);
 /* Count-of-counts of (space, skip k): ascending f; n_out = number of pairs. */

@@ -12,21 +12,37 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libaiwc.so")
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-FLAGS = ["-O3", "-std=c++17", "-fPIC", "-shared", f"--offload-arch={ARCH}",
+FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-result", "-Wno-unused-value",
          "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
 
+def _compile(src: str, obj: str) -> subprocess.CompletedProcess:
+    return subprocess.run([HIPCC] + FLAGS + ["-c", src, "-o", obj], capture_output=True, text=True)
+
+
 def build(verbose: bool = False) -> str:
+    """Compile every translation unit (in parallel), then link the library."""
+    from concurrent.futures import ThreadPoolExecutor
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
-    cmd = [HIPCC] + FLAGS + srcs + ["-o", LIB + ".tmp"]
-    r = subprocess.run(cmd, capture_output=True, text=True)
+    odir = os.path.join(HERE, "_build")
+    os.makedirs(odir, exist_ok=True)
+    objs = [os.path.join(odir, os.path.basename(s)[:-4] + ".o") for s in srcs]
+    jobs = max(1, min(len(srcs), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1)), 16))
+    with ThreadPoolExecutor(jobs) as ex:
+        results = list(ex.map(_compile, srcs, objs))
+    for src, r in zip(srcs, results):
+        if r.returncode != 0:
+            sys.stderr.write(r.stdout + r.stderr)
+            raise RuntimeError(f"hipcc failed compiling {os.path.basename(src)}")
+        if verbose:
+            sys.stderr.write(r.stderr)
+    r = subprocess.run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC"] + objs +
+                       ["-o", LIB + ".tmp"], capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc failed building libaiwc.so")
-    if verbose:
-        sys.stderr.write(r.stderr)
+        raise RuntimeError("hipcc failed linking libaiwc.so")
     os.replace(LIB + ".tmp", LIB)
     return LIB
 

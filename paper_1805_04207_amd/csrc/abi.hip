@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <atomic>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -21,6 +22,9 @@ u64 br_blocks_for(u64 n);
 }
 
 static thread_local std::string g_noctx_err;
+// Creation serials of traces: a destroyed trace's heap address may be reused
+// by the next trace, its serial never is.
+static std::atomic<u64> g_trace_serial{0};
 
 void ctx_error(aiwc_ctx *ctx, const char *fmt, ...) {
   char buf[512];
@@ -460,6 +464,7 @@ extern "C" aiwc_status aiwc_trace_create(aiwc_ctx *ctx, const aiwc_trace_desc *d
   HIP_OR(ctx, hipSetDevice(ctx->device));
   aiwc_trace *t = new aiwc_trace();
   t->ctx = ctx;
+  t->serial = ++g_trace_serial;
   t->d = *d;
   t->d.opcode_table = nullptr;
   t->n_classes = ncls;
@@ -666,19 +671,18 @@ extern "C" aiwc_status aiwc_characterize_merged(aiwc_ctx *ctx, const aiwc_trace 
 }
 
 // ------------------------------------------------------------------ metrics
-extern "C" aiwc_status aiwc_metrics_read(aiwc_metrics *m, aiwc_metrics_host *out) {
-  if (!m || !out) { ctx_error(m ? m->ctx : nullptr, "aiwc_metrics_read: NULL argument"); return AIWC_ERR_INVALID_ARG; }
-  aiwc_ctx *ctx = m->ctx;
-  HIP_OR(ctx, hipEventSynchronize(m->done));
-  std::vector<char> h(m->plan.r_metrics + sizeof(aiwc_metrics_host) + 32);
-  HIP_OR(ctx, hipMemcpy(h.data(), (char *)m->buf + m->plan.r_metrics,
-                        sizeof(aiwc_metrics_host) + 32, hipMemcpyDeviceToHost));
+// The result block's metrics struct and its status words (written by
+// k_finalize): checks the status words and fills *out.
+aiwc_status decode_result(aiwc_ctx *ctx, const char *raw, aiwc_metrics_host *out,
+                          u32 spec_pairs[2]) {
   aiwc_metrics_host r;
-  memcpy(&r, h.data(), sizeof r);
+  memcpy(&r, raw, sizeof r);
   u64 status[4];
-  memcpy(status, h.data() + sizeof(aiwc_metrics_host), sizeof status);
-  m->spec_pairs[0] = (u32)(status[2] & 0xFFFFFFFFu);
-  m->spec_pairs[1] = (u32)(status[2] >> 32);
+  memcpy(status, raw + sizeof(aiwc_metrics_host), sizeof status);
+  if (spec_pairs) {
+    spec_pairs[0] = (u32)(status[2] & 0xFFFFFFFFu);
+    spec_pairs[1] = (u32)(status[2] >> 32);
+  }
   if (status[0]) {
     ctx_error(ctx, "trace content is invalid (%llu bad opcode ids / sites / outcomes)",
               (unsigned long long)status[0]);
@@ -688,8 +692,22 @@ extern "C" aiwc_status aiwc_metrics_read(aiwc_metrics *m, aiwc_metrics_host *out
     ctx_error(ctx, "opcode kinds disagree with the memory / branch stream lengths");
     return AIWC_ERR_INCONSISTENT;
   }
+  if (status[3]) {
+    ctx_error(ctx, "internal capacity limit: %llu on-chip table rounds could not be split "
+              "further (the metrics would be incomplete)", (unsigned long long)status[3]);
+    return AIWC_ERR_UNSUPPORTED;
+  }
   *out = r;
   return AIWC_OK;
+}
+
+extern "C" aiwc_status aiwc_metrics_read(aiwc_metrics *m, aiwc_metrics_host *out) {
+  if (!m || !out) { ctx_error(m ? m->ctx : nullptr, "aiwc_metrics_read: NULL argument"); return AIWC_ERR_INVALID_ARG; }
+  aiwc_ctx *ctx = m->ctx;
+  HIP_OR(ctx, hipEventSynchronize(m->done));
+  char h[sizeof(aiwc_metrics_host) + 32];
+  HIP_OR(ctx, hipMemcpy(h, (char *)m->buf + m->plan.r_metrics, sizeof h, hipMemcpyDeviceToHost));
+  return decode_result(ctx, h, out, m->spec_pairs);
 }
 
 extern "C" aiwc_status aiwc_metrics_class_hist(aiwc_metrics *m, uint64_t *out, size_t len) {

@@ -84,6 +84,7 @@ struct aiwc_ctx {
 
 struct aiwc_trace {
   aiwc_ctx *ctx = nullptr;
+  u64 serial = 0;                 // unique per created trace, never reused
   aiwc_trace_desc d{};
   u32 n_classes = 0;
   std::vector<u32> host_info;
@@ -122,6 +123,8 @@ aiwc_status new_metrics(aiwc_ctx *ctx, const aiwc_trace *t, const TracePlan &p,
 aiwc_status characterize_planned(aiwc_ctx *ctx, const aiwc_trace *t, u32 pbits,
                                  hipStream_t s, aiwc_metrics **out);
 aiwc_status validate_on_device(aiwc_ctx *ctx, const aiwc_trace *t);
+aiwc_status decode_result(aiwc_ctx *ctx, const char *raw, aiwc_metrics_host *out,
+                          u32 spec_pairs[2]);
 
 void sizer_init(aiwc_ctx *ctx);
 void sizer_free(aiwc_ctx *ctx);

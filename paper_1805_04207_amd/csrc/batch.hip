@@ -40,8 +40,9 @@ void free_waves(std::vector<Wave> &w) {
 }  // namespace
 
 struct BatchState {
-  // cache key of the prepared batch
-  std::vector<const aiwc_trace *> key;
+  // cache key of the prepared batch: the traces' creation serials (a trace
+  // destroyed and another created at the same address must not match)
+  std::vector<u64> key;
   std::vector<u32> key_pbits;
   u64 key_cap = 0;
   bool key_graph = false;
@@ -112,9 +113,10 @@ extern "C" aiwc_status aiwc_characterize_batch(aiwc_ctx *ctx, const aiwc_trace *
   const u64 cap = opts->admission_cap_bytes ? opts->admission_cap_bytes : (200ull << 30);
   const bool graph = opts->use_graph != 0;
 
-  bool same = graph && B.key_graph && B.key.size() == n && B.key_cap == cap &&
-              B.key_arena == ctx->arena && std::equal(B.key.begin(), B.key.end(), traces) &&
-              B.key_pbits == pbits;
+  std::vector<u64> serials(n);
+  for (size_t i = 0; i < n; ++i) serials[i] = traces[i]->serial;
+  bool same = graph && B.key_graph && B.key_cap == cap && B.key_arena == ctx->arena &&
+              B.key == serials && B.key_pbits == pbits;
   if (!same) {
     if (B.done) hipEventSynchronize(B.done);
     free_waves(B.waves);
@@ -185,7 +187,7 @@ extern "C" aiwc_status aiwc_characterize_batch(aiwc_ctx *ctx, const aiwc_trace *
       }
       w.dims.batch = w.dev_args;
     }
-    B.key.assign(traces, traces + n);
+    B.key = serials;
     B.key_pbits = pbits;
     B.key_cap = cap;
     B.key_graph = graph;

@@ -34,7 +34,8 @@ struct DevAccum {
   u64 br_queue;
   u64 bad_mem;
   u64 pat_lo, pat_hi;        // pattern entropy sum, 2^-64 units
-  u64 pad[2];
+  u64 split_fail;            // on-chip tables that could not be split further
+  u64 pad[1];
 };
 
 // Everything a kernel needs to know about one trace and its scratch.

@@ -496,7 +496,7 @@ __global__ void __launch_bounds__(WIN_BLOCK) k_br_windows(TraceArgs A0, const Tr
         if (tid == 0) {
           S.live_n = 0; S.overflow = 0;
           if (M >= (1u << 23) || S.sp_top + 2 > 64) {
-            atomicAdd(&A.acc->bad_mem, 1ull);   // hash bits exhausted: report
+            atomicAdd(&A.acc->split_fail, 1ull);   // hash bits exhausted: report
           } else {
             S.stack_m[S.sp_top] = 2 * M; S.stack_c[S.sp_top] = C;
             S.stack_m[S.sp_top + 1] = 2 * M; S.stack_c[S.sp_top + 1] = C + M;

@@ -338,8 +338,10 @@ __global__ void __launch_bounds__(FB) k_finalize(TraceArgs A0, const TraceArgs *
   o->load_imbalance = o->ipt_max - o->ipt_min;
   o->overflow_redos = (uint32_t)acc->redos;
   o->partitions = A.n_mem ? (1u << A.pbits) : 0u;
-  // status words: [0] invalid content, [1] inconsistent kinds, [2] spectrum pairs
+  // status words: [0] invalid content, [1] inconsistent kinds, [2] spectrum
+  // pairs, [3] on-chip tables whose split limit was reached
   status[0] = acc->bad_ids + acc->bad_mem;
+  status[3] = acc->split_fail;
   status[1] = (nload + nstore + 2 * natom != A.n_mem || nbr != A.n_branch) ? 1ull : 0ull;
   status[2] = S.bcast[1] | (S.bcast[2] << 32);
 }

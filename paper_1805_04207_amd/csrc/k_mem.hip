@@ -741,7 +741,7 @@ __global__ void __launch_bounds__(BK_BLOCK) k_mem_bucket(TraceArgs A0, const Tra
         if (tid == 0) {
           S.npages = 0; S.overflow = 0; S.redos += 1;
           if (M >= (1u << 30) || S.sp_top + 2 > 32) {
-            atomicAdd(&A.acc->bad_mem, 1ull);   // hash bits exhausted: report, never spin
+            atomicAdd(&A.acc->split_fail, 1ull);   // hash bits exhausted: report, never spin
           } else {
             S.stack_m[S.sp_top] = 2 * M; S.stack_c[S.sp_top] = C;
             S.stack_m[S.sp_top + 1] = 2 * M; S.stack_c[S.sp_top + 1] = C + M;

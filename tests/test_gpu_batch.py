@@ -88,3 +88,23 @@ def test_autotune_search_keeps_results(batch12, tmp_path, monkeypatch):
     got = [m.read() for m in c.characterize_batch(trs, autotune=aiwc.AUTOTUNE_SEARCH)]
     for g, r in zip(got, ref):
         assert same(g, r)
+
+
+def test_graph_cache_after_destroy_and_recreate():
+    # a cached batch graph belongs to the traces it was built for: a trace
+    # destroyed and another created (possibly at the same host address, with
+    # other arrays and sizes) must not replay the old graph
+    import paper_1805_04207_amd as aiwc
+    from gpu_util import ctx
+    c = ctx()
+    for rep in range(4):
+        sp = tg.config3_specs(seed=40 + rep, n_traces=1, scale=2e-3)[0]
+        h = tg.generate_host(sp)
+        dev = aiwc.host_to_device(h, 0)
+        t = aiwc.device_trace(c, dev, h.table, sp.n_sites, sp.history_len, sp.wg_size)
+        got = c.characterize_batch([t], use_graph=True)[0].read()
+        assert same(got, c.characterize(t).read(), drop=()), f"rep {rep}"
+        bad = compare(got, oracle.characterize(h))
+        assert not bad, "\n".join(bad[:10])
+        t.close()
+        del dev

@@ -57,6 +57,20 @@ def spectrum_of(counts0):
     return {int(x): int(b[x]) for x in f}
 
 
+def spectrum_of_host(h, space):
+    """{f: m_f} of one space's level-0 counts, from the host trace."""
+    a = np.asarray(h.addr)[((np.asarray(h.mem_kind) >> 1) & 1) == space]
+    if a.size == 0:
+        return {}
+    _, c = np.unique(a, return_counts=True)
+    return spectrum_of(c)
+
+
+def res_spectrum(ctx, t, space):
+    """The spectrum pairs of the plain path on trace t."""
+    return ctx.characterize(t).spectrum(space)
+
+
 def invariants(r, n_mem_space):
     """Relations that hold for any trace (Metrics section definitions)."""
     for s in (0, 1):
@@ -160,6 +174,17 @@ def test_stress_batch_full_size():
         bad = compare(ctx.characterize(trs[i]).read(), want)
         assert not bad, f"plain, trace {i}:\n" + "\n".join(bad[:20])
     log("oracle parity on the two smallest traces")
+    # the largest trace (2^28 uniform addresses, 4.5e7 branches at history
+    # 32 over 2^16 sites) against the vectorised oracle, element by element
+    top = int(order[-1])
+    log(f"vectorised oracle on the largest trace {top} ({n_mem[top]} addresses)")
+    hh = tg.generate_host(specs[top])
+    want = bulk.characterize(hh)
+    bad = compare(res[top], want)
+    assert not bad, f"batched, trace {top}:\n" + "\n".join(bad[:20])
+    assert spectrum_of_host(hh, 0) == dict(res_spectrum(ctx, trs[top], 0)), "spectrum"
+    log(f"oracle parity on the largest trace {top}")
+    del hh, want
     # the plain per-trace path on a sample (median, largest)
     for i in (int(order[len(order) // 2]), int(order[-1])):
         assert same(ctx.characterize(trs[i]).read(), res[i]), f"trace {i}"
@@ -207,6 +232,16 @@ def test_uneven_batch_full_size():
     assert not bad, f"trace {mid}:\n" + "\n".join(bad[:20])
     log(f"oracle parity on traces {int(order[0])}, {int(order[1])}, {int(order[2])} and {mid} "
         f"({n_ev[mid]} events)")
+    # the largest trace (about 1e8 events) against the vectorised oracle
+    top = int(order[-1])
+    log(f"vectorised oracle on the largest trace {top} ({n_ev[top]} events)")
+    hh = tg.generate_host(specs[top])
+    want = bulk.characterize(hh)
+    bad = compare(res[top], want)
+    assert not bad, f"trace {top}:\n" + "\n".join(bad[:20])
+    for s in (0, 1):
+        assert spectrum_of_host(hh, s) == dict(res_spectrum(ctx, trs[top], s)), f"spectrum {s}"
+    log(f"oracle parity on the largest trace {top}")
 
 
 @pytest.mark.timeout(1200)

@@ -7,8 +7,8 @@ import pytest
 import oracle
 import tracegen as tg
 from oracle.compare import compare
-from helpers import (BARRIER, BRANCH, COMPUTE, ID_BARRIER, ID_BRANCH, ID_LOAD, ID_STORE,
-                     branch_trace, mem_trace, mk, random_trace, table)
+from helpers import (BARRIER, BRANCH, COMPUTE, ID_ATOMIC, ID_BARRIER, ID_BRANCH, ID_LOAD,
+                     ID_STORE, atomic_trace, branch_trace, mem_trace, mk, random_trace, table)
 
 pytestmark = pytest.mark.gpu
 
@@ -115,6 +115,46 @@ def test_config2_medium_device_generated():
     got = ctx().characterize(t).read()
     bad = compare(got, oracle.characterize(h))
     assert not bad, "\n".join(bad[:20])
+
+
+def test_atomic_traces():
+    # an atomic read-modify-write: one instruction, a read and a write event
+    rng = np.random.default_rng(11)
+    a = rng.integers(0, 1 << 16, size=3000, dtype=np.uint64) * 4
+    got = check(atomic_trace(a, rng.integers(0, 2, size=a.size)))
+    assert got["space"][0]["total_reads"] == got["space"][0]["total_writes"]
+    # the config1 recipe with a quarter of its memory instructions atomic,
+    # generated on the device (identical bytes) and on the host
+    import torch
+    from gpu_util import ctx
+    import paper_1805_04207_amd as aiwc
+    spec = tg.config1()
+    spec.p_atomic = 0.25
+    h = tg.generate_host(spec)
+    assert int((h.opcode == tg.ID_ATOMIC).sum()) > 1000
+    d = tg.generate_device(spec, 0)
+    for f in ("opcode", "wi_offsets", "addr", "mem_kind", "br_site", "br_taken"):
+        x = getattr(h, f)
+        y = d[f][:x.size].cpu().numpy().view(x.dtype)
+        assert np.array_equal(x, y), f"device generator differs in {f}"
+    check(h)
+
+
+def test_atomic_with_one_memory_event_is_inconsistent():
+    from gpu_util import run
+    import paper_1805_04207_amd as aiwc
+    tr = mk([ID_ATOMIC, 0], [2], [256], [0])
+    assert not oracle.consistent(tr)
+    with pytest.raises(aiwc.AiwcError) as e:
+        run(tr)
+    assert e.value.status == 2
+    with pytest.raises(aiwc.AiwcError) as e:
+        run(tr, validate=True)
+    assert e.value.status == 2
+    # with both of its events it is consistent, on both sides
+    ok = mk([ID_ATOMIC, 0], [2], [256, 256], [0, 1])
+    assert oracle.consistent(ok)
+    check(ok)
 
 
 def test_determinism_twice():

@@ -30,8 +30,8 @@ MASK64 = (1 << 64) - 1
 
 # opcode id layout shared by every generated trace
 N_COMPUTE_IDS = 60
-ID_LOAD, ID_STORE, ID_BRANCH, ID_BARRIER, ID_RET = 60, 61, 62, 63, 64
-N_OPCODE_IDS = 65
+ID_LOAD, ID_STORE, ID_BRANCH, ID_BARRIER, ID_RET, ID_ATOMIC = 60, 61, 62, 63, 64, 65
+N_OPCODE_IDS = 66
 KIND_COMPUTE, KIND_LOAD, KIND_STORE, KIND_ATOMIC, KIND_BRANCH, KIND_BARRIER, KIND_OTHER = range(7)
 
 
@@ -51,7 +51,7 @@ class TgParams(ctypes.Structure):
         ("id_store", ctypes.c_uint32), ("id_branch", ctypes.c_uint32),
         ("id_barrier", ctypes.c_uint32), ("id_ret", ctypes.c_uint32),
         ("n_sites", ctypes.c_uint32), ("n_phases", ctypes.c_uint32),
-        ("pad", ctypes.c_uint32),
+        ("p_atomic_q32", ctypes.c_uint32), ("id_atomic", ctypes.c_uint32),
     ]
 
 
@@ -108,10 +108,11 @@ def opcode_table() -> np.ndarray:
     t[ID_BRANCH] = (32, 1, KIND_BRANCH)
     t[ID_BARRIER] = (33, 1, KIND_BARRIER)
     t[ID_RET] = (34, 1, KIND_OTHER)
+    t[ID_ATOMIC] = (35, 1, KIND_ATOMIC)
     return t
 
 
-N_CLASSES = 35
+N_CLASSES = 36
 
 
 @dataclass
@@ -126,6 +127,7 @@ class TraceSpec:
     p_mem: float = 0.30
     p_branch: float = 0.05
     p_store: float = 0.5
+    p_atomic: float = 0.0                 # share of memory instructions that are atomic RMWs
     p_local: float = 0.0
     mix: tuple = (1.0, 0.0, 0.0)          # global (sweep, stencil, random)
     sweep_base: int = 1 << 28
@@ -167,6 +169,8 @@ class TraceSpec:
         p.id_load, p.id_store, p.id_branch = ID_LOAD, ID_STORE, ID_BRANCH
         p.id_barrier, p.id_ret = ID_BARRIER, ID_RET
         p.n_sites = self.n_sites
+        p.p_atomic_q32 = q32(self.p_atomic) if self.p_atomic > 0 else 0
+        p.id_atomic = ID_ATOMIC
         return p
 
     def tables(self):

@@ -13,9 +13,13 @@
  * Event recipe for work-item w at 1-based position p of its L_w events:
  *   p == L_w                      -> RET       (kind OTHER)
  *   period > 0 and p % period == 0 -> BARRIER
- *   else u = hash32(kind stream):  u < p_mem            -> LOAD or STORE
+ *   else u = hash32(kind stream):  u < p_mem            -> LOAD or STORE, or
+ *                                                          ATOMIC_RMW with
+ *                                                          probability p_atomic
  *                                  u < p_mem + p_branch -> BRANCH_COND
  *                                  else                 -> compute id (Zipf CDF)
+ * An ATOMIC_RMW instruction issues two memory events at one address: a read,
+ * then a write.
  * Memory and branch events are emitted in the simulator's schedule order:
  * work-group by work-group, barrier phase by phase, work-item by work-item.
  */
@@ -28,7 +32,7 @@
 #error "define TG_FN before including tg_core.h"
 #endif
 
-enum { TG_S_LEN = 1, TG_S_KIND = 2, TG_S_VAL = 3, TG_S_ADDR = 4 };
+enum { TG_S_LEN = 1, TG_S_KIND = 2, TG_S_VAL = 3, TG_S_ADDR = 4, TG_S_ATOM = 5 };
 enum { TG_EV_COMPUTE = 0, TG_EV_MEM = 1, TG_EV_BRANCH = 2, TG_EV_BARRIER = 3,
        TG_EV_RET = 4 };
 
@@ -53,7 +57,9 @@ typedef struct tg_params {
   uint32_t id_load, id_store, id_branch, id_barrier, id_ret;
   uint32_t n_sites;
   uint32_t n_phases;             /* (len_max - 1) / period + 1, or 1        */
-  uint32_t pad;
+  uint32_t p_atomic_q32;         /* share of memory instructions that are
+                                    atomic read-modify-writes               */
+  uint32_t id_atomic;
 } tg_params;
 
 TG_FN uint64_t tg_mix(uint64_t z) {
@@ -89,6 +95,14 @@ TG_FN int tg_event_type(const tg_params *P, uint64_t w, uint32_t p, uint32_t L) 
   if (u < P->p_mem_q32) return TG_EV_MEM;
   if ((uint64_t)u < (uint64_t)P->p_mem_q32 + P->p_branch_q32) return TG_EV_BRANCH;
   return TG_EV_COMPUTE;
+}
+
+/* Whether the memory instruction at (w, p) is an atomic read-modify-write
+ * (two memory events); never drawn when p_atomic is 0, so traces without
+ * atomics do not depend on this stream.                                     */
+TG_FN int tg_is_atomic(const tg_params *P, uint64_t w, uint32_t p) {
+  return P->p_atomic_q32 != 0u &&
+         (uint32_t)tg_hash(P->seed, TG_S_ATOM, w, p) < P->p_atomic_q32;
 }
 
 TG_FN uint32_t tg_compute_id(const tg_params *P, const uint32_t *zipf_cdf,

@@ -36,7 +36,7 @@ __global__ void k_count(tg_params P, const uint64_t *wi_off, uint64_t *mem_cnt,
       cur = ph;
     }
     int t = tg_event_type(&P, w, p, L);
-    cm += (t == TG_EV_MEM);
+    cm += (t == TG_EV_MEM) ? (tg_is_atomic(&P, w, p) ? 2u : 1u) : 0u;
     cb += (t == TG_EV_BRANCH);
   }
   if (cur != 0xFFFFFFFFu) { mem_cnt[slot] = cm; br_cnt[slot] = cb; }
@@ -70,10 +70,17 @@ __global__ void k_fill(tg_params P, const uint32_t *zipf_cdf,
     } else if (t == TG_EV_MEM) {
       uint8_t k;
       uint64_t a = tg_mem_event(&P, w, p, &jsw, &jst, &k);
-      addr[mo] = a;
-      kind[mo] = k;
-      ++mo;
-      id = (uint16_t)((k & 1u) ? P.id_store : P.id_load);
+      if (tg_is_atomic(&P, w, p)) {
+        // the read, then the write, of one address
+        addr[mo] = a; kind[mo] = (uint8_t)(k & 2u); ++mo;
+        addr[mo] = a; kind[mo] = (uint8_t)((k & 2u) | 1u); ++mo;
+        id = (uint16_t)P.id_atomic;
+      } else {
+        addr[mo] = a;
+        kind[mo] = k;
+        ++mo;
+        id = (uint16_t)((k & 1u) ? P.id_store : P.id_load);
+      }
     } else if (t == TG_EV_BRANCH) {
       uint32_t s;
       uint8_t y;

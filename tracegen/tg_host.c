@@ -38,7 +38,7 @@ static void walk_count(tg_plan *pl, uint64_t w) {
   for (uint32_t p = 1; p <= L; ++p) {
     int t = tg_event_type(P, w, p, L);
     uint64_t s = tg_sched_slot(P, w, tg_phase(P, p));
-    if (t == TG_EV_MEM) pl->mem_off[s]++;
+    if (t == TG_EV_MEM) pl->mem_off[s] += tg_is_atomic(P, w, p) ? 2u : 1u;
     else if (t == TG_EV_BRANCH) pl->br_off[s]++;
   }
 }
@@ -66,6 +66,13 @@ static void walk_fill(tg_plan *pl, uint64_t w, tg_job *j) {
       case TG_EV_MEM: {
         uint8_t k;
         uint64_t a = tg_mem_event(P, w, p, &jsw, &jst, &k);
+        if (tg_is_atomic(P, w, p)) {
+          /* the read, then the write, of one address */
+          j->addr[mo] = a; j->kind[mo] = (uint8_t)(k & 2u); ++mo;
+          j->addr[mo] = a; j->kind[mo] = (uint8_t)((k & 2u) | 1u); ++mo;
+          id = (uint16_t)P->id_atomic;
+          break;
+        }
         j->addr[mo] = a;
         j->kind[mo] = k;
         ++mo;
