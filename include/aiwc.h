@@ -268,6 +268,48 @@ aiwc_status aiwc_trace_destroy(aiwc_trace *trace);
 aiwc_status aiwc_characterize(aiwc_ctx *ctx, const aiwc_trace *trace,
                               void *stream, aiwc_metrics **out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * aiwc_characterize without any allocation.  The scratch buffers of every
+ * stage (partition records, radix buffers, histograms, accumulators) live in
+ * one statically allocated device array of AIWC_STATIC_SCRATCH_BYTES per GPU,
+ * held from the library's first context on that GPU until the process ends;
+ * the result goes to a caller-owned device block.  The call enqueues the
+ * kernels on `stream` (single-stream order) and returns; it calls no
+ * hipMalloc / hipFree, creates no event or stream and copies nothing to the
+ * host.
+ *   dev_result   device pointer, result_bytes long, written by the kernels:
+ *                offset 0: aiwc_metrics_host; right after it four uint64
+ *                status words: [0] != 0 trace content invalid (the
+ *                INVALID_ARG case of aiwc_metrics_read), [1] != 0 kinds
+ *                inconsistent with the stream lengths (INCONSISTENT),
+ *                [2] spectrum pair counts (not exported here), [3] != 0 an
+ *                on-chip round could not be split (UNSUPPORTED); the metrics
+ *                are valid only when words 0, 1 and 3 are 0.  At offset
+ *                AIWC_STATIC_CLASS_OFFSET: the per-class instruction counts,
+ *                uint64[n_classes] with n_classes = 1 + the largest op_class
+ *                of the opcode table.  result_bytes must be at least
+ *                AIWC_STATIC_RESULT_BYTES(n_classes).
+ * Every call on one GPU uses that GPU's one scratch array: calls that
+ * overlap on a GPU (other streams, other host threads, other contexts of the
+ * process) race and must be serialized by the caller (same stream, or
+ * events).  The array keeps the last call's contents; each call clears what
+ * it needs zeroed with a kernel.  Limit: traces whose plan needs more than
+ * AIWC_STATIC_SCRATCH_BYTES of scratch (8 B per memory event for its
+ * partition record, per-block partition histograms, 8 B per branch event
+ * for the radix buffers, ~1.2 MiB of fixed tables: about 2.5 MiB for a trace
+ * of 5e5 events, 41 MiB for 1.3e7 events with 4e6 memory events; up to
+ * about 5.6e6 memory events at the 30% memory / 5% branch mix) return
+ * UNSUPPORTED before anything is enqueued; use aiwc_characterize for those.
+ * Errors: INVALID_ARG (null, foreign trace, result_bytes too small),
+ * UNSUPPORTED (over the limit), HIP (launch failure, or the array's address
+ * could not be found at context creation).                                  */
+#define AIWC_STATIC_SCRATCH_BYTES (64ull << 20)
+#define AIWC_STATIC_CLASS_OFFSET ((sizeof(aiwc_metrics_host) + 32 + 255) / 256 * 256)
+#define AIWC_STATIC_RESULT_BYTES(n_classes) (AIWC_STATIC_CLASS_OFFSET + 8 * (size_t)(n_classes))
+aiwc_status aiwc_characterize_static(aiwc_ctx *ctx, const aiwc_trace *trace, void *stream,
+                                     void *dev_result, size_t result_bytes);
+
 /* Metrics of several invocations of one kernel taken together (the paper
  * reports each kernel as the aggregate over all its invocations at a problem
  * size: Evaluation section).  The result is, by definition, that of the one

@@ -101,7 +101,8 @@ class TrainOpts(ctypes.Structure):
 
 EXPORTS = [
     "aiwc_context_create", "aiwc_context_destroy", "aiwc_last_error", "aiwc_trace_create",
-    "aiwc_trace_destroy", "aiwc_characterize", "aiwc_characterize_merged",
+    "aiwc_trace_destroy", "aiwc_characterize", "aiwc_characterize_static",
+    "aiwc_characterize_merged",
     "aiwc_stream_create", "aiwc_stream_append", "aiwc_stream_finish", "aiwc_stream_destroy",
     "aiwc_characterize_batch", "aiwc_batch_last_stats",
     "aiwc_metrics_read", "aiwc_metrics_class_hist", "aiwc_metrics_spectrum", "aiwc_metrics_destroy",
@@ -134,6 +135,7 @@ def load_library(path: str = LIB_PATH):
         "aiwc_trace_create": (st, [vp, ctypes.POINTER(TraceDesc), ctypes.POINTER(vp)]),
         "aiwc_trace_destroy": (st, [vp]),
         "aiwc_characterize": (st, [vp, vp, vp, ctypes.POINTER(vp)]),
+        "aiwc_characterize_static": (st, [vp, vp, vp, vp, sz]),
         "aiwc_characterize_merged": (st, [vp, ctypes.POINTER(vp), sz, vp, ctypes.POINTER(vp)]),
         "aiwc_stream_create": (st, [vp, u64, u64, ctypes.c_uint32, ctypes.POINTER(vp)]),
         "aiwc_stream_append": (st, [vp, vp, vp]),
@@ -223,6 +225,13 @@ class Context:
         self.check(self.lib.aiwc_characterize(self.h, trace.h, _stream_ptr(stream),
                                               ctypes.byref(m)))
         return Metrics(self, m)
+
+    def characterize_static(self, trace: "Trace", out, stream=None):
+        """aiwc_characterize_static: no allocation; the result goes to `out`,
+        a uint8 CUDA tensor of at least static_result_bytes(n_classes) bytes
+        (decode a host copy with static_result)."""
+        self.check(self.lib.aiwc_characterize_static(self.h, trace.h, _stream_ptr(stream),
+                                                     out.data_ptr(), int(out.numel())))
 
     def characterize_merged(self, traces: Sequence["Trace"], stream=None) -> "Metrics":
         """Metrics of the invocations taken together (their concatenation)."""
@@ -323,6 +332,38 @@ class Context:
 
     def sizer_set_margin(self, margin_log2: float):
         self.check(self.lib.aiwc_sizer_set_margin(self.h, margin_log2))
+
+
+STATIC_SCRATCH_BYTES = 64 << 20
+
+
+def static_class_offset() -> int:
+    """AIWC_STATIC_CLASS_OFFSET of include/aiwc.h."""
+    return (ctypes.sizeof(MetricsHost) + 32 + 255) // 256 * 256
+
+
+def static_result_bytes(n_classes: int) -> int:
+    """AIWC_STATIC_RESULT_BYTES(n_classes) of include/aiwc.h."""
+    return static_class_offset() + 8 * n_classes
+
+
+def static_result(raw: bytes, n_classes: int):
+    """Decode a host copy of an aiwc_characterize_static result block:
+    (metrics dict, class histogram list).  The status words map to the
+    errors aiwc_metrics_read reports."""
+    import numpy as np
+    n = ctypes.sizeof(MetricsHost)
+    r = MetricsHost.from_buffer_copy(raw[:n])
+    status = np.frombuffer(raw[n:n + 32], dtype=np.uint64)
+    if status[0]:
+        raise AiwcError(AIWC_ERR_INVALID_ARG, f"trace content is invalid ({int(status[0])})")
+    if status[1]:
+        raise AiwcError(AIWC_ERR_INCONSISTENT, "opcode kinds disagree with the stream lengths")
+    if status[3]:
+        raise AiwcError(AIWC_ERR_UNSUPPORTED, "an on-chip table round could not be split")
+    o = static_class_offset()
+    cls = np.frombuffer(raw[o:o + 8 * n_classes], dtype=np.uint64)
+    return _struct_to_dict(r), cls.tolist()
 
 
 def _stream_ptr(stream) -> Optional[int]:

@@ -340,6 +340,33 @@ extern "C" aiwc_status aiwc_profile_read(aiwc_ctx *ctx, char *names, size_t name
   return AIWC_OK;
 }
 
+// ---------------------------------------------------- allocation-free path
+// Scratch of aiwc_characterize_static: one array per GPU, allocated with the
+// code object.  In host code `scratch` names a host-side stand-in; the
+// device address of each GPU's copy is looked up once per device (at
+// context creation, with the device current) and only that address is used.
+static __device__ __align__(256) unsigned char scratch[AIWC_STATIC_SCRATCH_BYTES];
+static std::mutex g_static_mu;
+static constexpr int STATIC_MAX_DEVICES = 64;
+static void *g_static_ptr[STATIC_MAX_DEVICES];
+
+static hipError_t static_scratch_setup(int device) {
+  std::lock_guard<std::mutex> lk(g_static_mu);
+  if (device < 0 || device >= STATIC_MAX_DEVICES) return hipErrorInvalidDevice;
+  if (g_static_ptr[device]) return hipSuccess;
+  void *ptr = nullptr;
+  hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  if (!ptr) return hipErrorInvalidSymbol;
+  g_static_ptr[device] = ptr;
+  return hipSuccess;
+}
+
+static void *static_scratch_ptr(int device) {
+  std::lock_guard<std::mutex> lk(g_static_mu);
+  return (device >= 0 && device < STATIC_MAX_DEVICES) ? g_static_ptr[device] : nullptr;
+}
+
 // --------------------------------------------------------------- context
 extern "C" aiwc_status aiwc_context_create(int hip_device, aiwc_ctx **out) {
   if (!out) { ctx_error(nullptr, "aiwc_context_create: out is NULL"); return AIWC_ERR_INVALID_ARG; }
@@ -359,6 +386,14 @@ extern "C" aiwc_status aiwc_context_create(int hip_device, aiwc_ctx **out) {
   if (hipGetDeviceProperties(&prop, hip_device) == hipSuccess) {
     c->n_cu = prop.multiProcessorCount;
     c->arch = prop.gcnArchName;
+  }
+  const hipError_t es = static_scratch_setup(hip_device);
+  if (es != hipSuccess) {
+    hipGetLastError();
+    delete c;
+    ctx_error(nullptr, "aiwc_context_create: device %d: address of the static scratch array: %s",
+              hip_device, hipGetErrorString(es));
+    return AIWC_ERR_HIP;
   }
   sizer_init(c);
   *out = c;
@@ -565,6 +600,51 @@ extern "C" aiwc_status aiwc_characterize(aiwc_ctx *ctx, const aiwc_trace *t, voi
     if (v >= 4 && v <= 15) pbits = (u32)v;
   }
   return characterize_planned(ctx, t, pbits, (hipStream_t)stream, out);
+}
+
+// The allocation-free variant: the plan of aiwc_characterize, its scratch in
+// the GPU's static array, the result in the caller's block, the single-stream
+// stage order (no side stream or events to create).
+static_assert(AIWC_STATIC_CLASS_OFFSET == (sizeof(aiwc_metrics_host) + 32 + 255) / 256 * 256,
+              "the static result layout follows the metrics handle's result block");
+extern "C" aiwc_status aiwc_characterize_static(aiwc_ctx *ctx, const aiwc_trace *t, void *stream,
+                                                void *dev_result, size_t result_bytes) {
+  if (!ctx || !t || !dev_result) {
+    ctx_error(ctx, "aiwc_characterize_static: NULL argument");
+    return AIWC_ERR_INVALID_ARG;
+  }
+  if (t->ctx != ctx) { ctx_error(ctx, "trace belongs to another context"); return AIWC_ERR_INVALID_ARG; }
+  const u64 need_out = AIWC_STATIC_RESULT_BYTES(t->n_classes);
+  if (result_bytes < need_out) {
+    ctx_error(ctx, "aiwc_characterize_static: result block of %zu bytes, %llu needed for %u classes",
+              result_bytes, (unsigned long long)need_out, t->n_classes);
+    return AIWC_ERR_INVALID_ARG;
+  }
+  char *ptr = (char *)static_scratch_ptr(ctx->device);
+  if (!ptr) {
+    ctx_error(ctx, "aiwc_characterize_static: no static scratch address for device %d", ctx->device);
+    return AIWC_ERR_HIP;
+  }
+  TracePlan p;
+  plan_trace(t, bound_pbits(t->d.n_mem), p);
+  if (p.scratch_bytes > AIWC_STATIC_SCRATCH_BYTES) {
+    ctx_error(ctx, "aiwc_characterize_static: the trace needs %llu bytes of scratch, the static "
+              "array holds %llu (use aiwc_characterize)", (unsigned long long)p.scratch_bytes,
+              (unsigned long long)AIWC_STATIC_SCRATCH_BYTES);
+    return AIWC_ERR_UNSUPPORTED;
+  }
+  p.spec_export_cap = 0;   // the block holds no spectrum pairs
+  HIP_OR(ctx, hipSetDevice(ctx->device));
+  TraceArgs a;
+  fill_args(t, p, ptr, (char *)dev_result, a);
+  BatchDims dims;
+  add_dims(t, p, a, dims);
+  const hipError_t e = enqueue_stages(a, dims, (hipStream_t)stream, nullptr, nullptr);
+  if (e != hipSuccess) {
+    ctx_error(ctx, "kernel launch failed: %s", hipGetErrorString(e));
+    return AIWC_ERR_HIP;
+  }
+  return AIWC_OK;
 }
 
 // Several invocations as one: their streams are concatenated in a staging
