@@ -103,7 +103,9 @@ void plan_trace(const aiwc_trace *t, u32 pbits, TracePlan &p, const Tune *tune) 
   p.o_ipt_large = take(8ull * p.large_cap);
   p.o_part_hist = take(4ull * p.n_hist_blocks * P);
   p.o_part_off = take(4ull * (P + 1));
+  p.o_part_order = take(4ull * P);
   p.o_part_rec = take(8ull * std::max<u64>(1, d.n_mem));
+  p.o_part_tag = take(4ull * std::max<u64>(1, d.n_mem));
   // radix records: site << 1 | outcome (u32), or with the global history
   // site << 33 | history << 1 | outcome (u64)
   const u64 rec = (d.flags & AIWC_BRANCH_GLOBAL_HISTORY) ? 8 : 4;
@@ -170,7 +172,9 @@ void fill_args(const aiwc_trace *t, const TracePlan &p, char *scratch, char *res
   a.seg_end = (u32 *)(scratch + p.o_seg_end);
   a.part_hist = (u32 *)(scratch + p.o_part_hist);
   a.part_off = (u32 *)(scratch + p.o_part_off);
+  a.part_order = (u32 *)(scratch + p.o_part_order);
   a.part_rec = (u64 *)(scratch + p.o_part_rec);
+  a.part_tag = (u32 *)(scratch + p.o_part_tag);
   a.br_a = (u32 *)(scratch + p.o_br_a);
   a.br_b = (u32 *)(scratch + p.o_br_b);
   a.br_cnt = (u32 *)(scratch + p.o_br_cnt);

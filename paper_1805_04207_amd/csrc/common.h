@@ -73,7 +73,9 @@ struct TraceArgs {
   u32 *seg_start, *seg_end;  // [n_sites]
   u32 *part_hist;            // [n_hist_blocks][P]
   u32 *part_off;             // [P + 1]
+  u32 *part_order;           // [P] bucket-kernel queue order: oversized partitions first
   u64 *part_rec;             // [n_mem]
+  u32 *part_tag;             // [n_mem] page slot and position of each record (bucket kernel)
   u32 *br_a, *br_b;          // [n_branch] radix ping-pong
   u32 *br_cnt;               // [256 * br_tiles]
   u32 *pat_hist;             // [2^m] windows per history pattern (pattern entropy)

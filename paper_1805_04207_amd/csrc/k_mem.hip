@@ -153,6 +153,20 @@ __global__ void __launch_bounds__(1024) k_mem_binscan(TraceArgs A0, const TraceA
     __syncthreads();
   }
   if (threadIdx.x == 0) A.part_off[P] = carry;
+  // the bucket kernel's queue order: partitions of more than STAGE records
+  // (several rounds, or heavy pages whose records are read once per page)
+  // first, so that the longest ones do not start last; the order of the
+  // rest is free (results do not depend on it)
+  __shared__ u32 nbig, nsmall;
+  if (threadIdx.x == 0) { nbig = 0; nsmall = 0; }
+  __syncthreads();
+  for (u32 i = threadIdx.x; i < P; i += 1024)
+    if (A.part_off[i + 1] - A.part_off[i] > AIWC_STAGE_CAP) A.part_order[atomicAdd(&nbig, 1u)] = i;
+  __syncthreads();
+  const u32 nb = nbig;
+  for (u32 i = threadIdx.x; i < P; i += 1024)
+    if (A.part_off[i + 1] - A.part_off[i] <= AIWC_STAGE_CAP)
+      A.part_order[nb + atomicAdd(&nsmall, 1u)] = i;
 }
 
 // -------------------------------------------------------------- scatter
@@ -238,10 +252,13 @@ constexpr u32 MEDIUM = 64;
 constexpr int UNROLL = 8;                         // records in flight per thread
 constexpr u32 SPEC_LDS = 256;
 constexpr u32 STAGE_CAP = AIWC_STAGE_CAP;         // staged records per round
+constexpr u32 TAG_POS = (1u << 21) - 1u;          // position field of a record tag
 // Dense-tree nodes of count >= 256 found by the wavefronts in one round, kept
 // for the block: at most 11 levels * STAGE_CAP / 256 of them.
 constexpr u32 BLIST_CAP = AIWC_NSKIP * STAGE_CAP / 256;
 static_assert(STAGE_CAP < 0xFFFFu, "staging positions travel in 16 bits");
+static_assert(PT_SLOTS <= 2048, "a slot travels in the 11 high bits of a tag and of a staged record");
+static_assert(STAGE_CAP <= (1u << 15) && HEAVY < (1u << 17), "start | size << 15 fits 32 bits");
 
 struct BucketShared {
   u64 pkey[PT_SLOTS];              // page key, EMPTY if free
@@ -251,7 +268,7 @@ struct BucketShared {
   uint16_t psz[PT_CAP];            // records of compact index (saturated at 65535)
   u32 pend[PT_CAP];                // staging cursor, then end, of compact index
   u32 dense[BK_WAVES][1024];       // per-wave byte-offset counters
-  u32 rbits[BK_WAVES][32], wbits[BK_WAVES][32];
+  u32 rbits[32], wbits[32];        // read / write bitmaps of a heavy page
   u64 term[2][256];                // c*log2(N_s/c) for c < 256, 2^-40 units
   u32 spec[2][SPEC_LDS];           // level-0 nodes of count c, 2 <= c < SPEC_LDS
   u64 spf[2][SPEC_SLOTS], spm[2][SPEC_SLOTS];
@@ -313,11 +330,15 @@ __device__ __noinline__ void spec_cache_add(BucketShared &S, SpecRef G, u32 s, u
 // A round stages at most STAGE_CAP records, so per level its terms sum below
 // STAGE_CAP * 32 < 2^20 (2^60 units) and its nodes number below 2^16 (dn:
 // nodes | nodes of count 1 << 16); a heavy page has at most 1024 nodes per
-// level, whose small terms sum below 1024 * 256 * 32 = 2^23.
+// level, whose small terms sum below 1024 * 256 * 32 = 2^23.  Level-0 nodes
+// of count 2..5 (the common small counts) are tallied in two packed words
+// (count 2 | count 3 << 16, count 4 | count 5 << 16: at most STAGE_CAP nodes
+// per lane and round) instead of LDS atomics on a few hot spectrum bins.
 struct LaneAcc {
   u64 lo[AIWC_NSKIP];              // 2^-40 units
   u32 dn[AIWC_NSKIP];
   u32 ur, uw;
+  u32 sp23, sp45;
   int space;
 };
 
@@ -325,6 +346,7 @@ __device__ __forceinline__ void lacc_clear(LaneAcc &L, int space) {
 #pragma unroll
   for (int k = 0; k < AIWC_NSKIP; ++k) { L.lo[k] = 0; L.dn[k] = 0; }
   L.ur = L.uw = 0;
+  L.sp23 = L.sp45 = 0;
   L.space = space;
 }
 
@@ -396,9 +418,15 @@ __device__ __forceinline__ void lacc_flush(LaneAcc &L, BucketShared &S) {
     }
   }
   const u64 r = wave_total(L.ur), w = wave_total(L.uw);
+  const u32 f2 = wave_total(L.sp23 & 0xFFFFu), f3 = wave_total(L.sp23 >> 16);
+  const u32 f4 = wave_total(L.sp45 & 0xFFFFu), f5 = wave_total(L.sp45 >> 16);
   if (lane == 0) {
     if (r) atomicAdd(&S.ur[s], r);
     if (w) atomicAdd(&S.uw[s], w);
+    if (f2) atomicAdd(&S.spec[s][2], f2);
+    if (f3) atomicAdd(&S.spec[s][3], f3);
+    if (f4) atomicAdd(&S.spec[s][4], f4);
+    if (f5) atomicAdd(&S.spec[s][5], f5);
   }
   lacc_clear(L, s);
 }
@@ -409,6 +437,13 @@ __device__ __forceinline__ void lacc_flush(LaneAcc &L, BucketShared &S) {
 __device__ __forceinline__ void add_small_node(LaneAcc &L, const BucketShared &S, int k, u32 c) {
   L.lo[k] += S.term[L.space][c >= 2 ? c : 0u];   // term[0] = 0
   L.dn[k] += (c != 0 ? 1u : 0u) + (c == 1 ? 0x10000u : 0u);
+}
+
+// The level-0 spectrum entry of a node of count c < SPEC_LDS (c < 2: none).
+__device__ __forceinline__ void spec_node(LaneAcc &L, BucketShared &S, u32 c) {
+  L.sp23 += (c == 2 ? 1u : 0u) + (c == 3 ? 0x10000u : 0u);
+  L.sp45 += (c == 4 ? 1u : 0u) + (c == 5 ? 0x10000u : 0u);
+  if (c >= 6) atomicAdd(&S.spec[L.space][c], 1u);
 }
 
 // A node of count >= 256 (rare): its term goes straight to the block's
@@ -428,9 +463,15 @@ __device__ __forceinline__ void big_node(BucketShared &S, SpecRef G, int s, int 
 // 16-byte strided offsets spread over 8 banks instead of 2).
 __device__ __forceinline__ u32 cslot(u32 off) { return off ^ (((off >> 5) & 3u) << 2); }
 
+// A dense counter's access count.  Counters of staged pages (at most HEAVY
+// records) hold reads | writes << 16 (RW); heavy pages count plainly.
+template <bool RW>
+__device__ __forceinline__ u32 cval(u32 x) { return RW ? (x & 0xFFFFu) + (x >> 16) : x; }
+
 // The nodes of count >= 256 of the dense tree over cnt[1024] (see
 // page_levels).  Few pages have any: plain loops, so that the logarithm is
 // emitted twice rather than once per node (and no call spills registers).
+template <bool RW>
 __device__ __forceinline__ void big_pass(BucketShared &S, SpecRef G, const u32 *cnt, int s,
                                          u64 N) {
   const int lane = lane_id();
@@ -442,13 +483,13 @@ __device__ __forceinline__ void big_pass(BucketShared &S, SpecRef G, const u32 *
     for (int j = 0; j < (16 >> k); ++j) {
       u32 v = 0;
 #pragma unroll 1
-      for (int q = 0; q < (1 << k); ++q) v += my[((j << k) + q) ^ sw];
+      for (int q = 0; q < (1 << k); ++q) v += cval<RW>(my[((j << k) + q) ^ sw]);
       if (v >= 256) big_node(S, G, s, k, v, N);
     }
   }
   u32 t = 0;
 #pragma unroll
-  for (int q = 0; q < 16; ++q) t += my[q];
+  for (int q = 0; q < 16; ++q) t += cval<RW>(my[q]);
   u32 tk[AIWC_NSKIP - 5];
 #pragma unroll
   for (int k = 5; k < AIWC_NSKIP; ++k) {
@@ -466,6 +507,7 @@ __device__ __forceinline__ void big_pass(BucketShared &S, SpecRef G, const u32 *
 
 // As big_pass, but the nodes are appended to the block's list (their counts
 // stay below 2^24: a staged page has at most HEAVY records).
+template <bool RW>
 __device__ __forceinline__ void big_collect(BucketShared &S, const u32 *cnt, int s) {
   const int lane = lane_id();
   const u32 *my = cnt + 16 * lane;
@@ -477,7 +519,7 @@ __device__ __forceinline__ void big_collect(BucketShared &S, const u32 *cnt, int
     for (int j = 0; j < (16 >> k); ++j) {
       u32 v = 0;
 #pragma unroll 1
-      for (int q = 0; q < (1 << k); ++q) v += my[((j << k) + q) ^ sw];
+      for (int q = 0; q < (1 << k); ++q) v += cval<RW>(my[((j << k) + q) ^ sw]);
       if (v >= 256) {
         const u32 bi = atomicAdd(&S.nblist, 1u);
         if (bi < BLIST_CAP) S.blist[bi] = tag | ((u32)k << 24) | v;
@@ -486,7 +528,7 @@ __device__ __forceinline__ void big_collect(BucketShared &S, const u32 *cnt, int
   }
   u32 t = 0;
 #pragma unroll
-  for (int q = 0; q < 16; ++q) t += my[q];
+  for (int q = 0; q < 16; ++q) t += cval<RW>(my[q]);
 #pragma unroll
   for (int k = 5; k < AIWC_NSKIP; ++k) {
     t += __shfl_xor(t, 1 << (k - 5), 64);
@@ -498,13 +540,15 @@ __device__ __forceinline__ void big_collect(BucketShared &S, const u32 *cnt, int
 }
 
 // All levels of one page whose byte-offset counts sit in cnt[1024] (LDS,
-// owned by this wavefront) and whose read / write bitmaps in rb[32], wb[32].
+// owned by this wavefront): with RW each counter holds reads | writes << 16,
+// otherwise plain counts with read / write bitmaps in rb[32], wb[32].
 // Lane l loads counters 16l..16l+15 (swizzled, see cslot): levels 0..4 are
 // sums inside the lane, levels 5..10 sums across 2, 4, .., 64 lanes (the
-// lowest lane owns the node).  Counts below 256 are accumulated in one pass;
-// if any node reaches 256, a second pass walks the tree again for those
-// nodes only.
-template <bool DEFER>
+// lowest lane owns the node).  Counts below 256 are accumulated in one pass
+// (branch free, so that the table loads of a level issue back to back); if
+// any node reaches 256, a second pass walks the tree again for those nodes
+// only.
+template <bool DEFER, bool RW>
 __device__ __forceinline__ void page_levels(LaneAcc &L, BucketShared &S, SpecRef G,
                                             const u32 *cnt, const u32 *rb, const u32 *wb,
                                             u64 N) {
@@ -518,20 +562,27 @@ __device__ __forceinline__ void page_levels(LaneAcc &L, BucketShared &S, SpecRef
     const uint4 x = src[q ^ sw];
     c[4 * q] = x.x; c[4 * q + 1] = x.y; c[4 * q + 2] = x.z; c[4 * q + 3] = x.w;
   }
-  if (lane < 32) {
+  // positions and nodes that are empty in every lane (most of them on
+  // strided pages) are skipped by the whole wavefront
+  if constexpr (RW) {
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      if (c[j] == 0) continue;
+      L.ur += (c[j] & 0xFFFFu) != 0 ? 1u : 0u;
+      L.uw += (c[j] >> 16) != 0 ? 1u : 0u;
+      c[j] = (c[j] & 0xFFFFu) + (c[j] >> 16);
+    }
+  } else if (lane < 32) {
     L.ur += __builtin_popcount(rb[lane]);
     L.uw += __builtin_popcount(wb[lane]);
   }
-  // a level-0 position empty in every lane (common: strided pages use one
-  // counter in 2^j) is skipped by the whole wavefront; the coarser levels
-  // load their terms in one batch
   bool anybig = false;
 #pragma unroll
   for (int j = 0; j < 16; ++j) {
     if (__ballot(c[j] != 0) == 0) continue;
     const u32 v = c[j] < 256 ? c[j] : 0u;
     add_small_node(L, S, 0, v);
-    if (v >= 2) atomicAdd(&S.spec[s][v], 1u);
+    spec_node(L, S, v);
     anybig |= c[j] >= 256;
   }
 #pragma unroll
@@ -539,6 +590,7 @@ __device__ __forceinline__ void page_levels(LaneAcc &L, BucketShared &S, SpecRef
 #pragma unroll
     for (int j = 0; j < (16 >> k); ++j) {
       c[j] = c[2 * j] + c[2 * j + 1];
+      if (c[j] == 0) continue;
       add_small_node(L, S, k, c[j] < 256 ? c[j] : 0u);
       anybig |= c[j] >= 256;
     }
@@ -558,8 +610,8 @@ __device__ __forceinline__ void page_levels(LaneAcc &L, BucketShared &S, SpecRef
     anybig |= own && t >= 256;
   }
   if (__ballot(anybig) != 0) {
-    if constexpr (DEFER) big_collect(S, cnt, s);
-    else big_pass(S, G, cnt, s, N);
+    if constexpr (DEFER) big_collect<RW>(S, cnt, s);
+    else big_pass<RW>(S, G, cnt, s, N);
   }
 }
 
@@ -593,7 +645,7 @@ __device__ __forceinline__ void match_levels(LaneAcc &L, BucketShared &S, u32 of
     L.lo[k] += t[k];
     L.dn[k] += (c[k] != 0 ? 1u : 0u) + (c[k] == 1 ? 0x10000u : 0u);
   }
-  if (c[0] >= 2) atomicAdd(&S.spec[L.space][c[0]], 1u);
+  spec_node(L, S, c[0]);
   // distinct read / written addresses: the lowest read (write) of each level-0 node
   const u64 Bw = __ballot(w != 0);
   const u64 Q = P & (w ? Bw : ~Bw);
@@ -603,10 +655,11 @@ __device__ __forceinline__ void match_levels(LaneAcc &L, BucketShared &S, u32 of
   }
 }
 
-__device__ __forceinline__ u32 pt_find(const BucketShared &S, u64 pk) {
-  u32 slot = hash_slot(pk, PT_SLOTS);
-  while (S.pkey[slot] != pk) slot = (slot + 1 == PT_SLOTS) ? 0 : slot + 1;
-  return slot;
+// Home slot of a page key in the page table (Fibonacci hashing: the high
+// bits of the product depend on every key bit, including those above the
+// ones a split fixes).
+__device__ __forceinline__ u32 pt_slot(u64 pk) {
+  return (u32)((pk * 0x9E3779B97F4A7C15ull) >> (64 - 11));
 }
 
 __device__ __forceinline__ u64 low_mask(u32 n) { return n >= 64 ? ~0ull : (1ull << n) - 1ull; }
@@ -646,8 +699,8 @@ __global__ void __launch_bounds__(BK_BLOCK) k_mem_bucket(TraceArgs A0, const Tra
   while (true) {
     if (tid == 0) S.work = (u32)atomicAdd(&A.acc->mem_queue, 1ull);
     __syncthreads();
-    const u32 p = S.work;
-    if (p >= P) break;
+    if (S.work >= P) break;
+    const u32 p = A.part_order[S.work];
     const u64 base = A.part_off[p];
     const u32 n = A.part_off[p + 1] - (u32)base;
     if (tid == 0) { S.sp_top = 1; S.stack_m[0] = 1; S.stack_c[0] = 0; }
@@ -657,23 +710,60 @@ __global__ void __launch_bounds__(BK_BLOCK) k_mem_bucket(TraceArgs A0, const Tra
       __syncthreads();
       if (tid == 0) S.sp_top -= 1;
       // ---- 1. page pass (UNROLL records in flight per thread; the first
-      // lane of each run of one page's records counts the whole run)
+      // lane of each run of one page's records counts the whole run).  The
+      // count before the run's addition is the run's first position inside
+      // its page: every record leaves its tag (slot << 21 | position,
+      // saturated) in part_tag, so that the regroup needs no table lookup.
       const u64 below = (1ull << lane) - 1ull;
+      // software pipelined: the next batch's loads are in flight while this
+      // batch is counted
+      u64 nx[UNROLL];
+#pragma unroll
+      for (int u = 0; u < UNROLL; ++u) {
+        const u32 i = (u32)tid + (u32)u * BK_BLOCK;
+        nx[u] = i < n ? A.part_rec[base + i] : EMPTY;
+      }
       for (u32 w0 = (u32)(tid - lane); w0 < n; w0 += BK_BLOCK * UNROLL) {
         u64 rv[UNROLL];
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u) {
-          const u32 i = w0 + (u32)u * BK_BLOCK + (u32)lane;
-          rv[u] = i < n ? A.part_rec[base + i] : EMPTY;
+          rv[u] = nx[u];
+          const u32 i = w0 + (u32)(BK_BLOCK * UNROLL) + (u32)u * BK_BLOCK + (u32)lane;
+          nx[u] = i < n ? A.part_rec[base + i] : EMPTY;
         }
+        // run heads and their first probe slots for all records at once
+        u32 hs[UNROLL], run[UNROLL];
+        u64 hw[UNROLL];
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u) {
           const u64 pk = rv[u] >> 11;
           const bool valid = rv[u] != EMPTY && ((u32)pk & (M - 1u)) == C;
           const u64 ends = run_ends(valid ? pk : EMPTY);
-          if (!valid || (lane > 0 && ((ends >> (lane - 1)) & 1ull) == 0)) continue;
-          const u32 run = (u32)__builtin_ctzll(ends & ~below) - (u32)lane + 1u;
-          u32 slot = hash_slot(pk, PT_SLOTS);
+          const bool head = valid && (lane == 0 || ((ends >> (lane - 1)) & 1ull) != 0);
+          run[u] = head ? (u32)__builtin_ctzll(ends & ~below) - (u32)lane + 1u : 0u;
+          hs[u] = pt_slot(pk);
+        }
+        // first probes: the page is usually in its home slot already, so the
+        // table loads and the count atomics of all records are in flight
+        // together; the rest take the probing loop
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) hw[u] = run[u] ? S.pkey[hs[u]] : EMPTY;
+        u32 hv[UNROLL];
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+          const u64 pk = rv[u] >> 11;
+          hv[u] = 0;
+          if (run[u] && hw[u] == pk) {
+            const u32 at = atomicAdd(&S.pcnt[hs[u]], run[u]);
+            hv[u] = (hs[u] << 21) | (at < TAG_POS ? at : TAG_POS);
+            run[u] = 0;
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+          if (!run[u]) continue;
+          const u64 pk = rv[u] >> 11;
+          u32 slot = hs[u];
           while (true) {
             u64 w = S.pkey[slot];
             if (w == EMPTY) {
@@ -688,9 +778,28 @@ __global__ void __launch_bounds__(BK_BLOCK) k_mem_bucket(TraceArgs A0, const Tra
                 w = old;
               }
             }
-            if (w == pk) { atomicAdd(&S.pcnt[slot], run); break; }
+            if (w == pk) {
+              const u32 at = atomicAdd(&S.pcnt[slot], run[u]);
+              hv[u] = (slot << 21) | (at < TAG_POS ? at : TAG_POS);
+              break;
+            }
             slot = (slot + 1 == PT_SLOTS) ? 0 : slot + 1;
           }
+        }
+        // each lane of a run takes its head's slot and the next position
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+          const u64 pk = rv[u] >> 11;
+          const bool valid = rv[u] != EMPTY && ((u32)pk & (M - 1u)) == C;
+          const u64 ends = run_ends(valid ? pk : EMPTY);
+          const bool head = valid && (lane == 0 || ((ends >> (lane - 1)) & 1ull) != 0);
+          const u64 H = __ballot(head) & (below | (1ull << lane));
+          const int hl = H ? 63 - __builtin_clzll(H) : lane;
+          const u32 h0 = __shfl(hv[u], hl, 64);
+          const u32 pos = (h0 & TAG_POS) + (u32)(lane - hl);
+          if (valid)
+            A.part_tag[base + w0 + (u32)u * BK_BLOCK + (u32)lane] =
+                (h0 & ~TAG_POS) | (pos < TAG_POS ? pos : TAG_POS);
         }
       }
       __syncthreads();
@@ -776,41 +885,47 @@ __global__ void __launch_bounds__(BK_BLOCK) k_mem_bucket(TraceArgs A0, const Tra
         c0 = (u32)__builtin_amdgcn_readfirstlane((int)c0);
         c1 = (u32)__builtin_amdgcn_readfirstlane((int)c1);
         c2 = (u32)__builtin_amdgcn_readfirstlane((int)c2);
-        if (cl == 0) S.pend[j] = c0 + (x01 & 0xFFFFu) - c;
-        else if (cl == 1) S.pend[j] = c1 + (x01 >> 16) - c;
-        else if (cl == 2) S.pend[j] = c2 + x2 - c;
+        // pend: the page's end in the staging array; the page's table word
+        // becomes its start | size << 15 (~0: not staged)
+        u32 end = 0;
+        if (cl == 0) end = c0 + (x01 & 0xFFFFu);
+        else if (cl == 1) end = c1 + (x01 >> 16);
+        else if (cl == 2) end = c2 + x2;
+        if (j < np) {
+          S.pend[j] = end;
+          S.pcnt[S.pslot[j]] = cl < 3 ? (end - c) | (c << 15) : ~0u;
+        }
       }
       __syncthreads();
-      // regroup: the first lane of each run reserves the run's positions
-      for (u32 w0 = (u32)(tid - lane); w0 < n; w0 += BK_BLOCK * UNROLL) {
+      // regroup: every staged record goes to its page's start plus the
+      // position the page pass gave it
+      u64 nr[UNROLL];
+      u32 nt[UNROLL];
+#pragma unroll
+      for (int u = 0; u < UNROLL; ++u) {
+        const u32 i = (u32)tid + (u32)u * BK_BLOCK;
+        nr[u] = i < n ? A.part_rec[base + i] : EMPTY;
+        nt[u] = i < n ? A.part_tag[base + i] : 0u;
+      }
+      for (u32 w0 = (u32)tid; w0 < n; w0 += BK_BLOCK * UNROLL) {
         u64 rv[UNROLL];
+        u32 tg[UNROLL];
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u) {
-          const u32 i = w0 + (u32)u * BK_BLOCK + (u32)lane;
-          rv[u] = i < n ? A.part_rec[base + i] : EMPTY;
+          rv[u] = nr[u];
+          tg[u] = nt[u];
+          const u32 i = w0 + (u32)(BK_BLOCK * UNROLL) + (u32)u * BK_BLOCK;
+          nr[u] = i < n ? A.part_rec[base + i] : EMPTY;
+          nt[u] = i < n ? A.part_tag[base + i] : 0u;
         }
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u) {
-          const u64 pk = rv[u] >> 11;
-          const bool valid = rv[u] != EMPTY && ((u32)pk & (M - 1u)) == C;
-          const u64 ends = run_ends(valid ? pk : EMPTY);
-          const bool head = valid && (lane == 0 || ((ends >> (lane - 1)) & 1ull) != 0);
-          // head: page index << 16 | first position (positions < STAGE_CAP
-          // <= 2^15; 0xFFFF: heavy page, not staged), broadcast to its run
-          u32 hp = 0xFFFFu;
-          if (head) {
-            const u32 ci = S.pidx[pt_find(S, pk)];
-            hp = (ci << 16) | 0xFFFFu;
-            if (S.psz[ci] <= HEAVY)
-              hp = (ci << 16) |
-                   atomicAdd(&S.pend[ci], (u32)__builtin_ctzll(ends & ~below) - (u32)lane + 1u);
-          }
-          const u64 H = __ballot(head) & (below | (1ull << lane));
-          const int hl = H ? 63 - __builtin_clzll(H) : lane;
-          const u32 h0 = __shfl(hp, hl, 64);
-          const u32 p0 = (h0 & 0xFFFFu) + (u32)(lane - hl);
-          if (valid && (h0 & 0xFFFFu) != 0xFFFFu && p0 < STAGE_CAP)
-            S.stage[p0] = ((h0 >> 16) << 11) | (u32)(rv[u] & 2047ull);
+          if (rv[u] == EMPTY || ((u32)(rv[u] >> 11) & (M - 1u)) != C) continue;
+          const u32 slot = tg[u] >> 21;
+          const u32 pc = S.pcnt[slot];
+          if (pc == ~0u) continue;
+          const u32 p0 = (pc & 0x7FFFu) + (tg[u] & TAG_POS);
+          if (p0 < STAGE_CAP) S.stage[p0] = (slot << 11) | (u32)(rv[u] & 2047ull);
         }
       }
       __syncthreads();
@@ -822,7 +937,7 @@ __global__ void __launch_bounds__(BK_BLOCK) k_mem_bucket(TraceArgs A0, const Tra
           if (S.psz[ci] <= HEAVY) continue;
           const u64 hk = S.pkey[S.pslot[ci]];
           for (u32 i = tid; i < 1024; i += BK_BLOCK) S.dense[0][i] = 0;
-          if (tid < 32) { S.rbits[0][tid] = 0; S.wbits[0][tid] = 0; }
+          if (tid < 32) { S.rbits[tid] = 0; S.wbits[tid] = 0; }
           __syncthreads();
           for (u32 i0 = tid; i0 < n; i0 += BK_BLOCK * UNROLL) {
             u64 rv[UNROLL];
@@ -836,7 +951,7 @@ __global__ void __launch_bounds__(BK_BLOCK) k_mem_bucket(TraceArgs A0, const Tra
               if (rv[u] == EMPTY || (rv[u] >> 11) != hk) continue;
               const u32 off = (u32)(rv[u] >> 1) & 1023u;
               atomicAdd(&S.dense[0][cslot(off)], 1u);
-              atomicOr((rv[u] & 1u) ? &S.wbits[0][off >> 5] : &S.rbits[0][off >> 5],
+              atomicOr((rv[u] & 1u) ? &S.wbits[off >> 5] : &S.rbits[off >> 5],
                        1u << (off & 31u));
             }
           }
@@ -845,7 +960,7 @@ __global__ void __launch_bounds__(BK_BLOCK) k_mem_bucket(TraceArgs A0, const Tra
             const int sp = bi < nb0 ? 0 : 1;
             LaneAcc H;
             lacc_clear(H, sp);
-            page_levels<false>(H, S, G, S.dense[0], S.rbits[0], S.wbits[0], sp ? N1 : N0);
+            page_levels<false, false>(H, S, G, S.dense[0], S.rbits, S.wbits, sp ? N1 : N0);
             lacc_flush(H, S);
           }
           __syncthreads();
@@ -858,7 +973,6 @@ __global__ void __launch_bounds__(BK_BLOCK) k_mem_bucket(TraceArgs A0, const Tra
         const u32 W0 = (R0 + SMALL - 1) / SMALL, W1 = (R1 + SMALL - 1) / SMALL;
         const u32 e0 = W0, e1 = e0 + nb0, e2 = e1 + W1, e3 = e2 + nb1;
         u32 *dn = S.dense[wave];
-        u32 *rb = S.rbits[wave], *wb = S.wbits[wave];
         LaneAcc L;
         lacc_clear(L, 0);
         while (true) {
@@ -878,8 +992,8 @@ __global__ void __launch_bounds__(BK_BLOCK) k_mem_bucket(TraceArgs A0, const Tra
             u64 pm = 0;
             if (i < rend) {
               v = S.stage[i];
-              const u32 ci = v >> 11;
-              const u32 sz = S.psz[ci], st = S.pend[ci] - sz;
+              const u32 pc = S.pcnt[v >> 11];
+              const u32 sz = pc >> 15, st = pc & 0x7FFFu;
               if (st >= lo && st < lo + SMALL) pm = low_mask(sz) << (st - lo);
             }
             match_levels(L, S, (v >> 1) & 1023u, v & 1u, pm);
@@ -897,7 +1011,6 @@ __global__ void __launch_bounds__(BK_BLOCK) k_mem_bucket(TraceArgs A0, const Tra
           uint4 *z = reinterpret_cast<uint4 *>(dn + 16 * lane);
 #pragma unroll
           for (int q = 0; q < 4; ++q) z[q] = make_uint4(0, 0, 0, 0);
-          if (lane < 32) { rb[lane] = 0; wb[lane] = 0; }
           __builtin_amdgcn_wave_barrier();
           for (u32 i0 = o0 + lane; i0 < o1; i0 += AIWC_WAVE * 4) {
             u32 vv[4];
@@ -910,13 +1023,12 @@ __global__ void __launch_bounds__(BK_BLOCK) k_mem_bucket(TraceArgs A0, const Tra
             for (int u = 0; u < 4; ++u) {
               if (vv[u] == ~0u) continue;
               const u32 off = (vv[u] >> 1) & 1023u;
-              atomicAdd(&dn[cslot(off)], 1u);
-              atomicOr((vv[u] & 1u) ? &wb[off >> 5] : &rb[off >> 5], 1u << (off & 31u));
+              atomicAdd(&dn[cslot(off)], (vv[u] & 1u) ? 0x10000u : 1u);
             }
           }
           __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
           __builtin_amdgcn_wave_barrier();
-          page_levels<true>(L, S, G, dn, rb, wb, N);
+          page_levels<true, true>(L, S, G, dn, nullptr, nullptr, N);
           __builtin_amdgcn_wave_barrier();
         }
         lacc_flush(L, S);
