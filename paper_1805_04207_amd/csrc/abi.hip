@@ -106,6 +106,7 @@ void plan_trace(const aiwc_trace *t, u32 pbits, TracePlan &p, const Tune *tune) 
   p.o_part_order = take(4ull * P);
   p.o_part_rec = take(8ull * std::max<u64>(1, d.n_mem));
   p.o_part_tag = take(4ull * std::max<u64>(1, d.n_mem));
+  p.o_ops_wlo = take(8ull * (p.ops_tasks + 1));
   // radix records: site << 1 | outcome (u32), or with the global history
   // site << 33 | history << 1 | outcome (u64)
   const u64 rec = (d.flags & AIWC_BRANCH_GLOBAL_HISTORY) ? 8 : 4;
@@ -159,6 +160,7 @@ void fill_args(const aiwc_trace *t, const TracePlan &p, char *scratch, char *res
   a.large_cap = p.large_cap;
   a.ops_task = p.ops_task;
   a.ops_tasks = p.ops_tasks;
+  a.ops_wlo = (u64 *)(scratch + p.o_ops_wlo);
   a.acc = (DevAccum *)(scratch + p.o_acc);
   a.id_hist = (u64 *)(scratch + p.o_id_hist);
   a.class_hist = (u64 *)(scratch + p.o_class_hist);
@@ -223,6 +225,7 @@ void add_dims(const aiwc_trace *t, const TracePlan &p, const TraceArgs &a, Batch
 // The context's side stream, created on first use (default priority,
 // non-blocking so that a caller on the null stream does not serialize it).
 const SideStream *side_stream(aiwc_ctx *ctx) {
+  if (ctx->single_stream) return nullptr;
   SideStream &S = ctx->side;
   if (!S.s) {
     if (hipStreamCreateWithFlags(&S.s, hipStreamNonBlocking) != hipSuccess ||
@@ -260,11 +263,15 @@ hipError_t enqueue_stages(const TraceArgs &a, const BatchDims &d, hipStream_t s,
     e = aiwc_kernels::launch_ops(a, d, t, pm);
   }
   if (e == hipSuccess) e = aiwc_kernels::launch_branch(a, d, t, pm);
-  if (e == hipSuccess) e = aiwc_kernels::launch_mem(a, d, s, pm);
+  if (e == hipSuccess) e = aiwc_kernels::launch_mem_partition(a, d, s, pm);
+  // the bucket kernel fills every CU's registers and LDS, so nothing of the
+  // side chain could run beside it: it starts once that chain is done
   if (e == hipSuccess && side) {
     e = hipEventRecord(side->join, side->s);
     if (e == hipSuccess) e = hipStreamWaitEvent(s, side->join, 0);
+    AIWC_MARK(pm, "join", s);   // the bucket kernel's span starts after the wait
   }
+  if (e == hipSuccess) e = aiwc_kernels::launch_mem_bucket(a, d, s, pm);
   if (e == hipSuccess) e = aiwc_kernels::launch_finalize(a, d, s, pm);
   return e;
 }
@@ -399,6 +406,9 @@ extern "C" aiwc_status aiwc_context_create(int hip_device, aiwc_ctx **out) {
               hip_device, hipGetErrorString(es));
     return AIWC_ERR_HIP;
   }
+  // AIWC_SINGLE_STREAM=1: every stage on the caller's stream, one after the
+  // other (per-kernel timing without overlap)
+  if (const char *e = getenv("AIWC_SINGLE_STREAM")) c->single_stream = atoi(e) != 0;
   sizer_init(c);
   *out = c;
   return AIWC_OK;

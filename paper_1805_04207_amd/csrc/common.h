@@ -63,6 +63,7 @@ struct TraceArgs {
   u64 large_cap;             // capacity of the ITB / IPT large-value lists
   u64 ops_task;              // events per ops task
   u64 ops_tasks;
+  u64 *ops_wlo;              // [ops_tasks + 1] first work-item of each ops task (or null)
   // scratch (device)
   DevAccum *acc;
   u64 *id_hist;              // [n_ids]
@@ -218,6 +219,10 @@ namespace aiwc_kernels {
 hipError_t launch_zero(const TraceArgs &a, const BatchDims &d, hipStream_t s);
 hipError_t launch_ops(const TraceArgs &a, const BatchDims &d, hipStream_t s, StageMarks *pm);
 hipError_t launch_mem(const TraceArgs &a, const BatchDims &d, hipStream_t s, StageMarks *pm);
+hipError_t launch_mem_partition(const TraceArgs &a, const BatchDims &d, hipStream_t s,
+                                StageMarks *pm);
+hipError_t launch_mem_bucket(const TraceArgs &a, const BatchDims &d, hipStream_t s,
+                             StageMarks *pm);
 hipError_t launch_branch(const TraceArgs &a, const BatchDims &d, hipStream_t s, StageMarks *pm);
 hipError_t launch_finalize(const TraceArgs &a, const BatchDims &d, hipStream_t s, StageMarks *pm);
 u64 scan_blocks_for(u64 n);

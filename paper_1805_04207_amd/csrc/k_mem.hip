@@ -457,11 +457,14 @@ __device__ __forceinline__ void big_node(BucketShared &S, SpecRef G, int s, int 
   if (k == 0) spec_cache_add(S, G, (u32)s, v, 1ull);
 }
 
-// Dense byte-offset counters are stored swizzled: offset o sits at word
-// o ^ (((o >> 5) & 3) << 2), still inside o's group of 16, so that the
-// 16-word groups of eight neighbouring lanes cover all 32 LDS banks (and
-// 16-byte strided offsets spread over 8 banks instead of 2).
-__device__ __forceinline__ u32 cslot(u32 off) { return off ^ (((off >> 5) & 3u) << 2); }
+// Dense byte-offset counters are stored swizzled: offset o of group
+// g = o >> 4 sits at word o ^ cswz(g), still inside its group of 16.  Bits
+// 2..3 of the swizzle, (g >> 1) & 3, make the 16-byte reads of eight
+// neighbouring lanes (lane l reads group l) cover all 32 LDS banks; bits 0..1,
+// (g >> 3) & 3, spread the counting atomics of 4-byte aligned and 16-byte
+// strided offsets over all 32 banks (without them such offsets share 8).
+__device__ __forceinline__ u32 cswz(u32 g) { return (((g >> 1) & 3u) << 2) | ((g >> 3) & 3u); }
+__device__ __forceinline__ u32 cslot(u32 off) { return off ^ cswz(off >> 4); }
 
 // A dense counter's access count.  Counters of staged pages (at most HEAVY
 // records) hold reads | writes << 16 (RW); heavy pages count plainly.
@@ -476,7 +479,7 @@ __device__ __forceinline__ void big_pass(BucketShared &S, SpecRef G, const u32 *
                                          u64 N) {
   const int lane = lane_id();
   const u32 *my = cnt + 16 * lane;
-  const u32 sw = (((u32)lane >> 1) & 3u) << 2;
+  const u32 sw = cswz((u32)lane);
 #pragma unroll 1
   for (int k = 0; k <= 4; ++k) {
 #pragma unroll 1
@@ -511,7 +514,7 @@ template <bool RW>
 __device__ __forceinline__ void big_collect(BucketShared &S, const u32 *cnt, int s) {
   const int lane = lane_id();
   const u32 *my = cnt + 16 * lane;
-  const u32 sw = (((u32)lane >> 1) & 3u) << 2;
+  const u32 sw = cswz((u32)lane);
   const u32 tag = (u32)s << 31;
 #pragma unroll 1
   for (int k = 0; k <= 4; ++k) {
@@ -555,12 +558,17 @@ __device__ __forceinline__ void page_levels(LaneAcc &L, BucketShared &S, SpecRef
   const int lane = lane_id();
   const int s = L.space;
   const uint4 *src = reinterpret_cast<const uint4 *>(cnt + 16 * lane);
-  const u32 sw = ((u32)lane >> 1) & 3u;
+  const u32 sw = cswz((u32)lane);
+  const u32 sh = sw >> 2;                  // which 16-byte chunk
+  const bool s0 = (sw & 1u) != 0, s1 = (sw & 2u) != 0;   // order inside it
   u32 c[16];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    const uint4 x = src[q ^ sw];
-    c[4 * q] = x.x; c[4 * q + 1] = x.y; c[4 * q + 2] = x.z; c[4 * q + 3] = x.w;
+    uint4 x = src[q ^ sh];
+    // element e of the chunk holds position e ^ (sw & 3)
+    u32 a0 = s0 ? x.y : x.x, a1 = s0 ? x.x : x.y, a2 = s0 ? x.w : x.z, a3 = s0 ? x.z : x.w;
+    c[4 * q] = s1 ? a2 : a0; c[4 * q + 1] = s1 ? a3 : a1;
+    c[4 * q + 2] = s1 ? a0 : a2; c[4 * q + 3] = s1 ? a1 : a3;
   }
   // positions and nodes that are empty in every lane (most of them on
   // strided pages) are skipped by the whole wavefront
@@ -1094,6 +1102,24 @@ static void allow_big_lds(K kernel) {
 }
 
 hipError_t launch_mem(const TraceArgs &a, const BatchDims &d, hipStream_t s, StageMarks *pm) {
+  hipError_t e = launch_mem_partition(a, d, s, pm);
+  if (e == hipSuccess) e = launch_mem_bucket(a, d, s, pm);
+  return e;
+}
+
+hipError_t launch_mem_bucket(const TraceArgs &a, const BatchDims &d, hipStream_t s,
+                             StageMarks *pm) {
+  if (!d.any_mem) return hipSuccess;
+  const dim3 gb((unsigned)(d.max_parts < 512 ? d.max_parts : 512), d.n);
+  const TraceArgs *b = d.batch;
+  if (b) hipLaunchKernelGGL(k_mem_bucket<true>, gb, dim3(BK_BLOCK), 0, s, a, b);
+  else hipLaunchKernelGGL(k_mem_bucket<false>, gb, dim3(BK_BLOCK), 0, s, a, b);
+  AIWC_MARK(pm, "k_mem_bucket", s);
+  return hipGetLastError();
+}
+
+hipError_t launch_mem_partition(const TraceArgs &a, const BatchDims &d, hipStream_t s,
+                                StageMarks *pm) {
   if (!d.any_mem) return hipSuccess;
   static bool attrs = false;
   if (!attrs) {
@@ -1105,7 +1131,7 @@ hipError_t launch_mem(const TraceArgs &a, const BatchDims &d, hipStream_t s, Sta
   }
   const size_t lds = (size_t)d.max_parts * 4;
   const dim3 gh((unsigned)d.max_hist_blocks, d.n), gc((unsigned)((d.max_parts + 255) / 256), d.n);
-  const dim3 g1(1, d.n), gb((unsigned)(d.max_parts < 512 ? d.max_parts : 512), d.n);
+  const dim3 g1(1, d.n);
   const TraceArgs *b = d.batch;
   if (b) {
     if (d.vec) hipLaunchKernelGGL((k_mem_hist<true, true>), gh, dim3(MEM_BLOCK), lds, s, a, b);
@@ -1131,9 +1157,6 @@ hipError_t launch_mem(const TraceArgs &a, const BatchDims &d, hipStream_t s, Sta
     else hipLaunchKernelGGL((k_mem_scatter<false, false>), gh, dim3(MEM_BLOCK), lds, s, a, b);
   }
   AIWC_MARK(pm, "k_mem_scatter", s);
-  if (b) hipLaunchKernelGGL(k_mem_bucket<true>, gb, dim3(BK_BLOCK), 0, s, a, b);
-  else hipLaunchKernelGGL(k_mem_bucket<false>, gb, dim3(BK_BLOCK), 0, s, a, b);
-  AIWC_MARK(pm, "k_mem_bucket", s);
   return hipGetLastError();
 }
 

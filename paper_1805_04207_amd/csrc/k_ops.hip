@@ -62,6 +62,17 @@ __host__ __device__ __forceinline__ u32 ops_copies(u32 nid) {
   return nc;
 }
 
+// First work-item of every ops task (the binary searches of all tasks at
+// once, so that no wavefront of k_ops waits on a chain of dependent loads).
+template <bool BATCH>
+__global__ void k_ops_bounds(TraceArgs A0, const TraceArgs *batch) {
+  const TraceArgs A = trace_args<BATCH>(A0, batch);
+  if (!A.ops_wlo) return;
+  const u64 t = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t > A.ops_tasks) return;
+  A.ops_wlo[t] = (t == A.ops_tasks) ? A.n_wi : lower_bound(A.wi_off, A.n_wi + 1, t * A.ops_task);
+}
+
 template <bool LDS_IDS, bool BATCH, bool VEC>
 __global__ void __launch_bounds__(OPS_BLOCK) k_ops(TraceArgs A0, const TraceArgs *batch) {
   extern __shared__ u32 lds[];
@@ -91,9 +102,15 @@ __global__ void __launch_bounds__(OPS_BLOCK) k_ops(TraceArgs A0, const TraceArgs
 
   const u64 nwaves = (u64)gridDim.x * OPS_WAVES;
   for (u64 t = (u64)blockIdx.x * OPS_WAVES + wave; t < A.ops_tasks; t += nwaves) {
-    u64 w_lo = lower_bound(A.wi_off, A.n_wi + 1, t * A.ops_task);
-    u64 w_hi = (t + 1 == A.ops_tasks) ? A.n_wi
-                                      : lower_bound(A.wi_off, A.n_wi + 1, (t + 1) * A.ops_task);
+    u64 w_lo, w_hi;
+    if (A.ops_wlo) {
+      w_lo = A.ops_wlo[t];
+      w_hi = A.ops_wlo[t + 1];
+    } else {
+      w_lo = lower_bound(A.wi_off, A.n_wi + 1, t * A.ops_task);
+      w_hi = (t + 1 == A.ops_tasks) ? A.n_wi
+                                    : lower_bound(A.wi_off, A.n_wi + 1, (t + 1) * A.ops_task);
+    }
     if (w_lo > A.n_wi) w_lo = A.n_wi;
     if (w_hi > A.n_wi) w_hi = A.n_wi;
     if (w_hi <= w_lo) continue;
@@ -133,6 +150,24 @@ __global__ void __launch_bounds__(OPS_BLOCK) k_ops(TraceArgs A0, const TraceArgs
         }
       }
       u32 bm = 0;
+      // whole-wavefront fast path: every lane holds 8 valid ids, so the
+      // table loads and the counting atomics are issued back to back
+      bool fast = false;
+      if (LDS_IDS && VEC && i0 >= e0 && i0 + 8 <= e1) {
+        u32 mx = ids[0];
+#pragma unroll
+        for (int j = 1; j < 8; ++j) mx = ids[j] > mx ? ids[j] : mx;
+        fast = mx < nid;
+      }
+      if (LDS_IDS && __ballot(!fast) == 0) {
+        u32 in[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) in[j] = info[ids[j]];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) atomicAdd(&hist[copy * nid + ids[j]], 1u);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) bm |= ((in[j] & 0xFFu) == KIND_BARRIER ? 1u : 0u) << j;
+      } else
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         const u32 id = ids[j];
@@ -285,6 +320,11 @@ size_t ops_lds_bytes(u32 n_ids) {
 
 hipError_t launch_ops(const TraceArgs &a, const BatchDims &d, hipStream_t s, StageMarks *pm) {
   if (d.max_ops_tasks == 0) return hipSuccess;
+  if (d.batch || a.ops_wlo) {
+    const dim3 gt((unsigned)((d.max_ops_tasks + 1 + 255) / 256), d.n);
+    if (d.batch) hipLaunchKernelGGL(k_ops_bounds<true>, gt, dim3(256), 0, s, a, d.batch);
+    else hipLaunchKernelGGL(k_ops_bounds<false>, gt, dim3(256), 0, s, a, nullptr);
+  }
   u64 waves = d.max_ops_tasks < 4096 ? d.max_ops_tasks : 4096;
   unsigned gx = (unsigned)((waves + OPS_WAVES - 1) / OPS_WAVES);
   if (d.ops_max_blocks && gx > d.ops_max_blocks) gx = d.ops_max_blocks;

@@ -7,7 +7,8 @@ from helpers import random_trace
 
 pytestmark = pytest.mark.gpu
 
-STAGES = {"k_zero", "k_ops", "k_mem_hist", "k_mem_scan", "k_mem_scatter", "k_mem_bucket",
+# "join": the caller's stream waiting for the side stream, before the bucket
+STAGES = {"k_zero", "k_ops", "k_mem_hist", "k_mem_scan", "k_mem_scatter", "join", "k_mem_bucket",
           "k_br_pack", "k_br_sort", "k_br_segments", "k_br_windows", "k_finalize"}
 
 
