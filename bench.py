@@ -22,6 +22,8 @@ HBM_PEAK_GBS = 8000.0
 COPY_BYTES = 1 << 30          # the plain copy that calibrates the traffic counters
 MAIN_STREAM_KERNELS = ("k_zero", "k_mem_hist", "k_mem_scan", "k_mem_scatter", "k_mem_bucket",
                        "k_finalize")
+TARGET_FRAC = 0.60            # the fraction of HBM peak the whole path is asked to reach
+CPU_SHARE = 16                # host threads one GPU's share of the box may use
 
 
 def workload_tag(n_wi_log2: int) -> str:
@@ -268,6 +270,114 @@ def stress_leg(ctx, args, sizing, stream):
             "total_partitions": st["total_partitions"]}
 
 
+def cpu_leg(args):
+    """The C oracle on bounded samples of the benchmarked recipe, on the
+    host's own cores: one thread on one sample trace, then one thread per
+    sample trace on as many traces as the box's share of cores (parallel
+    across traces, as the oracle is meant to scale), median of three runs
+    each.  Trace generation is not timed."""
+    import statistics
+    import threading
+    import oracle
+    import tracegen as tg
+
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    nthr = max(1, min(CPU_SHARE, avail))
+    w = args.cpu_sample_wi_log2
+    hs = [tg.generate_host(tg.config2(seed=1 + 100 * i, n_wi=1 << w)) for i in range(nthr)]
+    ev = [h.opcode.size for h in hs]
+
+    def one():
+        t0 = time.perf_counter()
+        oracle.characterize(hs[0])
+        return time.perf_counter() - t0
+
+    def many():
+        ths = [threading.Thread(target=oracle.characterize, args=(h,)) for h in hs]
+        t0 = time.perf_counter()
+        for t in ths:
+            t.start()
+        for t in ths:
+            t.join()
+        return time.perf_counter() - t0
+
+    t1 = [one() for _ in range(3)]
+    tn = [many() for _ in range(3)]
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"value": sum(ev) / statistics.median(tn), "unit": "events/s", "cores": nthr,
+            "kind": "oracle",
+            "sample": f"{nthr} config2-recipe traces of 2^{w} work-items (seeds 1, 101, ..; "
+                      f"{sum(ev)} events in total), one C-oracle thread per trace, median of 3 "
+                      f"runs; single thread: the first trace ({ev[0]} events)",
+            "single_thread": {"value": ev[0] / statistics.median(t1), "runs_s": t1},
+            "runs_s": tn, "nproc": os.cpu_count(), "threads_available": avail,
+            "cpu_model": model}
+
+
+def config1_leg(ctx, stream, steps):
+    """The small trace (config1 recipe, ~5e5 events): device time per
+    characterization (HIP events, median) and parity with the C oracle."""
+    import statistics
+    import torch
+    import oracle
+    import tracegen as tg
+    import paper_1805_04207_amd as aiwc
+    from oracle.compare import compare
+
+    spec = tg.config1()
+    h = tg.generate_host(spec)
+    dev = aiwc.host_to_device(h, 0)
+    tr = aiwc.device_trace(ctx, dev, h.table, spec.n_sites, spec.history_len, spec.wg_size)
+    got = ctx.characterize(tr, stream).read()
+    bad = compare(got, oracle.characterize(h))
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    dev_us, wall_us = [], []
+    for _ in range(max(10, steps)):
+        t0 = time.perf_counter()
+        e0.record(stream)
+        m = ctx.characterize(tr, stream)
+        e1.record(stream)
+        m.read()
+        wall_us.append(1e6 * (time.perf_counter() - t0))
+        dev_us.append(1e3 * e0.elapsed_time(e1))
+    us = statistics.median(dev_us)
+    return {"events": int(h.opcode.size), "memory_events": int(h.addr.size),
+            "branch_events": int(h.br_site.size), "us_per_characterization": us,
+            "events_per_s": h.opcode.size / (us * 1e-6),
+            "wall_us_with_read": statistics.median(wall_us),
+            "parity_with_oracle": not bad, "mismatches": bad[:5]}
+
+
+def sizing_leg(ctx, args):
+    """The learned part against the method without it (config4 recipe): one
+    batch of held-out config2-family traces (2^10..2^16 work-items) under
+    BOUND, HEURISTIC and LEARNED sizing: partitions (scratch reserved and
+    work), partitions redone after an overflow, time of the batched call;
+    the metrics must be identical."""
+    from paper_1805_04207_amd.train_sizer import DEFAULT_WEIGHTS, evaluate
+    if not os.path.exists(DEFAULT_WEIGHTS):
+        return None
+    ctx.sizer_load(DEFAULT_WEIGHTS)
+    out = evaluate(ctx, args.sizing_traces, 4, 10.0, 16.0, repeats=3)
+    h, l = out["heuristic"], out["learned"]
+    out["learned_over_heuristic"] = {"partitions": l["partitions"] / max(1, h["partitions"]),
+                                     "reserved_bytes": l["reserved_bytes"] /
+                                     max(1, h["reserved_bytes"]),
+                                     "time": l["ms"] / h["ms"]}
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -275,7 +385,11 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n-wi-log2", type=int, default=20, help="work-items = 2^x (config2 recipe)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-wi-log2", type=int, default=17)
+    ap.add_argument("--cpu-sample-wi-log2", type=int, default=15)
+    ap.add_argument("--no-config1", action="store_true", help="skip the small-trace leg")
+    ap.add_argument("--no-sizing", action="store_true",
+                    help="skip the BOUND / HEURISTIC / LEARNED sizing leg")
+    ap.add_argument("--sizing-traces", type=int, default=256)
     ap.add_argument("--no-batch", action="store_true", help="skip the batched legs")
     ap.add_argument("--no-stress", action="store_true", help="skip the stress batch leg")
     ap.add_argument("--batch-traces", type=int, default=512)
@@ -337,6 +451,24 @@ def main() -> int:
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ctx.profile_enable(False)
+    # each kernel alone: a context without the side stream (every stage on
+    # the caller's stream, one after the other), a few steps, HIP events
+    os.environ["AIWC_SINGLE_STREAM"] = "1"
+    ctx1 = aiwc.Context(0)
+    del os.environ["AIWC_SINGLE_STREAM"]
+    tr1 = aiwc.device_trace(ctx1, dev, tg.opcode_table(), spec.n_sites, spec.history_len,
+                            spec.wg_size)
+    ctx1.characterize(tr1, stream).read()
+    ctx1.profile_enable(True)
+    alone = {}
+    t0 = time.perf_counter()
+    for _ in range(max(2, args.steps // 2)):
+        ctx1.characterize(tr1, stream).read()
+        for name, ms in ctx1.profile_read():
+            alone.setdefault(name, []).append(ms)
+    torch.cuda.synchronize()
+    single_ms = 1000.0 * (time.perf_counter() - t0) / max(2, args.steps // 2)
+    del tr1, ctx1
     ms_step = 1000.0 * dt / args.steps
     value = n_ev * args.steps / dt
     passes = (max(1, spec.n_sites - 1).bit_length() + 7) // 8 if spec.n_sites > 1 else 0
@@ -348,8 +480,11 @@ def main() -> int:
     ach = algorithmic_bytes(dom, n_ev, n_wi, n_mem, n_br, passes) / (avg[dom] * 1e-3) / 1e9
     compulsory = 2.0 * n_ev + 9.0 * n_mem + 5.0 * n_br + 8.0 * (n_wi + 1)
     comp_gbs = compulsory / (ms_step * 1e-3) / 1e9
-    print("# per-kernel ms: " + ", ".join(f"{k}={v:.3f}" for k, v in avg.items()),
+    alone_avg = {k: float(np.mean(v)) for k, v in alone.items()}
+    print("# stage spans ms (two streams): " + ", ".join(f"{k}={v:.3f}" for k, v in avg.items()),
           file=sys.stderr, flush=True)
+    print("# kernels alone ms (one stream): " +
+          ", ".join(f"{k}={v:.3f}" for k, v in alone_avg.items()), file=sys.stderr, flush=True)
     from paper_1805_04207_amd.profile_summary import read_traffic
     tpath = os.path.join(ROOT, "profiles", f"traffic_{dom}_{workload_tag(args.n_wi_log2)}.md")
     trec = read_traffic(tpath, dom, workload_tag(args.n_wi_log2))
@@ -369,18 +504,21 @@ def main() -> int:
     if not args.no_batch:
         batched = batch_legs(ctx, tr, spec, n_ev, args, stream)
 
+    small = None
+    if not args.no_config1:
+        small = config1_leg(ctx, stream, args.steps)
+        print(f"# config1: {small['us_per_characterization']:.1f} us, parity "
+              f"{small['parity_with_oracle']}", file=sys.stderr, flush=True)
+
+    sizing = None
+    if not args.no_sizing:
+        sizing = sizing_leg(ctx, args)
+
     cpu = None
     if not args.no_cpu_baseline:
-        import oracle
-        sspec = tg.config2(n_wi=1 << args.cpu_sample_wi_log2)
-        h = tg.generate_host(sspec)
-        t0 = time.perf_counter()
-        oracle.characterize(h)
-        cdt = time.perf_counter() - t0
-        cpu = {"value": h.opcode.size / cdt, "unit": "events/s", "cores": 1, "kind": "oracle",
-               "sample": f"config2 recipe with 2^{args.cpu_sample_wi_log2} work-items "
-                         f"({h.opcode.size} events, {h.addr.size} memory, {h.br_site.size} branch"
-                         f" events), single-threaded C oracle, {cdt:.1f} s"}
+        cpu = cpu_leg(args)
+        print(f"# cpu oracle: {cpu['value']:.3e} events/s on {cpu['cores']} threads, "
+              f"{cpu['single_thread']['value']:.3e} on one", file=sys.stderr, flush=True)
 
     out = {
         "metric": METRIC, "value": value, "unit": "events/s", "n_gpus": 1, "steps": args.steps,
@@ -393,12 +531,20 @@ def main() -> int:
                    "path": "plain per-trace aiwc_characterize", "n_events": n_ev,
                    "compulsory_bytes": compulsory, "compulsory_gbps": comp_gbs,
                    "compulsory_hbm_frac": comp_gbs / HBM_PEAK_GBS,
-                   "kernel_ms": avg, "partitions": r["partitions"],
+                   "stage_span_ms": avg, "kernel_ms_alone": alone_avg,
+                   "ms_per_step_one_stream": single_ms,
+                   "stage_span_note": "two-stream order: spans between HIP events on each "
+                                      "stream, so side-stream spans include waiting for CUs "
+                                      "the memory kernels hold; kernel_ms_alone has each "
+                                      "kernel alone on one stream",
+                   "partitions": r["partitions"],
                    "overflow_redos": r["overflow_redos"], "streamed": streamed,
                    "branch_variants": variants,
-                   "batched": batched},
+                   "batched": batched, "config1": small, "sizing": sizing},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "target_frac": TARGET_FRAC,
+                     "limiter": "on-chip work per record (VALU issue and LDS round trips at "
+                                "two wavefronts per SIMD), not HBM",
                      "traffic": trec["traffic_bytes"] if trec else None,
                      "algorithmic_bytes": algorithmic_bytes(dom, n_ev, n_wi, n_mem, n_br, passes),
                      "kernel_ms": avg[dom]},

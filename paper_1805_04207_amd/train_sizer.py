@@ -56,7 +56,7 @@ def build_dataset(ctx, n: int, seed: int, wi_lo: float, wi_hi: float, batch: int
     return x, y
 
 
-def evaluate(ctx, n: int, seed: int, wi_lo: float, wi_hi: float):
+def evaluate(ctx, n: int, seed: int, wi_lo: float, wi_hi: float, repeats: int = 1):
     """What the network gains: one batch of held-out traces under each sizing
     mode -- partitions (device memory and work), partitions redone after an
     overflow, and the time of the batched call; metrics must not change."""
@@ -76,18 +76,23 @@ def evaluate(ctx, n: int, seed: int, wi_lo: float, wi_hi: float):
     for name, mode in (("bound", SIZING_BOUND), ("heuristic", SIZING_HEURISTIC),
                        ("learned", SIZING_LEARNED)):
         ctx.characterize_batch(trs, sizing=mode)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        res = [m.read() for m in ctx.characterize_batch(trs, sizing=mode)]
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
+        dts = []
+        for _ in range(max(1, repeats)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = [m.read() for m in ctx.characterize_batch(trs, sizing=mode)]
+            torch.cuda.synchronize()
+            dts.append(time.perf_counter() - t0)
+        dt = float(np.median(dts))
         st = ctx.batch_stats()
         key = [json.dumps({k: v for k, v in r.items() if k not in ("overflow_redos", "partitions")},
                           sort_keys=True) for r in res]
         if ref is None:
             ref = key
         out[name] = {"ms": 1e3 * dt, "partitions": st["total_partitions"],
-                     "redo_partitions": st["redo_partitions"], "waves": st["waves"],
+                     "redo_partitions": st["redo_partitions"],
+                     "redo_rate": st["redo_partitions"] / max(1, st["total_partitions"]),
+                     "reserved_bytes": st["reserved_bytes"], "waves": st["waves"],
                      "identical_metrics": key == ref}
         print(f"# eval {name}: {out[name]}", file=sys.stderr, flush=True)
     return out
