@@ -379,6 +379,33 @@ aiwc_status aiwc_stream_append(aiwc_stream *st, const aiwc_trace *chunk, void *s
  * waits for the device).  Errors: INVALID_ARG (null, nothing appended,
  * already finished), OUT_OF_MEMORY, HIP.                                    */
 aiwc_status aiwc_stream_finish(aiwc_stream *st, void *stream, aiwc_metrics **out);
+/* Out-of-core memory stage.  Caps the device memory that finish may use for
+ * the partitioned memory records (12 B per record: the 8-byte partition
+ * record and its 4-byte page tag); 0 = no cap (default).  When the retained
+ * memory stream holds more records than the cap allows, finish reduces it
+ * one group of partitions at a time: a first sweep over the retained stream
+ * counts every partition's records (and each space's reads and writes),
+ * then each group sweeps the stream again, keeps only its partitions'
+ * records and runs the bucket stage on them.  Partitions hold disjoint 1 KiB
+ * pages, so the groups' integer sums are exactly the whole's; the result is
+ * identical to the single pass.  With AIWC_STREAM_HOST_RETAIN the sweeps
+ * move the retained stream from pinned host memory in chunks of at most
+ * 2^22 records, so the device never holds the whole memory stream.  A
+ * single partition larger than the cap is reduced alone (the cap is then
+ * exceeded by it).  The branch stream is still reduced in one pass.
+ * Errors: INVALID_ARG (null, finished stream).                              */
+aiwc_status aiwc_stream_set_device_budget(aiwc_stream *st, uint64_t bytes);
+typedef struct aiwc_stream_stats {
+  uint32_t struct_size;         /* = sizeof(aiwc_stream_stats)               */
+  uint32_t groups;              /* partition groups of the last finish (1:
+                                   one pass over the whole memory stream)   */
+  uint64_t memory_events;       /* retained memory events                    */
+  uint64_t device_records;      /* partition records the device held at once */
+  uint64_t largest_partition;   /* records of the largest partition         */
+} aiwc_stream_stats;
+/* Sizes of the last finish of the stream (host struct).  Errors:
+ * INVALID_ARG (null, struct_size mismatch, not finished).                   */
+aiwc_status aiwc_stream_get_stats(const aiwc_stream *st, aiwc_stream_stats *out);
 /* Release the stream's buffers (waits for the device).  NULL is a no-op. */
 aiwc_status aiwc_stream_destroy(aiwc_stream *st);
 

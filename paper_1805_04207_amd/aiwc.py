@@ -92,6 +92,12 @@ class BatchStats(ctypes.Structure):
                 ("total_partitions", ctypes.c_uint64), ("plan_ms", ctypes.c_double)]
 
 
+class StreamStats(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("groups", ctypes.c_uint32),
+                ("memory_events", ctypes.c_uint64), ("device_records", ctypes.c_uint64),
+                ("largest_partition", ctypes.c_uint64)]
+
+
 class TrainOpts(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("epochs", ctypes.c_uint32),
                 ("batch", ctypes.c_uint32), ("seed", ctypes.c_uint32), ("lr", ctypes.c_float),
@@ -104,6 +110,7 @@ EXPORTS = [
     "aiwc_trace_destroy", "aiwc_characterize", "aiwc_characterize_static",
     "aiwc_characterize_merged",
     "aiwc_stream_create", "aiwc_stream_append", "aiwc_stream_finish", "aiwc_stream_destroy",
+    "aiwc_stream_set_device_budget", "aiwc_stream_get_stats",
     "aiwc_characterize_batch", "aiwc_batch_last_stats",
     "aiwc_metrics_read", "aiwc_metrics_class_hist", "aiwc_metrics_spectrum", "aiwc_metrics_destroy",
     "aiwc_sizer_features", "aiwc_sizer_train", "aiwc_sizer_predict", "aiwc_sizer_grad",
@@ -141,6 +148,8 @@ def load_library(path: str = LIB_PATH):
         "aiwc_stream_append": (st, [vp, vp, vp]),
         "aiwc_stream_finish": (st, [vp, vp, ctypes.POINTER(vp)]),
         "aiwc_stream_destroy": (st, [vp]),
+        "aiwc_stream_set_device_budget": (st, [vp, u64]),
+        "aiwc_stream_get_stats": (st, [vp, ctypes.POINTER(StreamStats)]),
         "aiwc_characterize_batch": (st, [vp, ctypes.POINTER(vp), sz, ctypes.POINTER(BatchOpts), vp,
                                          ctypes.POINTER(vp)]),
         "aiwc_batch_last_stats": (st, [vp, ctypes.POINTER(BatchStats)]),
@@ -389,6 +398,17 @@ class Stream:
     def append(self, chunk: "Trace", stream=None):
         self._keep.append(chunk)
         self.ctx.check(self.ctx.lib.aiwc_stream_append(self.h, chunk.h, _stream_ptr(stream)))
+
+    def set_device_budget(self, nbytes: int):
+        """Cap the device bytes finish may use for partition records (0: no
+        cap); above it the memory stage runs group by group."""
+        self.ctx.check(self.ctx.lib.aiwc_stream_set_device_budget(self.h, int(nbytes)))
+
+    def stats(self) -> Dict:
+        s = StreamStats()
+        s.struct_size = ctypes.sizeof(StreamStats)
+        self.ctx.check(self.ctx.lib.aiwc_stream_get_stats(self.h, ctypes.byref(s)))
+        return _struct_to_dict(s)
 
     def finish(self, stream=None) -> "Metrics":
         m = ctypes.c_void_p()

@@ -54,7 +54,7 @@ static inline u32 ceil_log2(u64 x) {
 // ------------------------------------------------------------------ plan
 // Scratch layout of one trace: a zero region (cleared by a kernel) followed
 // by buffers that every stage fully writes before reading.
-void plan_trace(const aiwc_trace *t, u32 pbits, TracePlan &p, const Tune *tune) {
+void plan_trace(const aiwc_trace *t, u32 pbits, TracePlan &p, const Tune *tune, u64 rec_cap) {
   const aiwc_trace_desc &d = t->d;
   const Tune T = tune ? *tune : Tune();
   p = TracePlan();
@@ -104,8 +104,11 @@ void plan_trace(const aiwc_trace *t, u32 pbits, TracePlan &p, const Tune *tune) 
   p.o_part_hist = take(4ull * p.n_hist_blocks * P);
   p.o_part_off = take(4ull * (P + 1));
   p.o_part_order = take(4ull * P);
-  p.o_part_rec = take(8ull * std::max<u64>(1, d.n_mem));
-  p.o_part_tag = take(4ull * std::max<u64>(1, d.n_mem));
+  // partition records and tags: the whole memory stream, or the largest
+  // group of partitions a stream reduces at once
+  const u64 nrec = std::max<u64>(1, std::min<u64>(d.n_mem, rec_cap));
+  p.o_part_rec = take(8ull * nrec);
+  p.o_part_tag = take(4ull * nrec);
   p.o_ops_wlo = take(8ull * (p.ops_tasks + 1));
   // radix records: site << 1 | outcome (u32), or with the global history
   // site << 33 | history << 1 | outcome (u64)

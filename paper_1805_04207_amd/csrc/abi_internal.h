@@ -111,7 +111,8 @@ struct aiwc_metrics {
 };
 
 void ctx_error(aiwc_ctx *ctx, const char *fmt, ...);
-void plan_trace(const aiwc_trace *t, u32 pbits, TracePlan &p, const Tune *tune = nullptr);
+void plan_trace(const aiwc_trace *t, u32 pbits, TracePlan &p, const Tune *tune = nullptr,
+                u64 rec_cap = ~0ull);
 u32 bound_pbits(u64 n_mem);
 void fill_args(const aiwc_trace *t, const TracePlan &p, char *scratch, char *result,
                TraceArgs &a);

@@ -75,6 +75,8 @@ struct TraceArgs {
   u32 *part_hist;            // [n_hist_blocks][P]
   u32 *part_off;             // [P + 1]
   u32 *part_order;           // [P] bucket-kernel queue order: oversized partitions first
+  u32 part_queue;            // entries of part_order the bucket kernel takes (0: all P)
+  u32 pad1;
   u64 *part_rec;             // [n_mem]
   u32 *part_tag;             // [n_mem] page slot and position of each record (bucket kernel)
   u32 *br_a, *br_b;          // [n_branch] radix ping-pong
@@ -223,6 +225,9 @@ hipError_t launch_mem_partition(const TraceArgs &a, const BatchDims &d, hipStrea
                                 StageMarks *pm);
 hipError_t launch_mem_bucket(const TraceArgs &a, const BatchDims &d, hipStream_t s,
                              StageMarks *pm);
+hipError_t launch_mem_count(const TraceArgs &a, u32 *count, hipStream_t s);
+hipError_t launch_mem_scatter_range(const TraceArgs &a, u32 p0, u32 p1, u32 *cursor, u64 *rec,
+                                    hipStream_t s);
 hipError_t launch_branch(const TraceArgs &a, const BatchDims &d, hipStream_t s, StageMarks *pm);
 hipError_t launch_finalize(const TraceArgs &a, const BatchDims &d, hipStream_t s, StageMarks *pm);
 u64 scan_blocks_for(u64 n);

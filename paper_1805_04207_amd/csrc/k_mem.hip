@@ -212,6 +212,74 @@ __global__ void __launch_bounds__(MEM_BLOCK) k_mem_scatter(TraceArgs A0, const T
   }
 }
 
+// ------------------------------------------------- partition groups (streams)
+// A stream whose memory events exceed the device budget is reduced one
+// group of partitions at a time (partitions hold disjoint pages, so the
+// groups' sums are the whole's).  k_mem_count: per-partition record counts
+// and the per-space read / write totals of one chunk of the memory stream,
+// added to the stream's totals.  k_mem_scatter_range: the records of one
+// chunk whose partition lies in [p0, p1) go to their partition's range of
+// the group's record array (cursor[p], advanced by one reservation per
+// block and partition).
+constexpr int GRP_BLOCK = 1024;
+
+__global__ void __launch_bounds__(GRP_BLOCK) k_mem_count(TraceArgs A, u32 *count) {
+  extern __shared__ u32 h[];   // [P]
+  __shared__ u64 sp_cnt[4];
+  const u32 P = 1u << A.pbits;
+  for (u32 i = threadIdx.x; i < P; i += GRP_BLOCK) h[i] = 0;
+  if (threadIdx.x < 4) sp_cnt[threadIdx.x] = 0;
+  __syncthreads();
+  u32 cnt[4] = {0, 0, 0, 0};
+  for (u64 i = (u64)blockIdx.x * GRP_BLOCK + threadIdx.x; i < A.n_mem;
+       i += (u64)gridDim.x * GRP_BLOCK) {
+    const uint8_t k = A.mem_kind[i];
+    u32 bin;
+    make_record(A.addr[i], k, A.pbits, bin);
+    atomicAdd(&h[bin], 1u);
+    cnt[((k >> 1) & 1u) * 2 + (k & 1u)] += 1;
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const u64 v = wave_sum_u64(cnt[j]);
+    if (lane_id() == 0 && v) atomicAdd(&sp_cnt[j], v);
+  }
+  __syncthreads();
+  for (u32 i = threadIdx.x; i < P; i += GRP_BLOCK)
+    if (h[i]) atomicAdd(&count[i], h[i]);
+  if (threadIdx.x < 4 && sp_cnt[threadIdx.x]) {
+    u64 *dst = (threadIdx.x & 1) ? &A.acc->sp_writes[threadIdx.x >> 1]
+                                 : &A.acc->sp_reads[threadIdx.x >> 1];
+    atomicAdd(dst, sp_cnt[threadIdx.x]);
+  }
+}
+
+__global__ void __launch_bounds__(GRP_BLOCK) k_mem_scatter_range(TraceArgs A, u32 p0, u32 p1,
+                                                                 u32 *cursor, u64 *rec) {
+  extern __shared__ u32 h[];   // [p1 - p0]: counts, then this block's cursors
+  const u32 np = p1 - p0;
+  for (u32 i = threadIdx.x; i < np; i += GRP_BLOCK) h[i] = 0;
+  __syncthreads();
+  // the block's slice of the chunk
+  const u64 per = (A.n_mem + gridDim.x - 1) / gridDim.x;
+  const u64 c0 = (u64)blockIdx.x * per;
+  const u64 c1 = c0 + per < A.n_mem ? c0 + per : A.n_mem;
+  for (u64 i = c0 + threadIdx.x; i < c1; i += GRP_BLOCK) {
+    u32 bin;
+    make_record(A.addr[i], A.mem_kind[i], A.pbits, bin);
+    if (bin >= p0 && bin < p1) atomicAdd(&h[bin - p0], 1u);
+  }
+  __syncthreads();
+  for (u32 i = threadIdx.x; i < np; i += GRP_BLOCK)
+    if (h[i]) h[i] = atomicAdd(&cursor[p0 + i], h[i]);
+  __syncthreads();
+  for (u64 i = c0 + threadIdx.x; i < c1; i += GRP_BLOCK) {
+    u32 bin;
+    const u64 r = make_record(A.addr[i], A.mem_kind[i], A.pbits, bin);
+    if (bin >= p0 && bin < p1) rec[atomicAdd(&h[bin - p0], 1u)] = r;
+  }
+}
+
 // ---------------------------------------------------------------- bucket
 // One block per partition at a time (persistent, partitions from a queue).
 //  1. page pass   : an LDS table of the partition's pages (record >> 11, which
@@ -704,10 +772,11 @@ __global__ void __launch_bounds__(BK_BLOCK) k_mem_bucket(TraceArgs A0, const Tra
   if (tid == 0) { S.redos = 0; S.npages = 0; S.overflow = 0; S.nblist = 0; }
   __syncthreads();
 
+  const u32 Q = A.part_queue ? A.part_queue : P;   // entries of part_order to take
   while (true) {
     if (tid == 0) S.work = (u32)atomicAdd(&A.acc->mem_queue, 1ull);
     __syncthreads();
-    if (S.work >= P) break;
+    if (S.work >= Q) break;
     const u32 p = A.part_order[S.work];
     const u64 base = A.part_off[p];
     const u32 n = A.part_off[p + 1] - (u32)base;
@@ -1115,6 +1184,28 @@ hipError_t launch_mem_bucket(const TraceArgs &a, const BatchDims &d, hipStream_t
   if (b) hipLaunchKernelGGL(k_mem_bucket<true>, gb, dim3(BK_BLOCK), 0, s, a, b);
   else hipLaunchKernelGGL(k_mem_bucket<false>, gb, dim3(BK_BLOCK), 0, s, a, b);
   AIWC_MARK(pm, "k_mem_bucket", s);
+  return hipGetLastError();
+}
+
+hipError_t launch_mem_count(const TraceArgs &a, u32 *count, hipStream_t s) {
+  if (a.n_mem == 0) return hipSuccess;
+  static bool attr = false;
+  if (!attr) { allow_big_lds(k_mem_count); attr = true; }
+  const u64 want = (a.n_mem + 16383) / 16384;
+  const unsigned g = (unsigned)(want < 1024 ? (want ? want : 1) : 1024);
+  hipLaunchKernelGGL(k_mem_count, dim3(g), dim3(GRP_BLOCK), (size_t)4 << a.pbits, s, a, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_mem_scatter_range(const TraceArgs &a, u32 p0, u32 p1, u32 *cursor, u64 *rec,
+                                    hipStream_t s) {
+  if (a.n_mem == 0 || p1 <= p0) return hipSuccess;
+  static bool attr = false;
+  if (!attr) { allow_big_lds(k_mem_scatter_range); attr = true; }
+  const u64 want = (a.n_mem + 16383) / 16384;
+  const unsigned g = (unsigned)(want < 1024 ? (want ? want : 1) : 1024);
+  hipLaunchKernelGGL(k_mem_scatter_range, dim3(g), dim3(GRP_BLOCK), (size_t)4 * (p1 - p0), s, a,
+                     p0, p1, cursor, rec);
   return hipGetLastError();
 }
 

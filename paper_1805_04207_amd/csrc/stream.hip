@@ -13,6 +13,7 @@
 // result is exactly that of the concatenated trace.
 #include <algorithm>
 #include <cstring>
+#include <vector>
 
 #include "abi_internal.h"
 
@@ -92,6 +93,11 @@ struct aiwc_stream {
   GrowBuf itb_large, ipt_large;     // values >= VAL_DENSE, 8 B each
   GrowBuf addr, kind, site, taken;  // retained memory and branch streams
   GrowBuf staged;                   // device copy of host-held streams at finish
+  // out-of-core memory stage
+  u64 budget = 0;                   // device bytes for partition records (0: no cap)
+  GrowBuf grp;                      // counts | cursors | space totals (device)
+  GrowBuf mstage;                   // device chunk of a host-held memory stream
+  aiwc_stream_stats stats{};
 };
 
 extern "C" aiwc_status aiwc_stream_destroy(aiwc_stream *st);
@@ -239,6 +245,151 @@ extern "C" aiwc_status aiwc_stream_append(aiwc_stream *st, const aiwc_trace *t, 
   return AIWC_OK;
 }
 
+extern "C" aiwc_status aiwc_stream_set_device_budget(aiwc_stream *st, uint64_t bytes) {
+  aiwc_ctx *ctx = st ? st->ctx : nullptr;
+  if (!st) { ctx_error(nullptr, "aiwc_stream_set_device_budget: NULL stream"); return AIWC_ERR_INVALID_ARG; }
+  if (st->finished) { ctx_error(ctx, "aiwc_stream_set_device_budget: the stream is finished"); return AIWC_ERR_INVALID_ARG; }
+  st->budget = bytes;
+  return AIWC_OK;
+}
+
+extern "C" aiwc_status aiwc_stream_get_stats(const aiwc_stream *st, aiwc_stream_stats *out) {
+  aiwc_ctx *ctx = st ? st->ctx : nullptr;
+  if (!st || !out || out->struct_size != sizeof(aiwc_stream_stats)) {
+    ctx_error(ctx, "aiwc_stream_get_stats: NULL argument or struct_size mismatch");
+    return AIWC_ERR_INVALID_ARG;
+  }
+  if (!st->finished) { ctx_error(ctx, "aiwc_stream_get_stats: the stream is not finished"); return AIWC_ERR_INVALID_ARG; }
+  *out = st->stats;
+  return AIWC_OK;
+}
+
+// The memory stage of a finish whose memory stream exceeds the device
+// budget: count every partition's records over the retained stream, cut the
+// partitions into contiguous groups of at most `cap` records, then per
+// group sweep the stream again, scatter the group's records and run the
+// bucket kernel over the group's partitions (largest first).  The
+// accumulators of all groups add up to those of one pass.
+static aiwc_status grouped_memory_stage(aiwc_stream *st, aiwc_trace &mt, u64 cap, hipStream_t s,
+                                        aiwc_metrics **out_m, TraceArgs &a, BatchDims &dims) {
+  aiwc_ctx *ctx = st->ctx;
+  const u64 n_mem = mt.d.n_mem;
+  const u32 pbits = bound_pbits(n_mem);
+  const u64 P = 1ull << pbits;
+  auto al = [](u64 x) { return (x + 255) & ~255ull; };
+  const u64 o_cur = al(4 * P), o_tot = o_cur + al(4 * P), gbytes = o_tot + al(sizeof(DevAccum));
+  aiwc_status rc = grow(ctx, st->grp, gbytes, s);
+  if (rc != AIWC_OK) return rc;
+  const bool host = st->addr.host;
+  const u64 C = std::min<u64>(n_mem, 1ull << 22);   // records per sweep chunk
+  if (host && (rc = grow(ctx, st->mstage, 9 * C, s)) != AIWC_OK) return rc;
+  u32 *cnt_d = (u32 *)st->grp.p, *cur_d = (u32 *)(st->grp.p + o_cur);
+  DevAccum *tot_d = (DevAccum *)(st->grp.p + o_tot);
+  {
+    TraceArgs z;
+    memset(&z, 0, sizeof z);
+    z.zero_base = st->grp.p;
+    z.zero_bytes = gbytes;
+    BatchDims zd;
+    zd.max_zero16 = gbytes / 16;
+    ST_HIP_OR(ctx, aiwc_kernels::launch_zero(z, zd, s));
+  }
+  // one chunk of the retained memory stream as kernel arguments
+  auto chunk = [&](u64 i0, TraceArgs &ac) -> hipError_t {
+    const u64 n = std::min<u64>(C, n_mem - i0);
+    ac.n_mem = n;
+    if (!host) {
+      ac.addr = (const u64 *)st->addr.p + i0;
+      ac.mem_kind = (const uint8_t *)st->kind.p + i0;
+      return hipSuccess;
+    }
+    hipError_t e = hipMemcpyAsync(st->mstage.p, st->addr.p + 8 * i0, 8 * n, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(st->mstage.p + 8 * C, st->kind.p + i0, n, hipMemcpyHostToDevice, s);
+    ac.addr = (const u64 *)st->mstage.p;
+    ac.mem_kind = (const uint8_t *)(st->mstage.p + 8 * C);
+    return e;
+  };
+  TraceArgs ac;
+  memset(&ac, 0, sizeof ac);
+  ac.pbits = pbits;
+  ac.acc = tot_d;
+  for (u64 i0 = 0; i0 < n_mem; i0 += C) {
+    ST_HIP_OR(ctx, chunk(i0, ac));
+    ST_HIP_OR(ctx, aiwc_kernels::launch_mem_count(ac, cnt_d, s));
+  }
+  std::vector<u32> cnt(P);
+  ST_HIP_OR(ctx, hipMemcpyAsync(cnt.data(), cnt_d, 4 * P, hipMemcpyDeviceToHost, s));
+  ST_HIP_OR(ctx, hipStreamSynchronize(s));
+  u64 maxp = 0;
+  for (u32 c : cnt) maxp = std::max<u64>(maxp, c);
+  const u64 cap_eff = std::max<u64>(cap, maxp);
+  std::vector<std::pair<u32, u32>> groups;
+  for (u64 p0 = 0, acc = 0, p = 0; p < P; ++p) {
+    if (acc + cnt[p] > cap_eff && p > p0) { groups.push_back({(u32)p0, (u32)p}); p0 = p; acc = 0; }
+    acc += cnt[p];
+    if (p + 1 == P) groups.push_back({(u32)p0, (u32)P});
+  }
+  // the plan with room for the largest group only
+  TracePlan p;
+  plan_trace(&mt, pbits, p, nullptr, cap_eff);
+  if ((rc = ensure_arena(ctx, p.scratch_bytes)) != AIWC_OK) return rc;
+  aiwc_metrics *m = nullptr;
+  if ((rc = new_metrics(ctx, &mt, p, &m)) != AIWC_OK) return rc;
+  if (ctx->last_done) ST_HIP_OR(ctx, hipStreamWaitEvent(s, ctx->last_done, 0));
+  fill_args(&mt, p, ctx->arena, (char *)m->buf, a);
+  a.addr = nullptr;        // the memory stream reaches the kernels by chunks only
+  a.mem_kind = nullptr;
+  point_at_state(st, a);
+  add_dims(&mt, p, a, dims);
+  hipError_t e = aiwc_kernels::launch_zero(a, dims, s);
+  // each space's accesses over the whole stream (the N of every entropy term)
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(&a.acc->sp_reads[0], &tot_d->sp_reads[0], 4 * sizeof(u64),
+                       hipMemcpyDeviceToDevice, s);
+  std::vector<u32> off(P + 1), order;
+  const u64 zero = 0;
+  for (size_t g = 0; g < groups.size() && e == hipSuccess; ++g) {
+    const u32 p0 = groups[g].first, p1 = groups[g].second;
+    std::fill(off.begin(), off.end(), 0u);
+    order.clear();
+    u32 run = 0;
+    for (u32 q = p0; q < p1; ++q) {
+      off[q] = run;
+      run += cnt[q];
+      if (cnt[q]) order.push_back(q);
+    }
+    off[p1] = run;
+    if (order.empty()) continue;
+    std::sort(order.begin(), order.end(), [&](u32 x, u32 y) { return cnt[x] > cnt[y]; });
+    // the previous group's kernels read these arrays: wait for them
+    e = hipStreamSynchronize(s);
+    if (e == hipSuccess) e = hipMemcpy(a.part_off, off.data(), 4 * (P + 1), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(a.part_order, order.data(), 4 * order.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(cur_d, off.data(), 4 * P, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(&a.acc->mem_queue, &zero, 8, hipMemcpyHostToDevice);
+    for (u64 i0 = 0; i0 < n_mem && e == hipSuccess; i0 += C) {
+      e = chunk(i0, ac);
+      if (e == hipSuccess)
+        e = aiwc_kernels::launch_mem_scatter_range(ac, p0, p1, cur_d, a.part_rec, s);
+    }
+    TraceArgs ag = a;
+    ag.part_queue = (u32)order.size();
+    if (e == hipSuccess) e = aiwc_kernels::launch_mem_bucket(ag, dims, s, nullptr);
+  }
+  if (e != hipSuccess) {
+    ctx_error(ctx, "the grouped memory stage failed: %s", hipGetErrorString(e));
+    hipStreamSynchronize(s);
+    aiwc_metrics_destroy(m);
+    return AIWC_ERR_HIP;
+  }
+  st->stats.groups = (u32)groups.size();
+  st->stats.device_records = std::min<u64>(n_mem, cap_eff);
+  st->stats.largest_partition = maxp;
+  *out_m = m;
+  return AIWC_OK;
+}
+
 extern "C" aiwc_status aiwc_stream_finish(aiwc_stream *st, void *stream, aiwc_metrics **out) {
   aiwc_ctx *ctx = st ? st->ctx : nullptr;
   if (!st || !out) { ctx_error(ctx, "aiwc_stream_finish: NULL argument"); return AIWC_ERR_INVALID_ARG; }
@@ -261,6 +412,53 @@ extern "C" aiwc_status aiwc_stream_finish(aiwc_stream *st, void *stream, aiwc_me
   mt.d.n_branch = st->taken.used;
   mt.d.br_site = (const uint32_t *)st->site.p;
   mt.d.br_taken = (const uint8_t *)st->taken.p;
+  st->stats = aiwc_stream_stats{};
+  st->stats.struct_size = sizeof(aiwc_stream_stats);
+  st->stats.memory_events = mt.d.n_mem;
+  const u64 cap = st->budget ? std::max<u64>(1, st->budget / 12) : ~0ull;
+  if (mt.d.n_mem > cap) {
+    // out of core: the branch stream comes to the device, the memory stream
+    // is swept in chunks by the grouped stage
+    if (st->site.host) {
+      auto al = [](u64 x) { return (x + 255) & ~255ull; };
+      const u64 o_taken = al(st->site.used), total = o_taken + al(st->taken.used);
+      aiwc_status rc0 = grow(ctx, st->staged, total, s);
+      if (rc0 != AIWC_OK) return rc0;
+      if (st->site.used)
+        ST_HIP_OR(ctx, hipMemcpyAsync(st->staged.p, st->site.p, st->site.used, hipMemcpyHostToDevice, s));
+      if (st->taken.used)
+        ST_HIP_OR(ctx, hipMemcpyAsync(st->staged.p + o_taken, st->taken.p, st->taken.used,
+                                      hipMemcpyHostToDevice, s));
+      mt.d.br_site = (const uint32_t *)st->staged.p;
+      mt.d.br_taken = (const uint8_t *)(st->staged.p + o_taken);
+    }
+    mt.d.n_sites = st->n_sites;
+    mt.n_classes = st->proto.n_classes;
+    mt.dev_info = st->proto.dev_info;
+    TraceArgs a;
+    BatchDims dims;
+    aiwc_metrics *m = nullptr;
+    aiwc_status rc = grouped_memory_stage(st, mt, cap, s, &m, a, dims);
+    if (rc != AIWC_OK) { mt.dev_info = nullptr; return rc; }
+    StageMarks *pm = nullptr;
+    if (ctx->prof.on) { ctx->prof.begin(s); pm = &ctx->prof; }
+    hipError_t e = aiwc_kernels::launch_branch(a, dims, s, pm);
+    if (e == hipSuccess) e = aiwc_kernels::launch_finalize(a, dims, s, pm);
+    mt.dev_info = nullptr;
+    if (e != hipSuccess) {
+      ctx_error(ctx, "kernel launch failed: %s", hipGetErrorString(e));
+      aiwc_metrics_destroy(m);
+      return AIWC_ERR_HIP;
+    }
+    ST_HIP_OR(ctx, hipEventRecord(m->done, s));
+    if (!ctx->last_done) ST_HIP_OR(ctx, hipEventCreateWithFlags(&ctx->last_done, hipEventDisableTiming));
+    ST_HIP_OR(ctx, hipEventRecord(ctx->last_done, s));
+    st->finished = true;
+    *out = m;
+    return AIWC_OK;
+  }
+  st->stats.groups = 1;
+  st->stats.device_records = mt.d.n_mem;
   if (st->addr.host) {
     // the retained streams come onto the device now, 256-byte aligned
     auto al = [](u64 x) { return (x + 255) & ~255ull; };
@@ -320,7 +518,7 @@ extern "C" aiwc_status aiwc_stream_destroy(aiwc_stream *st) {
   hipSetDevice(st->ctx->device);
   hipDeviceSynchronize();
   for (GrowBuf *b : {&st->itb_large, &st->ipt_large, &st->addr, &st->kind, &st->site, &st->taken,
-                     &st->staged})
+                     &st->staged, &st->grp, &st->mstage})
     release(*b);
   if (st->core) hipFree(st->core);
   if (st->proto.dev_info) hipFree(st->proto.dev_info);

@@ -6,7 +6,7 @@ import pytest
 
 import oracle
 from oracle.compare import compare
-from helpers import mk, random_trace
+from helpers import mem_trace, mk, random_trace
 
 pytestmark = pytest.mark.gpu
 
@@ -156,3 +156,65 @@ def test_streams_retained_in_host_memory(hint):
     trs = [random_trace(rng, 8, 2000, 40, 12, addr_bits=22) for _ in range(40)]
     trs[3] = mk(np.zeros(0, dtype=np.uint16), [], m=12)
     check(trs, hint=hint, host=True)
+
+
+def _budget_stream(trs, budget, host):
+    import paper_1805_04207_amd as aiwc
+    from gpu_util import ctx
+    c = ctx()
+    st = c.stream(host_retain=host)
+    st.set_device_budget(budget)
+    keep = []
+    for tr in trs:
+        dev = aiwc.host_to_device(tr, 0)
+        h = aiwc.device_trace(c, dev, tr.table, int(tr.n_sites), int(tr.history_len))
+        keep += [dev, h]
+        st.append(h)
+    m = st.finish()
+    return st, m, keep
+
+
+@pytest.mark.parametrize("host", [False, True])
+def test_out_of_core_memory_stage(host):
+    # the memory stream reduced one partition group at a time under a device
+    # budget of a quarter of its records: identical to the oracle on the
+    # concatenation, while the device holds at most a group's records
+    rng = np.random.default_rng(4242 + int(host))
+    trs = [random_trace(rng, 40, 3000, 400, 16, addr_bits=b, p_local=0.3)
+           for b in (12, 20, 28, 34)]
+    n_mem = sum(t.addr.size for t in trs)
+    st, m, keep = _budget_stream(trs, 12 * (n_mem // 4), host)
+    got = m.read()
+    s = st.stats()
+    print("groups", s["groups"], "device records", s["device_records"], "of", n_mem, flush=True)
+    assert s["memory_events"] == n_mem
+    assert s["groups"] >= 3 and s["device_records"] < n_mem
+    mt = oracle.MergedTrace(trs)
+    bad = compare(got, oracle.characterize(mt))
+    assert not bad, "\n".join(bad[:20])
+    for sp in (0, 1):
+        assert m.spectrum(sp) == oracle.spectrum(mt, sp, 0), f"spectrum space {sp}"
+    # and the same chunks in one pass give the identical result
+    from gpu_util import same
+    st1, m1, keep1 = _budget_stream(trs, 0, host)
+    assert st1.stats()["groups"] == 1
+    assert same(m1.read(), got, drop=("overflow_redos",))
+
+
+def test_out_of_core_with_a_partition_above_the_budget():
+    # one hot page (tens of thousands of accesses to 64 words) holds more
+    # records than the budget: its partition is reduced alone, the rest in
+    # groups, and the result is still exact
+    rng = np.random.default_rng(77)
+    hot = mem_trace(np.uint64(0x4000) + 4 * rng.integers(0, 64, size=40000).astype(np.uint64),
+                    (rng.random(40000) < 0.5).astype(np.uint8))
+    cold = random_trace(rng, 30, 2000, 50, 16, addr_bits=32, p_local=0.2)
+    trs = [cold, hot, cold]
+    n_mem = sum(t.addr.size for t in trs)
+    st, m, keep = _budget_stream(trs, 12 * 2000, True)
+    s = st.stats()
+    assert s["largest_partition"] >= 40000 and s["device_records"] >= 40000
+    assert s["groups"] >= 2 and s["memory_events"] == n_mem
+    mt = oracle.MergedTrace(trs)
+    bad = compare(m.read(), oracle.characterize(mt))
+    assert not bad, "\n".join(bad[:20])
