@@ -219,7 +219,23 @@ def stream_leg(ctx, dev, spec, n_ev, args, stream, ref):
     torch.cuda.synchronize()
     dt_h = time.perf_counter() - t0
     st.close()
+    # out of core: retained in pinned host memory, a quarter of the partition
+    # records on the device at a time
+    st = ctx.stream(host_retain=True)
+    st.set_device_budget(12 * (dev["n_mem"] // 4))
+    t0 = time.perf_counter()
+    for c in chunks:
+        st.append(c, stream)
+    got_o = st.finish(stream).read()
+    torch.cuda.synchronize()
+    dt_o = time.perf_counter() - t0
+    so = st.stats()
+    st.close()
     return {"chunks": k, "ms": 1e3 * dt, "events_per_s": n_ev / dt,
+            "out_of_core": {"ms": 1e3 * dt_o, "groups": so["groups"],
+                            "device_records": so["device_records"],
+                            "memory_events": so["memory_events"],
+                            "identical": strip(got_o) == strip(ref)},
             "host_retained_ms": 1e3 * dt_h, "host_retained_identical": strip(got_h) == strip(ref),
             "retained_bytes": 9 * dev["n_mem"] + 5 * dev["n_branch"],
             "input_bytes": 2 * n_ev + 8 * (spec.n_wi + 1) + 9 * dev["n_mem"] + 5 * dev["n_branch"],

@@ -109,6 +109,9 @@ void plan_trace(const aiwc_trace *t, u32 pbits, TracePlan &p, const Tune *tune, 
   const u64 nrec = std::max<u64>(1, std::min<u64>(d.n_mem, rec_cap));
   p.o_part_rec = take(8ull * nrec);
   p.o_part_tag = take(4ull * nrec);
+  // the two-level scatter: coarse-bucket records and the cursors
+  p.o_part_tmp = (d.n_mem && p.pbits >= TWO_LEVEL_PBITS) ? take(8ull * nrec) : 0;
+  p.o_part_cur = take(4ull * (P + 512));
   p.o_ops_wlo = take(8ull * (p.ops_tasks + 1));
   // radix records: site << 1 | outcome (u32), or with the global history
   // site << 33 | history << 1 | outcome (u64)
@@ -180,6 +183,8 @@ void fill_args(const aiwc_trace *t, const TracePlan &p, char *scratch, char *res
   a.part_order = (u32 *)(scratch + p.o_part_order);
   a.part_rec = (u64 *)(scratch + p.o_part_rec);
   a.part_tag = (u32 *)(scratch + p.o_part_tag);
+  a.part_tmp = p.o_part_tmp ? (u64 *)(scratch + p.o_part_tmp) : nullptr;
+  a.part_cur = (u32 *)(scratch + p.o_part_cur);
   a.br_a = (u32 *)(scratch + p.o_br_a);
   a.br_b = (u32 *)(scratch + p.o_br_b);
   a.br_cnt = (u32 *)(scratch + p.o_br_cnt);
@@ -208,6 +213,7 @@ void add_dims(const aiwc_trace *t, const TracePlan &p, const TraceArgs &a, Batch
     d.any_mem = true;
     d.max_hist_blocks = std::max<u64>(d.max_hist_blocks, p.n_hist_blocks);
     d.max_parts = std::max<u64>(d.max_parts, 1ull << p.pbits);
+    if (a.part_tmp) d.any_two_level = true; else d.any_one_level = true;
     if ((uintptr_t)a.addr % 16 || (uintptr_t)a.mem_kind % 8) d.vec = false;
   }
   if (D.n_branch) {

@@ -18,6 +18,7 @@ typedef unsigned int u32;
 #define SPEC_DENSE 256       // level-0 spectrum kept densely for f < 256
 #define AIWC_STAGE_CAP 16384 // records the bucket kernel stages on chip per round
 #define VAL_DENSE 65536      // ITB / IPT value histograms are dense below this
+#define TWO_LEVEL_PBITS 12   // partitions from 2^12 on are scattered in two passes
 struct DevAccum {
   u64 itb_min_inv, itb_max, itb_cnt, itb_sum;   // min stored as max of ~v
   u64 ipt_min_inv, ipt_max, ipt_cnt, ipt_sum;
@@ -78,6 +79,8 @@ struct TraceArgs {
   u32 part_queue;            // entries of part_order the bucket kernel takes (0: all P)
   u32 pad1;
   u64 *part_rec;             // [n_mem]
+  u64 *part_tmp;             // [n_mem] coarse-bucket records of the two-level scatter (or null)
+  u32 *part_cur;             // [P + 512] fine cursors, coarse cursors, coarse tile starts
   u32 *part_tag;             // [n_mem] page slot and position of each record (bucket kernel)
   u32 *br_a, *br_b;          // [n_branch] radix ping-pong
   u32 *br_cnt;               // [256 * br_tiles]
@@ -210,6 +213,7 @@ struct BatchDims {
   u64 ops_lds = 0;                    // dynamic LDS of the ops kernel (max over traces)
   u32 ops_max_blocks = 0;             // cap on the ops grid (0 = none)
   bool any_mem = false, any_branch = false;
+  bool any_two_level = false, any_one_level = false;   // memory scatter paths in use
   bool any_local = false, any_global = false;   // branch history variants present
   bool any_pattern = false;                     // some trace wants the pattern entropy
   u32 max_pattern_bins = 0;

@@ -33,6 +33,10 @@
 namespace {
 
 constexpr int MEM_BLOCK = 1024;
+// two-level scatter: coarse buckets of 256 partitions, then the partitions
+constexpr u32 FINE_BITS = 8;
+constexpr int SC_BLOCK = 1024;
+constexpr u32 SC_T = 8192;                 // records per tile (8 per thread)
 constexpr u32 SPEC_SLOTS = 64;    // per-space LDS cache of the level-0 spectrum
 constexpr u64 EMPTY = ~0ull;
 
@@ -167,6 +171,185 @@ __global__ void __launch_bounds__(1024) k_mem_binscan(TraceArgs A0, const TraceA
   for (u32 i = threadIdx.x; i < P; i += 1024)
     if (A.part_off[i + 1] - A.part_off[i] <= AIWC_STAGE_CAP)
       A.part_order[nb + atomicAdd(&nsmall, 1u)] = i;
+  if (!A.part_tmp) return;
+  // two-level scatter: fine cursors (one per partition), coarse cursors
+  // (one per 256 partitions), and where each coarse bucket's tiles start
+  const u32 NC = P >> FINE_BITS;
+  u32 *fcur = A.part_cur, *ccur = A.part_cur + P, *tst = A.part_cur + P + NC;
+  for (u32 i = threadIdx.x; i < P; i += 1024) fcur[i] = A.part_off[i];
+  for (u32 c = threadIdx.x; c < NC; c += 1024) ccur[c] = A.part_off[c << FINE_BITS];
+  if (threadIdx.x == 0) {
+    u32 t = 0;
+    for (u32 c = 0; c < NC; ++c) {
+      tst[c] = t;
+      const u32 sz = A.part_off[(c + 1) << FINE_BITS] - A.part_off[c << FINE_BITS];
+      t += (sz + SC_T - 1) / SC_T;
+    }
+    tst[NC] = t;
+  }
+}
+
+// ------------------------------------------------------ two-level scatter
+// With 2^15 partitions one pass cannot write coalesced runs: a block's
+// records of one partition are a few 8-byte stores among 32768 open
+// destinations.  From 2^12 partitions on the records go through two
+// passes instead.  Each pass takes tiles of SC_T records, counts them per
+// digit in LDS, reserves every digit's range of the destination with one
+// atomic on its cursor, sorts the tile by digit in LDS and writes it out in
+// runs: pass A to 2^(pbits-8) coarse buckets (the record carries its fine
+// digit in bits 56..63), pass B within each coarse bucket to its 256
+// partitions.  Record order inside a partition is free.
+struct TileShared {
+  u64 stage[SC_T];
+  uint8_t dig[SC_T];
+  u32 cnt[256], start[256], gbase[256];
+  u32 tst[257];
+};
+
+// Exclusive prefix of cnt[0..256) into start[] (one wavefront, 4 per lane).
+__device__ __forceinline__ void tile_scan(TileShared &S) {
+  const int l = lane_id();
+  const u32 a = S.cnt[4 * l], b = S.cnt[4 * l + 1], c = S.cnt[4 * l + 2], d = S.cnt[4 * l + 3];
+  u32 x = a + b + c + d;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const u32 y = __shfl_up(x, o, 64);
+    if (l >= o) x += y;
+  }
+  const u32 e = x - (a + b + c + d);
+  S.start[4 * l] = e;
+  S.start[4 * l + 1] = e + a;
+  S.start[4 * l + 2] = e + a + b;
+  S.start[4 * l + 3] = e + a + b + c;
+}
+
+// Stage the tile's records by digit and write them out in runs: dst[gbase[d]
+// + rank among the tile's records of digit d].  Every thread calls it with
+// its own records (nv of them, digits dg).
+template <int R>
+__device__ __forceinline__ void tile_write(TileShared &S, const u64 (&rec)[R], const u32 (&dg)[R],
+                                           int nv, u32 n, u64 *dst, u32 ndig, u32 *cursor) {
+  const int tid = threadIdx.x;
+  __syncthreads();
+  if (tid < 64) tile_scan(S);
+  __syncthreads();
+  if (tid < (int)ndig) {
+    const u32 c = S.cnt[tid];
+    if (c) S.gbase[tid] = atomicAdd(&cursor[tid], c);
+    S.cnt[tid] = S.start[tid];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    if (j < nv) {
+      const u32 r = atomicAdd(&S.cnt[dg[j]], 1u);
+      S.stage[r] = rec[j];
+      S.dig[r] = (uint8_t)dg[j];
+    }
+  }
+  __syncthreads();
+  for (u32 i = tid; i < n; i += SC_BLOCK) {
+    const u32 d = S.dig[i];
+    dst[S.gbase[d] + (i - S.start[d])] = S.stage[i];
+  }
+  __syncthreads();
+}
+
+template <bool VEC, bool BATCH>
+__global__ void __launch_bounds__(SC_BLOCK, 8) k_mem_scatter_a(TraceArgs A0, const TraceArgs *batch) {
+  __shared__ TileShared S;
+  const TraceArgs A = trace_args<BATCH>(A0, batch);
+  if (A.n_mem == 0 || !A.part_tmp) return;
+  const int tid = threadIdx.x;
+  const u32 P = 1u << A.pbits, NC = P >> FINE_BITS;
+  u32 *ccur = A.part_cur + P;
+  const u64 ntiles = (A.n_mem + SC_T - 1) / SC_T;
+  for (u64 t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const u64 t0 = t * SC_T;
+    const u32 n = (u32)((A.n_mem - t0) < SC_T ? (A.n_mem - t0) : SC_T);
+    if (tid < 256) S.cnt[tid] = 0;
+    __syncthreads();
+    const u64 i = t0 + 8ull * tid;
+    u64 a[8];
+    uint2 kk2 = make_uint2(0, 0);
+    int nv = 0;
+    if (i < A.n_mem) {
+      if (VEC && i + 8 <= A.n_mem) {
+        const ulonglong2 *pa = reinterpret_cast<const ulonglong2 *>(A.addr + i);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) { const ulonglong2 x = pa[q]; a[2 * q] = x.x; a[2 * q + 1] = x.y; }
+        kk2 = *reinterpret_cast<const uint2 *>(A.mem_kind + i);
+        nv = 8;
+      } else {
+        nv = (int)((A.n_mem - i) < 8 ? (A.n_mem - i) : 8);
+        for (int j = 0; j < 8; ++j) {
+          a[j] = j < nv ? A.addr[i + j] : 0;
+          const u32 kb = j < nv ? A.mem_kind[i + j] : 0;
+          if (j < 4) kk2.x |= kb << (8 * j); else kk2.y |= kb << (8 * (j - 4));
+        }
+      }
+    }
+    u64 rec[8];
+    u32 dg[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      rec[j] = 0;
+      dg[j] = 0;
+      if (j < nv) {
+        u32 bin;
+        const uint8_t k = (uint8_t)((j < 4 ? kk2.x : kk2.y) >> (8 * (j & 3)));
+        rec[j] = make_record(a[j], k, A.pbits, bin) | ((u64)(bin & 255u) << 56);
+        dg[j] = bin >> FINE_BITS;
+        atomicAdd(&S.cnt[dg[j]], 1u);
+      }
+    }
+    tile_write<8>(S, rec, dg, nv, n, A.part_tmp, NC, ccur);
+  }
+}
+
+template <bool BATCH>
+__global__ void __launch_bounds__(SC_BLOCK, 8) k_mem_scatter_b(TraceArgs A0, const TraceArgs *batch) {
+  __shared__ TileShared S;
+  const TraceArgs A = trace_args<BATCH>(A0, batch);
+  if (A.n_mem == 0 || !A.part_tmp) return;
+  const int tid = threadIdx.x;
+  const u32 P = 1u << A.pbits, NC = P >> FINE_BITS;
+  const u32 *tst_g = A.part_cur + P + NC;
+  for (u32 c = tid; c <= NC; c += SC_BLOCK) S.tst[c] = tst_g[c];
+  __syncthreads();
+  const u32 ntiles = S.tst[NC];
+  for (u32 t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    // the coarse bucket of tile t: the last c with tst[c] <= t
+    u32 lo = 0, hi = NC;
+    while (hi - lo > 1) {
+      const u32 mid = (lo + hi) >> 1;
+      if (S.tst[mid] <= t) lo = mid; else hi = mid;
+    }
+    const u32 c = lo;
+    const u64 b0 = A.part_off[c << FINE_BITS], b1 = A.part_off[(c + 1) << FINE_BITS];
+    const u64 t0 = b0 + (u64)(t - S.tst[c]) * SC_T;
+    const u32 n = (u32)((b1 - t0) < SC_T ? (b1 - t0) : SC_T);
+    if (tid < 256) S.cnt[tid] = 0;
+    __syncthreads();
+    u64 rec[8];
+    u32 dg[8];
+    int nv = 0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      // record j of this thread: t0 + j * SC_BLOCK + tid (coalesced)
+      const u32 k = (u32)j * SC_BLOCK + (u32)tid;
+      rec[j] = 0;
+      dg[j] = 0;
+      if (k < n) {
+        const u64 r = A.part_tmp[t0 + k];
+        dg[j] = (u32)(r >> 56);
+        rec[j] = r & ((1ull << 56) - 1ull);
+        atomicAdd(&S.cnt[dg[j]], 1u);
+        nv = j + 1;
+      }
+    }
+    tile_write<8>(S, rec, dg, nv, n, A.part_rec, 256u, A.part_cur + (c << FINE_BITS));
+  }
 }
 
 // -------------------------------------------------------------- scatter
@@ -174,7 +357,7 @@ template <bool VEC, bool BATCH>
 __global__ void __launch_bounds__(MEM_BLOCK) k_mem_scatter(TraceArgs A0, const TraceArgs *batch) {
   extern __shared__ u32 cur[];   // [P]
   const TraceArgs A = trace_args<BATCH>(A0, batch);
-  if (A.n_mem == 0 || blockIdx.x >= A.n_hist_blocks) return;
+  if (A.n_mem == 0 || blockIdx.x >= A.n_hist_blocks || A.part_tmp) return;
   const u32 P = 1u << A.pbits;
   const u32 *row = A.part_hist + (u64)blockIdx.x * P;
   for (u32 i = threadIdx.x; i < P; i += MEM_BLOCK) cur[i] = A.part_off[i] + row[i];
@@ -1240,12 +1423,27 @@ hipError_t launch_mem_partition(const TraceArgs &a, const BatchDims &d, hipStrea
     hipLaunchKernelGGL(k_mem_binscan<false>, g1, dim3(1024), 0, s, a, b);
   }
   AIWC_MARK(pm, "k_mem_scan", s);
-  if (b) {
-    if (d.vec) hipLaunchKernelGGL((k_mem_scatter<true, true>), gh, dim3(MEM_BLOCK), lds, s, a, b);
-    else hipLaunchKernelGGL((k_mem_scatter<false, true>), gh, dim3(MEM_BLOCK), lds, s, a, b);
-  } else {
-    if (d.vec) hipLaunchKernelGGL((k_mem_scatter<true, false>), gh, dim3(MEM_BLOCK), lds, s, a, b);
-    else hipLaunchKernelGGL((k_mem_scatter<false, false>), gh, dim3(MEM_BLOCK), lds, s, a, b);
+  if (d.any_one_level) {
+    if (b) {
+      if (d.vec) hipLaunchKernelGGL((k_mem_scatter<true, true>), gh, dim3(MEM_BLOCK), lds, s, a, b);
+      else hipLaunchKernelGGL((k_mem_scatter<false, true>), gh, dim3(MEM_BLOCK), lds, s, a, b);
+    } else {
+      if (d.vec) hipLaunchKernelGGL((k_mem_scatter<true, false>), gh, dim3(MEM_BLOCK), lds, s, a, b);
+      else hipLaunchKernelGGL((k_mem_scatter<false, false>), gh, dim3(MEM_BLOCK), lds, s, a, b);
+    }
+  }
+  if (d.any_two_level) {
+    // persistent tiles: two 84 KiB blocks per CU
+    const dim3 gt(1024, d.n);
+    if (b) {
+      if (d.vec) hipLaunchKernelGGL((k_mem_scatter_a<true, true>), gt, dim3(SC_BLOCK), 0, s, a, b);
+      else hipLaunchKernelGGL((k_mem_scatter_a<false, true>), gt, dim3(SC_BLOCK), 0, s, a, b);
+      hipLaunchKernelGGL(k_mem_scatter_b<true>, gt, dim3(SC_BLOCK), 0, s, a, b);
+    } else {
+      if (d.vec) hipLaunchKernelGGL((k_mem_scatter_a<true, false>), gt, dim3(SC_BLOCK), 0, s, a, b);
+      else hipLaunchKernelGGL((k_mem_scatter_a<false, false>), gt, dim3(SC_BLOCK), 0, s, a, b);
+      hipLaunchKernelGGL(k_mem_scatter_b<false>, gt, dim3(SC_BLOCK), 0, s, a, b);
+    }
   }
   AIWC_MARK(pm, "k_mem_scatter", s);
   return hipGetLastError();

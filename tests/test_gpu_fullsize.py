@@ -383,3 +383,21 @@ def test_stream_of_the_large_trace():
     got = st.finish().read()
     assert same(got, plain), "host-retained stream differs from the whole"
     log("host-retained stream identical to the plain path on the whole")
+    st.close()
+    # out of core: the memory stream stays in pinned host memory and the
+    # device holds a quarter of its partition records at a time
+    st = ctx.stream(host_retain=True)
+    st.set_device_budget(12 * (d["n_mem"] // 4))
+    for i in range(k):
+        p = {"opcode": d["opcode"][ecut[i]:ecut[i + 1]],
+             "wi_offsets": (off[wcut[i]:wcut[i + 1] + 1] - off[wcut[i]]).contiguous(),
+             "addr": d["addr"][mcut[i]:mcut[i + 1]], "mem_kind": d["mem_kind"][mcut[i]:mcut[i + 1]],
+             "br_site": d["br_site"][bcut[i]:bcut[i + 1]],
+             "br_taken": d["br_taken"][bcut[i]:bcut[i + 1]]}
+        st.append(aiwc.device_trace(ctx, p, tab, spec.n_sites, spec.history_len, spec.wg_size))
+    got = st.finish().read()
+    s = st.stats()
+    assert s["groups"] >= 4 and s["device_records"] < d["n_mem"] // 3, s
+    assert same(got, plain), "out-of-core stream differs from the whole"
+    log(f"out-of-core stream ({s['groups']} partition groups, {s['device_records']} of "
+        f"{d['n_mem']} records on the device at once) identical to the plain path")
