@@ -504,17 +504,18 @@ constexpr int UNROLL = 8;                         // records in flight per threa
 constexpr u32 SPEC_LDS = 256;
 constexpr u32 STAGE_CAP = AIWC_STAGE_CAP;         // staged records per round
 constexpr u32 TAG_POS = (1u << 21) - 1u;          // position field of a record tag
+constexpr u32 HEAVY_TAG = 1u << 31;               // big-list entry of an unstaged page
 // Dense-tree nodes of count >= 256 found by the wavefronts in one round, kept
 // for the block: at most 11 levels * STAGE_CAP / 256 of them.
 constexpr u32 BLIST_CAP = AIWC_NSKIP * STAGE_CAP / 256;
 static_assert(STAGE_CAP < 0xFFFFu, "staging positions travel in 16 bits");
 static_assert(PT_SLOTS <= 2048, "a slot travels in the 11 high bits of a tag and of a staged record");
-static_assert(STAGE_CAP <= (1u << 15) && HEAVY < (1u << 17), "start | size << 15 fits 32 bits");
+static_assert(STAGE_CAP <= (1u << 15) && HEAVY < (1u << 15),
+              "start | size << 15 (table word) and start | size << 16 (big list) fit 32 bits");
 
 struct BucketShared {
   u64 pkey[PT_SLOTS];              // page key, EMPTY if free
   u32 pcnt[PT_SLOTS];              // records of the page
-  uint16_t pidx[PT_SLOTS];         // compact index of the page
   uint16_t pslot[PT_CAP];          // slot of compact index
   uint16_t psz[PT_CAP];            // records of compact index (saturated at 65535)
   u32 pend[PT_CAP];                // staging cursor, then end, of compact index
@@ -527,7 +528,9 @@ struct BucketShared {
   u64 el[2][AIWC_NSKIP][3];        // entropy, 2^-40 units: el0 + el1 * 2^32 + el2 * 2^64
   u64 ur[2], uw[2];
   u64 redos;
-  uint16_t big[PT_CAP];            // pages > SMALL: space 0 from the front, 1 from the back
+  // pages > SMALL, space 0 from the front, 1 from the back: compact index
+  // (class phase), then start | size << 16 (staged) or HEAVY_TAG | index
+  u32 big[PT_CAP];
   u32 ctot[3], ccur[3];
   u32 npages, overflow, work, nbig0, nbig1, nheavy, next_item, sp_top;
   u32 stack_m[32], stack_c[32];
@@ -993,7 +996,8 @@ __global__ void __launch_bounds__(BK_BLOCK) k_mem_bucket(TraceArgs A0, const Tra
         }
         // run heads and their first probe slots for all records at once
         u32 hs[UNROLL], run[UNROLL];
-        u64 hw[UNROLL];
+        u64 hw[UNROLL], HB[UNROLL];
+        u32 vbits = 0;
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u) {
           const u64 pk = rv[u] >> 11;
@@ -1002,6 +1006,8 @@ __global__ void __launch_bounds__(BK_BLOCK) k_mem_bucket(TraceArgs A0, const Tra
           const bool head = valid && (lane == 0 || ((ends >> (lane - 1)) & 1ull) != 0);
           run[u] = head ? (u32)__builtin_ctzll(ends & ~below) - (u32)lane + 1u : 0u;
           hs[u] = pt_slot(pk);
+          HB[u] = __ballot(head);
+          vbits |= (valid ? 1u : 0u) << u;
         }
         // first probes: the page is usually in its home slot already, so the
         // table loads and the count atomics of all records are in flight
@@ -1031,7 +1037,7 @@ __global__ void __launch_bounds__(BK_BLOCK) k_mem_bucket(TraceArgs A0, const Tra
               u64 old = atomicCAS(&S.pkey[slot], EMPTY, pk);
               if (old == EMPTY) {
                 const u32 ci = atomicAdd(&S.npages, 1u);
-                if (ci < PT_CAP) { S.pidx[slot] = (uint16_t)ci; S.pslot[ci] = (uint16_t)slot; }
+                if (ci < PT_CAP) S.pslot[ci] = (uint16_t)slot;
                 else S.overflow = 1;
                 w = pk;
               } else {
@@ -1047,19 +1053,15 @@ __global__ void __launch_bounds__(BK_BLOCK) k_mem_bucket(TraceArgs A0, const Tra
           }
         }
         // each lane of a run takes its head's slot and the next position
+        u32 *tagp = A.part_tag + base + w0 + (u32)lane;
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u) {
-          const u64 pk = rv[u] >> 11;
-          const bool valid = rv[u] != EMPTY && ((u32)pk & (M - 1u)) == C;
-          const u64 ends = run_ends(valid ? pk : EMPTY);
-          const bool head = valid && (lane == 0 || ((ends >> (lane - 1)) & 1ull) != 0);
-          const u64 H = __ballot(head) & (below | (1ull << lane));
+          const bool valid = ((vbits >> u) & 1u) != 0;
+          const u64 H = HB[u] & (below | (1ull << lane));
           const int hl = H ? 63 - __builtin_clzll(H) : lane;
           const u32 h0 = __shfl(hv[u], hl, 64);
           const u32 pos = (h0 & TAG_POS) + (u32)(lane - hl);
-          if (valid)
-            A.part_tag[base + w0 + (u32)u * BK_BLOCK + (u32)lane] =
-                (h0 & ~TAG_POS) | (pos < TAG_POS ? pos : TAG_POS);
+          if (valid) tagp[u * BK_BLOCK] = (h0 & ~TAG_POS) | (pos < TAG_POS ? pos : TAG_POS);
         }
       }
       __syncthreads();
@@ -1090,8 +1092,17 @@ __global__ void __launch_bounds__(BK_BLOCK) k_mem_bucket(TraceArgs A0, const Tra
         }
         b0 = (u32)__builtin_amdgcn_readfirstlane((int)b0);
         b1 = (u32)__builtin_amdgcn_readfirstlane((int)b1);
-        if (l0) S.big[b0 + (u32)__builtin_popcountll(B0 & below)] = (uint16_t)j;
-        if (l1) S.big[PT_CAP - 1 - (b1 + (u32)__builtin_popcountll(B1 & below))] = (uint16_t)j;
+        // pend[j] holds the page's slot in the list until its start is known
+        if (l0) {
+          const u32 bi = b0 + (u32)__builtin_popcountll(B0 & below);
+          S.big[bi] = j;
+          S.pend[j] = bi;
+        }
+        if (l1) {
+          const u32 bi = PT_CAP - 1 - (b1 + (u32)__builtin_popcountll(B1 & below));
+          S.big[bi] = j;
+          S.pend[j] = bi;
+        }
         // class totals (classes 0 and 1 share a word: their counts are <= SMALL)
         const u32 t01 = wave_total((cl == 0 ? c : 0u) | ((cl == 1 ? c : 0u) << 16));
         const u32 t2 = wave_total(cl == 2 ? c : 0u);
@@ -1152,6 +1163,9 @@ __global__ void __launch_bounds__(BK_BLOCK) k_mem_bucket(TraceArgs A0, const Tra
         else if (cl == 1) end = c1 + (x01 >> 16);
         else if (cl == 2) end = c2 + x2;
         if (j < np) {
+          // a larger page's list entry becomes its start and size (one load
+          // per item), a heavy page's keeps its index
+          if (c > SMALL) S.big[S.pend[j]] = cl == 2 ? (end - c) | (c << 16) : HEAVY_TAG | j;
           S.pend[j] = end;
           S.pcnt[S.pslot[j]] = cl < 3 ? (end - c) | (c << 15) : ~0u;
         }
@@ -1193,8 +1207,9 @@ __global__ void __launch_bounds__(BK_BLOCK) k_mem_bucket(TraceArgs A0, const Tra
       // ---- 3a. heavy pages: counted by the whole block into dense[0]
       if (S.nheavy) {
         for (u32 bi = 0; bi < nb0 + nb1; ++bi) {
-          const u32 ci = S.big[bi < nb0 ? bi : PT_CAP - 1 - (bi - nb0)];
-          if (S.psz[ci] <= HEAVY) continue;
+          const u32 be = S.big[bi < nb0 ? bi : PT_CAP - 1 - (bi - nb0)];
+          if (!(be & HEAVY_TAG)) continue;
+          const u32 ci = be & 0xFFFFu;
           const u64 hk = S.pkey[S.pslot[ci]];
           for (u32 i = tid; i < 1024; i += BK_BLOCK) S.dense[0][i] = 0;
           if (tid < 32) { S.rbits[tid] = 0; S.wbits[tid] = 0; }
@@ -1235,11 +1250,13 @@ __global__ void __launch_bounds__(BK_BLOCK) k_mem_bucket(TraceArgs A0, const Tra
         u32 *dn = S.dense[wave];
         LaneAcc L;
         lacc_clear(L, 0);
+        // the next item's index is fetched while this one is processed
+        u32 nxt = 0;
+        if (lane == 0) nxt = atomicAdd(&S.next_item, 1u);
         while (true) {
-          u32 it = 0;
-          if (lane == 0) it = atomicAdd(&S.next_item, 1u);
-          it = (u32)__builtin_amdgcn_readfirstlane((int)it);
+          const u32 it = (u32)__builtin_amdgcn_readfirstlane((int)nxt);
           if (it >= e3) break;
+          if (lane == 0) nxt = atomicAdd(&S.next_item, 1u);
           const int sp = (it < e1) ? 0 : 1;
           const u64 N = sp ? N1 : N0;
           if (sp != L.space) { lacc_flush(L, S); L.space = sp; }
@@ -1259,10 +1276,9 @@ __global__ void __launch_bounds__(BK_BLOCK) k_mem_bucket(TraceArgs A0, const Tra
             match_levels(L, S, (v >> 1) & 1023u, v & 1u, pm);
             continue;
           }
-          const u32 ci = S.big[(it < e1) ? it - e0 : PT_CAP - 1 - (it - e2)];
-          const u32 sz = S.psz[ci];
-          if (sz > HEAVY) continue;
-          const u32 o1 = S.pend[ci], o0 = o1 - sz;
+          const u32 be = S.big[(it < e1) ? it - e0 : PT_CAP - 1 - (it - e2)];
+          if (be & HEAVY_TAG) continue;
+          const u32 sz = be >> 16, o0 = be & 0xFFFFu, o1 = o0 + sz;
           if (sz <= MEDIUM) {
             const u32 v = (u32)lane < sz ? S.stage[o0 + lane] : 0u;
             match_levels(L, S, (v >> 1) & 1023u, v & 1u, (u32)lane < sz ? low_mask(sz) : 0ull);
