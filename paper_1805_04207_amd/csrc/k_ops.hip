@@ -85,7 +85,10 @@ __global__ void __launch_bounds__(OPS_BLOCK) k_ops(TraceArgs A0, const TraceArgs
   u32 *hist = ipth + LDS_VALS;                        // [ncopies][nid]
   u32 *info = hist + (LDS_IDS ? ncopies * nid : 0);   // [nid]
 
-  const int tid = threadIdx.x, lane = lane_id(), wave = tid / AIWC_WAVE;
+  // the wave index is uniform: the task walk below then keeps its state in
+  // scalar registers (the barrier and work-item-end walk is wave-uniform)
+  const int tid = threadIdx.x, lane = lane_id();
+  const int wave = __builtin_amdgcn_readfirstlane(tid / AIWC_WAVE);
   if (LDS_IDS) {
     for (u32 i = tid; i < ncopies * nid; i += OPS_BLOCK) hist[i] = 0;
     for (u32 i = tid; i < nid; i += OPS_BLOCK) info[i] = A.op_info[i];
@@ -195,7 +198,7 @@ __global__ void __launch_bounds__(OPS_BLOCK) k_ops(TraceArgs A0, const TraceArgs
         u32 lm = 0;
         if (B) {
           bl = __builtin_ctzll(B);
-          lm = __shfl(bm, bl, 64);
+          lm = (u32)__builtin_amdgcn_readlane((int)bm, bl);
           nb = cb + 8ull * bl + (u64)__builtin_ctz(lm);
         }
         if (cur_w < w_hi && cur_end <= lim && cur_end <= nb) {
