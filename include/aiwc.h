@@ -541,6 +541,198 @@ aiwc_status aiwc_sizer_load(aiwc_ctx *ctx, const char *path);
 /* Margin (in log2 units) added to predictions before sizing.               */
 aiwc_status aiwc_sizer_set_margin(aiwc_ctx *ctx, float margin_log2);
 
+/* ----------------------------------------------------------- trace producer
+ * Produces the event arrays of one kernel launch by executing the kernel on
+ * the GPU.  The paper obtains its trace by interpreting a kernel's LLVM IR in
+ * a simulator that notifies a plugin of every executed instruction, memory
+ * access and branch outcome (Implementation section; Methodology, the SPIR
+ * paragraph).  Here a kernel is a program of aiwc_insn records (a register
+ * machine whose operations carry LLVM's opcode names) that libaiwc
+ * interprets with one GPU thread per work-item and one workgroup per
+ * work-group, recording the same events:
+ *   - every executed instruction appends its opcode id to its work-item's
+ *     opcode stream (the instructionExecuted notification);
+ *   - LOAD / STORE append one memory event at the access's start address,
+ *     ATOMIC a read and then a write event (memoryLoad, memoryStore,
+ *     memoryAtomicLoad, memoryAtomicStore);
+ *   - BR appends one branch event (site, 1 if the condition held);
+ *   - BARRIER ends an instructions-to-barrier segment (its opcode table
+ *     entry has AIWC_KIND_BARRIER).
+ * Event order follows the paper's schedule: work-groups one after another,
+ * and inside a work-group each work-item runs until it reaches a barrier or
+ * returns before the next work-item runs.  So the branch stream is ordered
+ * by (work-group, barrier interval, local id, execution order).  The opcode
+ * stream is work-item major (work-item w = group_linear * wg_size +
+ * local_linear), and so are the memory events (their order is free).
+ *
+ * Machine model.
+ *   - AIWC_NREG registers of 64 bits per work-item, zero at start except
+ *     r0..r(n_args-1), which hold the kernel arguments.
+ *   - Integer operations work on all 64 bits (two's complement; shift counts
+ *     taken mod 64; division or remainder by zero gives 0, and so does
+ *     INT64_MIN / -1 for its remainder, INT64_MIN for its quotient).
+ *   - F-operations work on the binary32 value in the low 32 bits, round to
+ *     nearest even, keep subnormals, and write the result's bits
+ *     zero-extended; a NaN result is written as 0x7FC00000.  FMIN / FMAX
+ *     return the other operand when one is NaN and order -0 below +0.
+ *   - width w > 1 applies an operation to w consecutive registers of each
+ *     register operand (an immediate operand is shared); a register range of
+ *     d must equal or not overlap those of a, b and c.
+ *   - Addresses: global argument j (counting global arguments only) is the
+ *     buffer whose address is (j + 1) << AIWC_ADDR_TAG_SHIFT; local
+ *     arguments are laid out in order, each 16-byte aligned, in the
+ *     work-group's local memory, whose addresses are offsets from 0 (tag 0).
+ *     The trace records these addresses (global events clear
+ *     AIWC_MEM_LOCAL, local events set it).  Local memory starts zeroed in
+ *     every work-group.
+ *   - An access must lie inside its buffer and be aligned to its element
+ *     size; otherwise the launch fails (AIWC_ERR_INVALID_ARG) without doing
+ *     the access.
+ *
+ * Operations (d, a, b, c are registers; "b" is imm instead when
+ * flags & AIWC_INSN_IMM_B; LLVM names in brackets are what the opcode table
+ * normally gives the id):
+ *   RET                      the work-item ends                       [ret]
+ *   MOV      d = b                                                    [phi]
+ *   ADD SUB MUL SDIV SREM UDIV UREM SHL LSHR ASHR AND OR XOR
+ *            d = a op b                                   [add, sub, ...]
+ *   ICMP     d = (a mode b) ? 1 : 0, mode AIWC_ICMP_*             [icmp]
+ *   FADD FSUB FMUL FDIV d = a op b                  [fadd, fsub, fmul, fdiv]
+ *   FCMP     d = (a mode b) ? 1 : 0, mode AIWC_FCMP_* (false if either
+ *            is NaN, except UNE)                                  [fcmp]
+ *   FMA      d = a * b + c, one rounding                          [call]
+ *   FSQRT    d = sqrt(a)                                          [call]
+ *   FMIN FMAX d = min / max (a, b)                                [call]
+ *   SITOFP   d = float((int32) a)                               [sitofp]
+ *   FPTOSI   d = (int64)(int32) trunc(a); NaN -> 0, saturating  [fptosi]
+ *   SEXT     d = (int64)(int32) a                                 [sext]
+ *   ZEXT     d = a & 0xFFFFFFFF                                   [zext]
+ *   SELECT   d = a != 0 ? b : c                                 [select]
+ *   GEP      d = a + b * imm (b a register);  with IMM_B: d = a + imm
+ *                                                        [getelementptr]
+ *   LOAD     d.. = element i at address a + i * size, mode AIWC_LD_*  [load]
+ *   STORE    element i of b.. to address a + i * size, mode AIWC_ST_* [store]
+ *   ATOMIC   d = old 32-bit value at a, sign-extended; stores
+ *            (old mode b), mode AIWC_AT_*                      [atomicrmw]
+ *   BR       next = a != 0 ? imm : target2; a branch event of `site` [br]
+ *   JMP      next = imm                                          [br]
+ *   BARRIER  waits for every work-item of the work-group         [call]
+ *   BUILTIN  d = work-item function mode (AIWC_BI_* + dimension)  [call]
+ * Falling off the end of the program, or running more than max_steps
+ * instructions in one work-item, fails the launch.                         */
+#define AIWC_NREG 64
+#define AIWC_ADDR_TAG_SHIFT 40
+#define AIWC_MAX_KERNEL_ARGS 32
+enum {
+  AIWC_OP_RET = 0, AIWC_OP_MOV, AIWC_OP_ADD, AIWC_OP_SUB, AIWC_OP_MUL, AIWC_OP_SDIV,
+  AIWC_OP_SREM, AIWC_OP_UDIV, AIWC_OP_UREM, AIWC_OP_SHL, AIWC_OP_LSHR, AIWC_OP_ASHR,
+  AIWC_OP_AND, AIWC_OP_OR, AIWC_OP_XOR, AIWC_OP_ICMP, AIWC_OP_FADD, AIWC_OP_FSUB,
+  AIWC_OP_FMUL, AIWC_OP_FDIV, AIWC_OP_FCMP, AIWC_OP_FMA, AIWC_OP_FSQRT, AIWC_OP_FMIN,
+  AIWC_OP_FMAX, AIWC_OP_SITOFP, AIWC_OP_FPTOSI, AIWC_OP_SEXT, AIWC_OP_ZEXT,
+  AIWC_OP_SELECT, AIWC_OP_GEP, AIWC_OP_LOAD, AIWC_OP_STORE, AIWC_OP_ATOMIC, AIWC_OP_BR,
+  AIWC_OP_JMP, AIWC_OP_BARRIER, AIWC_OP_BUILTIN, AIWC_OP_COUNT
+};
+enum { AIWC_ICMP_EQ = 0, AIWC_ICMP_NE, AIWC_ICMP_SLT, AIWC_ICMP_SLE, AIWC_ICMP_SGT,
+       AIWC_ICMP_SGE, AIWC_ICMP_ULT, AIWC_ICMP_ULE, AIWC_ICMP_UGT, AIWC_ICMP_UGE };
+enum { AIWC_FCMP_OEQ = 0, AIWC_FCMP_UNE, AIWC_FCMP_OLT, AIWC_FCMP_OLE, AIWC_FCMP_OGT,
+       AIWC_FCMP_OGE };
+enum { AIWC_LD_I32 = 0,  /* 4 bytes, sign-extended                            */
+       AIWC_LD_U32 = 1,  /* 4 bytes, zero-extended (also binary32 values)     */
+       AIWC_LD_64 = 2 }; /* 8 bytes                                           */
+enum { AIWC_ST_32 = 0, AIWC_ST_64 = 1 };
+enum { AIWC_AT_ADD = 0, AIWC_AT_SUB, AIWC_AT_AND, AIWC_AT_OR, AIWC_AT_XOR, AIWC_AT_MIN,
+       AIWC_AT_MAX, AIWC_AT_UMIN, AIWC_AT_UMAX };   /* MIN/MAX signed         */
+enum { AIWC_BI_GLOBAL_ID = 0, AIWC_BI_LOCAL_ID = 3, AIWC_BI_GROUP_ID = 6,
+       AIWC_BI_GLOBAL_SIZE = 9, AIWC_BI_LOCAL_SIZE = 12, AIWC_BI_NUM_GROUPS = 15 };
+enum { AIWC_INSN_IMM_B = 1u };
+
+typedef struct aiwc_insn {
+  uint8_t op;        /* AIWC_OP_*                                           */
+  uint8_t mode;      /* predicate, load / store / atomic form, builtin      */
+  uint8_t width;     /* 1..16; 1 for LOAD/STORE widths above, ATOMIC, BR,
+                        JMP, BARRIER, BUILTIN, RET                          */
+  uint8_t flags;     /* AIWC_INSN_IMM_B                                     */
+  uint8_t d, a, b, c;/* registers < AIWC_NREG                               */
+  uint16_t id;       /* opcode id recorded when the instruction executes    */
+  uint16_t site;     /* BR: branch site id (< n_sites)                      */
+  uint32_t target2;  /* BR: next instruction when the condition is zero     */
+  int64_t imm;       /* immediate; BR / JMP: next instruction index         */
+} aiwc_insn;         /* 24 bytes                                            */
+
+/* A program: n_insn instructions (host; copied), the opcode table its ids
+ * index (host; copied) and its number of branch sites.  The create call
+ * checks every field above and that each instruction's id has the kind its
+ * operation needs (LOAD -> AIWC_KIND_LOAD, STORE -> STORE, ATOMIC ->
+ * ATOMIC_RMW, BR -> BRANCH_COND, BARRIER -> BARRIER, any other -> COMPUTE
+ * or OTHER); AIWC_ERR_INVALID_ARG otherwise.                               */
+typedef struct aiwc_program_desc {
+  uint32_t struct_size;
+  uint32_t n_insn;
+  const aiwc_insn *code;
+  uint32_t n_opcode_ids;
+  uint32_t n_sites;
+  const aiwc_opcode_info *opcode_table;
+} aiwc_program_desc;
+
+enum { AIWC_ARG_GLOBAL = 0,   /* ptr: device buffer of `bytes` bytes (>= 1,
+                                 16-byte aligned); read and written in place */
+       AIWC_ARG_LOCAL = 1,    /* `bytes` of local memory per work-group      */
+       AIWC_ARG_SCALAR = 2 }; /* `value` is the register's 64 bits          */
+typedef struct aiwc_kernel_arg {
+  uint32_t kind;
+  uint32_t reserved;
+  void *ptr;
+  uint64_t bytes;
+  uint64_t value;
+} aiwc_kernel_arg;
+
+/* The launch: dims 1..3, global[i] a multiple of local[i], local size
+ * product <= 1024, local memory <= 65536 bytes.                             */
+typedef struct aiwc_ndrange {
+  uint32_t dims;
+  uint32_t global[3];
+  uint32_t local[3];
+  uint32_t reserved;
+} aiwc_ndrange;
+
+typedef struct aiwc_program aiwc_program;
+typedef struct aiwc_produced aiwc_produced;
+
+aiwc_status aiwc_program_create(aiwc_ctx *ctx, const aiwc_program_desc *desc,
+                                aiwc_program **out);
+aiwc_status aiwc_program_destroy(aiwc_program *prog);
+
+/* Execute the program over the ND-range and keep its trace.  The kernel runs
+ * twice: a counting run sizes every work-item's streams, then the global
+ * buffers are restored from a device copy taken before it and a recording
+ * run writes the events; the buffers end as the recording run left them.
+ * Blocks the calling thread (the trace's sizes decide its allocation).
+ * max_steps (1..2^31-1; 0 = 2^20) bounds the instructions of one work-item.
+ * Errors: INVALID_ARG for a bad ND-range or argument list, and for a run
+ * that accessed memory outside its buffers or misaligned, exceeded
+ * max_steps, fell off the program's end, or left some work-items of a
+ * work-group waiting at a barrier that others never reached (message names
+ * which); UNSUPPORTED when the two runs disagree (control flow that depends
+ * on the order in which work-groups ran, e.g. on an atomic's old value);
+ * OUT_OF_MEMORY for the snapshot or the trace arrays.                       */
+aiwc_status aiwc_produce(aiwc_program *prog, const aiwc_ndrange *nd,
+                         const aiwc_kernel_arg *args, uint32_t n_args, uint64_t max_steps,
+                         void *stream, aiwc_produced **out);
+
+/* A trace descriptor over the produced arrays: every stream field, the
+ * counts, wg_size, n_sites and the program's opcode table (owned by the
+ * produced object, valid until it is destroyed), history_len 16,
+ * max_lsb_skip 10 and flags 0; the caller may change history_len and flags
+ * before aiwc_trace_create.                                                 */
+aiwc_status aiwc_produced_desc(const aiwc_produced *p, aiwc_trace_desc *out);
+/* Copy the produced arrays to host memory (a NULL pointer skips that array;
+ * lengths are those of aiwc_produced_desc: n_events, n_workitems + 1, n_mem,
+ * n_mem, n_branch, n_branch).  Synchronous.                                 */
+aiwc_status aiwc_produced_to_host(const aiwc_produced *p, uint16_t *opcode, uint64_t *wi_offsets,
+                                  uint64_t *addr, uint8_t *mem_kind, uint32_t *br_site,
+                                  uint8_t *br_taken);
+aiwc_status aiwc_produced_destroy(aiwc_produced *p);
+
 #ifdef __cplusplus
 }
 #endif

@@ -21,8 +21,8 @@ LIB = os.path.join(HERE, "liboracle.so")
 
 def build() -> str:
     """Compile the C oracle (gcc, host only)."""
-    cmd = ["gcc", "-O2", "-std=gnu11", "-Wall", "-Wextra", "-fPIC", "-shared",
-           os.path.join(HERE, "aiwc_oracle.c"), "-o", LIB, "-lm"]
+    cmd = ["gcc", "-O2", "-std=gnu11", "-Wall", "-Wextra", "-fPIC", "-shared", "-ffp-contract=off",
+           os.path.join(HERE, "aiwc_oracle.c"), os.path.join(HERE, "producer.c"), "-o", LIB, "-lm"]
     subprocess.run(cmd, check=True)
     return LIB
 
@@ -77,6 +77,21 @@ class OrcResult(ctypes.Structure):
                 ("load_imbalance", ctypes.c_uint64)]
 
 
+class OrcArg(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_uint32), ("pad", ctypes.c_uint32), ("host", ctypes.c_void_p),
+                ("bytes", ctypes.c_uint64), ("value", ctypes.c_uint64)]
+
+
+class OrcProduced(ctypes.Structure):
+    _fields_ = [("n_events", ctypes.c_uint64), ("n_wi", ctypes.c_uint64),
+                ("n_mem", ctypes.c_uint64), ("n_branch", ctypes.c_uint64),
+                ("opcode", ctypes.c_void_p), ("wi_offsets", ctypes.c_void_p),
+                ("addr", ctypes.c_void_p), ("mem_kind", ctypes.c_void_p),
+                ("mem_wi", ctypes.c_void_p), ("br_site", ctypes.c_void_p),
+                ("br_taken", ctypes.c_void_p), ("error", ctypes.c_uint32),
+                ("error_wi", ctypes.c_uint64)]
+
+
 _lib = None
 
 
@@ -92,6 +107,10 @@ def _load():
         L.orc_spectrum.argtypes = [ctypes.POINTER(OrcTrace), ctypes.c_int, ctypes.c_int,
                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
                                    ctypes.POINTER(ctypes.c_size_t)]
+        L.orc_produce.argtypes = [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32,
+                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                  ctypes.c_uint32, ctypes.c_uint64, ctypes.POINTER(OrcProduced)]
+        L.orc_produce_free.argtypes = [ctypes.POINTER(OrcProduced)]
         _lib = L
     return _lib
 
@@ -235,3 +254,79 @@ def spectrum(tr, space: int, k: int = 0):
                       ctypes.byref(n)) != 0:
         raise ValueError("oracle rejected the trace")
     return [(int(a), int(c)) for a, c in zip(f[:n.value], m[:n.value])]
+
+
+# ------------------------------------------------------------ trace producer
+PRODUCE_ERRORS = {1: "out of bounds", 2: "misaligned", 4: "step limit", 8: "barrier mismatch",
+                  16: "ran off the program", 64: "invalid program"}
+
+
+class ProduceError(RuntimeError):
+    def __init__(self, code: int, wi: int):
+        super().__init__(f"kernel failed: {PRODUCE_ERRORS.get(code, code)} (work-item {wi})")
+        self.code = code
+        self.wi = wi
+
+
+class ProducedTrace:
+    """The oracle's trace of one kernel launch (HostTrace attributes, plus
+    mem_wi: the work-item of each memory event, in execution order)."""
+
+    def __init__(self, program, arrays, wg_size):
+        self.opcode, self.wi_offsets, self.addr, self.mem_kind, self.mem_wi, \
+            self.br_site, self.br_taken = arrays
+        self.table = program.table
+        self.n_sites = max(1, int(program.n_sites))
+        self.history_len = 16
+        self.wg_size = wg_size
+
+
+def produce(program, global_size, local_size, args, max_steps: int = 0) -> ProducedTrace:
+    """Run `program` (code: 24-byte instruction records, table, n_sites) over
+    the ND-range on the CPU in the paper's schedule.  args: Global (numpy
+    buffer, updated in place), Local (bytes) or Scalar (64-bit value)
+    objects.  Raises ProduceError when the kernel fails."""
+    L = _load()
+    code = np.ascontiguousarray(program.code)
+    assert code.dtype.itemsize == 24
+    dims = len(global_size)
+    g = (ctypes.c_uint32 * 3)(*(list(global_size) + [1] * (3 - dims)))
+    lo = (ctypes.c_uint32 * 3)(*(list(local_size) + [1] * (3 - dims)))
+    cargs = (OrcArg * max(1, len(args)))()
+    keep = []
+    for i, a in enumerate(args):
+        kind = a.kind
+        cargs[i].kind = kind
+        if kind == 0:
+            buf = a.array
+            assert buf.flags.c_contiguous
+            keep.append(buf)
+            cargs[i].host = buf.ctypes.data
+            cargs[i].bytes = buf.nbytes
+        elif kind == 1:
+            cargs[i].bytes = int(a.nbytes)
+        else:
+            cargs[i].value = int(a.value) & 0xFFFFFFFFFFFFFFFF
+    out = OrcProduced()
+    rc = L.orc_produce(code.ctypes.data, code.size, dims, g, lo, cargs, len(args), max_steps,
+                       ctypes.byref(out))
+    if rc != 0:
+        raise MemoryError("oracle producer ran out of memory")
+    if out.error:
+        raise ProduceError(out.error, out.error_wi)
+    try:
+        def arr(ptr, n, dt):
+            if n == 0:
+                return np.zeros(0, dtype=dt)
+            return np.ctypeslib.as_array(ctypes.cast(ptr, ctypes.POINTER(np.ctypeslib.as_ctypes_type(dt))),
+                                         shape=(n,)).copy()
+        arrays = (arr(out.opcode, out.n_events, np.uint16), arr(out.wi_offsets, out.n_wi + 1, np.uint64),
+                  arr(out.addr, out.n_mem, np.uint64), arr(out.mem_kind, out.n_mem, np.uint8),
+                  arr(out.mem_wi, out.n_mem, np.uint64), arr(out.br_site, out.n_branch, np.uint32),
+                  arr(out.br_taken, out.n_branch, np.uint8))
+    finally:
+        L.orc_produce_free(ctypes.byref(out))
+    wg = 1
+    for x in local_size:
+        wg *= int(x)
+    return ProducedTrace(program, arrays, wg)

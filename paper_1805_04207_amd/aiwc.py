@@ -105,6 +105,25 @@ class TrainOpts(ctypes.Structure):
                 ("reserved", ctypes.c_uint32)]
 
 
+class ProgramDesc(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("n_insn", ctypes.c_uint32),
+                ("code", ctypes.c_void_p), ("n_opcode_ids", ctypes.c_uint32),
+                ("n_sites", ctypes.c_uint32), ("opcode_table", ctypes.c_void_p)]
+
+
+class KernelArg(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_uint32), ("reserved", ctypes.c_uint32), ("ptr", ctypes.c_void_p),
+                ("bytes", ctypes.c_uint64), ("value", ctypes.c_uint64)]
+
+
+class NDRange(ctypes.Structure):
+    _fields_ = [("dims", ctypes.c_uint32), ("global_size", ctypes.c_uint32 * 3),
+                ("local_size", ctypes.c_uint32 * 3), ("reserved", ctypes.c_uint32)]
+
+
+ARG_GLOBAL, ARG_LOCAL, ARG_SCALAR = 0, 1, 2
+
+
 EXPORTS = [
     "aiwc_context_create", "aiwc_context_destroy", "aiwc_last_error", "aiwc_trace_create",
     "aiwc_trace_destroy", "aiwc_characterize", "aiwc_characterize_static",
@@ -116,6 +135,8 @@ EXPORTS = [
     "aiwc_sizer_features", "aiwc_sizer_train", "aiwc_sizer_predict", "aiwc_sizer_grad",
     "aiwc_sizer_num_params", "aiwc_sizer_get_params", "aiwc_sizer_set_params", "aiwc_sizer_save",
     "aiwc_sizer_load", "aiwc_sizer_set_margin", "aiwc_profile_enable", "aiwc_profile_read",
+    "aiwc_program_create", "aiwc_program_destroy", "aiwc_produce", "aiwc_produced_desc",
+    "aiwc_produced_to_host", "aiwc_produced_destroy",
 ]
 
 _lib = None
@@ -170,6 +191,13 @@ def load_library(path: str = LIB_PATH):
         "aiwc_sizer_set_margin": (st, [vp, ctypes.c_float]),
         "aiwc_profile_enable": (st, [vp, ctypes.c_int]),
         "aiwc_profile_read": (st, [vp, ctypes.c_char_p, sz, vp, sz, ctypes.POINTER(sz)]),
+        "aiwc_program_create": (st, [vp, ctypes.POINTER(ProgramDesc), ctypes.POINTER(vp)]),
+        "aiwc_program_destroy": (st, [vp]),
+        "aiwc_produce": (st, [vp, ctypes.POINTER(NDRange), vp, ctypes.c_uint32, u64, vp,
+                              ctypes.POINTER(vp)]),
+        "aiwc_produced_desc": (st, [vp, ctypes.POINTER(TraceDesc)]),
+        "aiwc_produced_to_host": (st, [vp, vp, vp, vp, vp, vp, vp]),
+        "aiwc_produced_destroy": (st, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -250,6 +278,10 @@ class Context:
         self.check(self.lib.aiwc_characterize_merged(self.h, arr, n, _stream_ptr(stream),
                                                      ctypes.byref(m)))
         return Metrics(self, m)
+
+    def program(self, code, table, n_sites: int) -> "Program":
+        """A kernel program for the trace producer (aiwc_program_create)."""
+        return Program(self, code, table, n_sites)
 
     def stream(self, mem_hint: int = 0, branch_hint: int = 0,
                host_retain: bool = False) -> "Stream":
@@ -527,3 +559,111 @@ class Metrics:
             self.close()
         except Exception:
             pass
+
+
+class Program:
+    """aiwc_program: a kernel program (24-byte instruction records, numpy)
+    with its opcode table and number of branch sites."""
+
+    def __init__(self, ctx: Context, code, table, n_sites: int):
+        import numpy as np
+        self.ctx = ctx
+        self._code = np.ascontiguousarray(code)
+        if self._code.dtype.itemsize != 24:
+            raise ValueError("instruction records are 24 bytes")
+        tab = np.asarray(table)
+        self._table = (OpcodeInfo * len(tab))()
+        for i, e in enumerate(tab):
+            self._table[i] = OpcodeInfo(int(e["op_class"]), int(e["simd_width"]), int(e["kind"]))
+        d = ProgramDesc(ctypes.sizeof(ProgramDesc), self._code.size, self._code.ctypes.data,
+                        len(tab), int(n_sites), ctypes.cast(self._table, ctypes.c_void_p))
+        h = ctypes.c_void_p()
+        ctx.check(ctx.lib.aiwc_program_create(ctx.h, ctypes.byref(d), ctypes.byref(h)))
+        self.h = h
+
+    def produce(self, global_size, local_size, args, max_steps: int = 0, stream=None) -> "Produced":
+        """Run the program; args are (ARG_GLOBAL, cuda tensor), (ARG_LOCAL,
+        bytes) or (ARG_SCALAR, value) pairs.  Global tensors are updated."""
+        n = len(args)
+        ca = (KernelArg * max(1, n))()
+        for i, (kind, v) in enumerate(args):
+            ca[i].kind = kind
+            if kind == ARG_GLOBAL:
+                ca[i].ptr = v.data_ptr()
+                ca[i].bytes = v.numel() * v.element_size()
+            elif kind == ARG_LOCAL:
+                ca[i].bytes = int(v)
+            else:
+                ca[i].value = int(v) & 0xFFFFFFFFFFFFFFFF
+        nd = NDRange()
+        nd.dims = len(global_size)
+        for i in range(3):
+            nd.global_size[i] = int(global_size[i]) if i < len(global_size) else 1
+            nd.local_size[i] = int(local_size[i]) if i < len(local_size) else 1
+        h = ctypes.c_void_p()
+        self.ctx.check(self.ctx.lib.aiwc_produce(self.h, ctypes.byref(nd), ca, n, int(max_steps),
+                                                 _stream_ptr(stream), ctypes.byref(h)))
+        return Produced(self.ctx, h)
+
+    def close(self):
+        if self.h:
+            self.ctx.lib.aiwc_program_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Produced:
+    """aiwc_produced: the trace arrays of one launch, on the device."""
+
+    def __init__(self, ctx: Context, h):
+        self.ctx = ctx
+        self.h = h
+        self.desc = TraceDesc()
+        ctx.check(ctx.lib.aiwc_produced_desc(h, ctypes.byref(self.desc)))
+
+    def to_host(self) -> Dict:
+        import numpy as np
+        d = self.desc
+        out = {"opcode": np.zeros(d.n_events, np.uint16),
+               "wi_offsets": np.zeros(d.n_workitems + 1, np.uint64),
+               "addr": np.zeros(d.n_mem, np.uint64), "mem_kind": np.zeros(d.n_mem, np.uint8),
+               "br_site": np.zeros(d.n_branch, np.uint32),
+               "br_taken": np.zeros(d.n_branch, np.uint8)}
+        keys = ("opcode", "wi_offsets", "addr", "mem_kind", "br_site", "br_taken")
+        self.ctx.check(self.ctx.lib.aiwc_produced_to_host(self.h, *[out[k].ctypes.data for k in keys]))
+        return out
+
+    def trace(self, history_len: int = 16, branch_flags: int = 0) -> "ProducedTrace":
+        return ProducedTrace(self, history_len, branch_flags)
+
+    def close(self):
+        if self.h:
+            self.ctx.lib.aiwc_produced_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class ProducedTrace(Trace):
+    """aiwc_trace over a produced trace's arrays (keeps the producer alive)."""
+
+    def __init__(self, produced: Produced, history_len: int = 16, branch_flags: int = 0):
+        ctx = produced.ctx
+        self.ctx = ctx
+        self._keep = produced
+        d = TraceDesc.from_buffer_copy(produced.desc)
+        d.history_len = history_len
+        d.flags = int(branch_flags)
+        self.desc = d
+        h = ctypes.c_void_p()
+        ctx.check(ctx.lib.aiwc_trace_create(ctx.h, ctypes.byref(d), ctypes.byref(h)))
+        self.h = h
