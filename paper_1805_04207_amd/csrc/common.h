@@ -36,6 +36,7 @@ struct DevAccum {
   u64 bad_mem;
   u64 pat_lo, pat_hi;        // pattern entropy sum, 2^-64 units
   u64 split_fail;            // on-chip tables that could not be split further
+  u64 br_queue2, br_big_n;   // windows blocks left to the hash-table kernel
   u64 pad[1];
 };
 
