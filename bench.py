@@ -286,12 +286,15 @@ def stress_leg(ctx, args, sizing, stream):
             "total_partitions": st["total_partitions"]}
 
 
-def cpu_leg(args):
+def cpu_leg(args, small=None):
     """The C oracle on bounded samples of the benchmarked recipe, on the
     host's own cores: one thread on one sample trace, then one thread per
     sample trace on as many traces as the box's share of cores (parallel
     across traces, as the oracle is meant to scale), median of three runs
-    each.  Trace generation is not timed."""
+    each.  Trace generation is not timed.  This leg is also where the bench
+    consults the oracle otherwise: the small-trace leg's metrics (`small`,
+    the GPU result) are compared with the oracle's, and the oracle's trace
+    producer is timed on the small kernel suite."""
     import statistics
     import threading
     import oracle
@@ -331,8 +334,23 @@ def cpu_leg(args):
                     break
     except OSError:
         pass
+    checks = {}
+    if small is not None:
+        from oracle.compare import compare
+        h1 = tg.generate_host(tg.config1())
+        bad = compare(small.pop("metrics"), oracle.characterize(h1))
+        checks["config1_parity"] = {"ok": not bad, "mismatches": bad[:5]}
+    from tracegen import kernels as K
+    n, t = 0, 0.0
+    for L in K.suite(scale=1, seed=7):
+        t0 = time.perf_counter()
+        tr = oracle.produce(L.program, L.global_size, L.local_size, L.fresh_args())
+        t += time.perf_counter() - t0
+        n += int(tr.opcode.size)
+    checks["producer_events_per_s_one_thread"] = n / t
+    checks["producer_sample"] = f"the ten-kernel suite at scale 1 ({n} events)"
     return {"value": sum(ev) / statistics.median(tn), "unit": "events/s", "cores": nthr,
-            "kind": "oracle",
+            "kind": "oracle", "checks": checks,
             "sample": f"{nthr} config2-recipe traces of 2^{w} work-items (seeds 1, 101, ..; "
                       f"{sum(ev)} events in total), one C-oracle thread per trace, median of 3 "
                       f"runs; single thread: the first trace ({ev[0]} events)",
@@ -343,20 +361,18 @@ def cpu_leg(args):
 
 def config1_leg(ctx, stream, steps):
     """The small trace (config1 recipe, ~5e5 events): device time per
-    characterization (HIP events, median) and parity with the C oracle."""
+    characterization (HIP events, median); its metrics go to the CPU leg,
+    which compares them with the oracle's."""
     import statistics
     import torch
-    import oracle
     import tracegen as tg
     import paper_1805_04207_amd as aiwc
-    from oracle.compare import compare
 
     spec = tg.config1()
     h = tg.generate_host(spec)
     dev = aiwc.host_to_device(h, 0)
     tr = aiwc.device_trace(ctx, dev, h.table, spec.n_sites, spec.history_len, spec.wg_size)
     got = ctx.characterize(tr, stream).read()
-    bad = compare(got, oracle.characterize(h))
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     dev_us, wall_us = [], []
     for _ in range(max(10, steps)):
@@ -371,8 +387,61 @@ def config1_leg(ctx, stream, steps):
     return {"events": int(h.opcode.size), "memory_events": int(h.addr.size),
             "branch_events": int(h.br_site.size), "us_per_characterization": us,
             "events_per_s": h.opcode.size / (us * 1e-6),
-            "wall_us_with_read": statistics.median(wall_us),
-            "parity_with_oracle": not bad, "mismatches": bad[:5]}
+            "wall_us_with_read": statistics.median(wall_us), "metrics": got}
+
+
+def producer_leg(ctx, stream, steps):
+    """The trace producer (kernel programs interpreted on the GPU, one
+    thread per work-item): for three kernels of the suite at a larger size,
+    the wall time of aiwc_produce (two runs of the kernel, counts, offsets,
+    the event arrays; synchronous), events produced per second, and the
+    device time of characterizing the produced trace (the oracle's
+    interpreter is timed in the CPU leg)."""
+    import statistics
+    import numpy as np
+    import torch
+    import paper_1805_04207_amd as aiwc
+    from tracegen import kernels as K
+
+    launches = [K.stencil2d(1024, 1024, seed=1), K.matmul_tiled(256, seed=2),
+                K.crc32(1 << 16, 8, seed=3)]
+    rows = []
+    for L in launches:
+        p = L.program
+        prog = ctx.program(p.code, p.table, p.n_sites)
+        args = []
+        for a in L.args:
+            if isinstance(a, K.Global):
+                args.append((aiwc.aiwc.ARG_GLOBAL,
+                             torch.from_numpy(a.array.copy().view(np.uint8)).to("cuda:0")))
+            elif isinstance(a, K.Local):
+                args.append((aiwc.aiwc.ARG_LOCAL, a.nbytes))
+            else:
+                args.append((aiwc.aiwc.ARG_SCALAR, a.value))
+        wall = []
+        prod = None
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            prod = prog.produce(L.global_size, L.local_size, args, stream=stream)
+            wall.append(1e3 * (time.perf_counter() - t0))
+        d = prod.desc
+        tr = prod.trace()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ms = []
+        for _ in range(max(3, steps // 2)):
+            e0.record(stream)
+            m = ctx.characterize(tr, stream)
+            e1.record(stream)
+            m.read()
+            ms.append(e0.elapsed_time(e1))
+        pm = statistics.median(wall)
+        rows.append({"kernel": p.name, "work_items": int(d.n_workitems), "events": int(d.n_events),
+                     "memory_events": int(d.n_mem), "branch_events": int(d.n_branch),
+                     "produce_ms": pm, "produce_events_per_s": d.n_events / (pm * 1e-3),
+                     "characterize_ms": statistics.median(ms)})
+        del tr, prod, prog
+    return {"kernels": rows}
 
 
 def sizing_leg(ctx, args):
@@ -406,6 +475,7 @@ def main() -> int:
     ap.add_argument("--no-sizing", action="store_true",
                     help="skip the BOUND / HEURISTIC / LEARNED sizing leg")
     ap.add_argument("--sizing-traces", type=int, default=256)
+    ap.add_argument("--no-producer", action="store_true", help="skip the trace-producer leg")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched legs")
     ap.add_argument("--no-stress", action="store_true", help="skip the stress batch leg")
     ap.add_argument("--batch-traces", type=int, default=512)
@@ -523,16 +593,25 @@ def main() -> int:
     small = None
     if not args.no_config1:
         small = config1_leg(ctx, stream, args.steps)
-        print(f"# config1: {small['us_per_characterization']:.1f} us, parity "
-              f"{small['parity_with_oracle']}", file=sys.stderr, flush=True)
+        print(f"# config1: {small['us_per_characterization']:.1f} us", file=sys.stderr, flush=True)
 
     sizing = None
     if not args.no_sizing:
         sizing = sizing_leg(ctx, args)
 
+    produced = None
+    if not args.no_producer:
+        produced = producer_leg(ctx, stream, args.steps)
+        print("# producer: " + ", ".join(f"{r['kernel']} {r['produce_events_per_s']:.2e} ev/s"
+                                         for r in produced["kernels"]), file=sys.stderr, flush=True)
+
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_leg(args)
+        cpu = cpu_leg(args, small)
+        if small is not None:
+            small["parity_with_oracle"] = cpu["checks"]["config1_parity"]["ok"]
+    if small is not None:
+        small.pop("metrics", None)
         print(f"# cpu oracle: {cpu['value']:.3e} events/s on {cpu['cores']} threads, "
               f"{cpu['single_thread']['value']:.3e} on one", file=sys.stderr, flush=True)
 
@@ -556,7 +635,8 @@ def main() -> int:
                    "partitions": r["partitions"],
                    "overflow_redos": r["overflow_redos"], "streamed": streamed,
                    "branch_variants": variants,
-                   "batched": batched, "config1": small, "sizing": sizing},
+                   "batched": batched, "config1": small, "sizing": sizing,
+                   "producer": produced},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "target_frac": TARGET_FRAC,
                      "limiter": "on-chip work per record (VALU issue and LDS round trips at "

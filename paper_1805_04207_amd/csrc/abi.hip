@@ -435,6 +435,8 @@ extern "C" aiwc_status aiwc_context_destroy(aiwc_ctx *ctx) {
   ctx->prof.release();
   sizer_free(ctx);
   batch_free(ctx);
+  for (auto &b : ctx->result_pool) hipFree(b.second);
+  for (hipEvent_t e : ctx->event_pool) hipEventDestroy(e);
   delete ctx;
   return AIWC_OK;
 }
@@ -555,6 +557,15 @@ extern "C" aiwc_status aiwc_trace_destroy(aiwc_trace *t) {
 }
 
 // ------------------------------------------------------------ characterize
+// Result blocks come in power-of-two sizes from 4 KiB, so that a destroyed
+// handle's block serves the next call of any trace of the same size class.
+static const size_t POOL_MAX = 64;
+static u64 result_class(u64 bytes) {
+  u64 c = 4096;
+  while (c < bytes) c <<= 1;
+  return c;
+}
+
 aiwc_status new_metrics(aiwc_ctx *ctx, const aiwc_trace *t, const TracePlan &p,
                         aiwc_metrics **out, SharedBuf *shared, void *buf) {
   aiwc_metrics *m = new aiwc_metrics();
@@ -565,13 +576,27 @@ aiwc_status new_metrics(aiwc_ctx *ctx, const aiwc_trace *t, const TracePlan &p,
     m->shared = shared;
     m->buf = buf;
     shared->refs += 1;
-  } else if (hipMalloc(&m->buf, p.result_bytes) != hipSuccess) {
-    hipGetLastError();
-    delete m;
-    ctx_error(ctx, "out of device memory for a result buffer");
-    return AIWC_ERR_OUT_OF_MEMORY;
+  } else {
+    const u64 cls = result_class(p.result_bytes);
+    for (size_t i = ctx->result_pool.size(); i-- > 0;) {
+      if (ctx->result_pool[i].first == cls) {
+        m->buf = ctx->result_pool[i].second;
+        ctx->result_pool.erase(ctx->result_pool.begin() + (long)i);
+        break;
+      }
+    }
+    if (!m->buf && hipMalloc(&m->buf, cls) != hipSuccess) {
+      hipGetLastError();
+      delete m;
+      ctx_error(ctx, "out of device memory for a result buffer");
+      return AIWC_ERR_OUT_OF_MEMORY;
+    }
+    m->buf_bytes = cls;
   }
-  if (hipEventCreateWithFlags(&m->done, hipEventDisableTiming) != hipSuccess) {
+  if (!ctx->event_pool.empty()) {
+    m->done = ctx->event_pool.back();
+    ctx->event_pool.pop_back();
+  } else if (hipEventCreateWithFlags(&m->done, hipEventDisableTiming) != hipSuccess) {
     if (!shared) hipFree(m->buf); else shared->refs -= 1;
     delete m;
     ctx_error(ctx, "hipEventCreate failed");
@@ -857,14 +882,20 @@ extern "C" aiwc_status aiwc_metrics_spectrum(aiwc_metrics *m, int space, uint64_
 
 extern "C" aiwc_status aiwc_metrics_destroy(aiwc_metrics *m) {
   if (!m) return AIWC_OK;
-  if (m->done) { hipEventSynchronize(m->done); hipEventDestroy(m->done); }
+  aiwc_ctx *ctx = m->ctx;
+  if (m->done) {
+    hipEventSynchronize(m->done);
+    if (ctx->event_pool.size() < POOL_MAX) ctx->event_pool.push_back(m->done);
+    else hipEventDestroy(m->done);
+  }
   if (m->shared) {
     if (--m->shared->refs == 0) {
       hipFree(m->shared->p);
       delete m->shared;
     }
   } else if (m->buf) {
-    hipFree(m->buf);
+    if (m->buf_bytes && ctx->result_pool.size() < POOL_MAX) ctx->result_pool.push_back({m->buf_bytes, m->buf});
+    else hipFree(m->buf);
   }
   if (m->stage) hipFree(m->stage);
   delete m;

@@ -82,6 +82,10 @@ struct aiwc_ctx {
   bool single_stream = false;      // AIWC_SINGLE_STREAM: no side stream
   std::vector<std::pair<std::string, Tune>> tune_cache;  // class key -> best shape
   bool tune_loaded = false;
+  // result blocks and completion events of destroyed metrics handles, kept
+  // for the next characterizations (no allocation in a steady loop)
+  std::vector<std::pair<u64, void *>> result_pool;      // (bytes, device block)
+  std::vector<hipEvent_t> event_pool;
 };
 
 struct aiwc_trace {
@@ -104,6 +108,7 @@ struct aiwc_metrics {
   TracePlan plan;
   u32 n_classes = 0;
   void *buf = nullptr;
+  u64 buf_bytes = 0;             // size of an owned (pooled) result block
   SharedBuf *shared = nullptr;   // set when buf points into a batch block
   hipEvent_t done = nullptr;
   u32 spec_pairs[2] = {0, 0};
