@@ -120,6 +120,13 @@ void plan_trace(const aiwc_trace *t, u32 pbits, TracePlan &p, const Tune *tune, 
   p.o_br_b = take(rec * std::max<u64>(1, d.n_branch));
   p.o_br_cnt = take(4ull * 256 * std::max<u64>(1, p.br_tiles));
   p.o_scan_tmp = take(4ull * aiwc_kernels::scan_tmp_elems(256 * std::max<u64>(1, p.br_tiles)));
+  // hot site segments (longer than a windows work block, per-site
+  // histories of m <= 16): a table of 2^m 64-bit counters each, for up to 64
+  p.br_hot_cap = 0;
+  if (!(d.flags & AIWC_BRANCH_GLOBAL_HISTORY) && d.history_len <= 16 && d.n_branch > AIWC_SORT_CAP)
+    p.br_hot_cap = (u32)std::min<u64>(64, d.n_branch / AIWC_SORT_CAP);
+  p.o_br_hot_list = take(8ull * std::max<u32>(1, p.br_hot_cap));
+  p.o_br_hot_tab = take(p.br_hot_cap ? (8ull << d.history_len) * p.br_hot_cap : 8);
   p.scratch_bytes = o;
   p.spec_export_cap = std::min<u32>(p.sp_cap, 65536);
   // result buffer: metrics, 4 status words, class histogram, spectrum pairs
@@ -188,6 +195,9 @@ void fill_args(const aiwc_trace *t, const TracePlan &p, char *scratch, char *res
   a.br_a = (u32 *)(scratch + p.o_br_a);
   a.br_b = (u32 *)(scratch + p.o_br_b);
   a.br_cnt = (u32 *)(scratch + p.o_br_cnt);
+  a.br_hot_list = (u32 *)(scratch + p.o_br_hot_list);
+  a.br_hot_tab = (unsigned long long *)(scratch + p.o_br_hot_tab);
+  a.br_hot_cap = p.br_hot_cap;
   a.pat_hist = (d.flags & AIWC_BRANCH_PATTERN_ENTROPY) ? (u32 *)(scratch + p.o_pat_hist) : nullptr;
   a.br_flags = d.flags & (AIWC_BRANCH_ZERO_HISTORY | AIWC_BRANCH_GLOBAL_HISTORY |
                           AIWC_BRANCH_PATTERN_ENTROPY);
@@ -219,6 +229,7 @@ void add_dims(const aiwc_trace *t, const TracePlan &p, const TraceArgs &a, Batch
   if (D.n_branch) {
     d.any_branch = true;
     if (D.flags & AIWC_BRANCH_GLOBAL_HISTORY) d.any_global = true; else d.any_local = true;
+    if (p.br_hot_cap) d.any_hot = true;
     if (D.flags & AIWC_BRANCH_PATTERN_ENTROPY) {
       d.any_pattern = true;
       d.max_pattern_bins = std::max<u32>(d.max_pattern_bins, 1u << D.history_len);

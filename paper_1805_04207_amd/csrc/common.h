@@ -19,6 +19,7 @@ typedef unsigned int u32;
 #define AIWC_STAGE_CAP 16384 // records the bucket kernel stages on chip per round
 #define VAL_DENSE 65536      // ITB / IPT value histograms are dense below this
 #define TWO_LEVEL_PBITS 12   // partitions from 2^12 on are scattered in two passes
+#define AIWC_SORT_CAP 16384  // branch records one windows work block counts on chip
 struct DevAccum {
   u64 itb_min_inv, itb_max, itb_cnt, itb_sum;   // min stored as max of ~v
   u64 ipt_min_inv, ipt_max, ipt_cnt, ipt_sum;
@@ -36,8 +37,8 @@ struct DevAccum {
   u64 bad_mem;
   u64 pat_lo, pat_hi;        // pattern entropy sum, 2^-64 units
   u64 split_fail;            // on-chip tables that could not be split further
-  u64 br_queue2, br_big_n;   // windows blocks left to the hash-table kernel
-  u64 pad[1];
+  u64 br_queue2, br_big_n;   // windows ranges left to the hash-table kernel
+  u64 br_hot_n, br_piece_q;  // hot site segments registered, their pieces taken
 };
 
 // Everything a kernel needs to know about one trace and its scratch.
@@ -84,7 +85,12 @@ struct TraceArgs {
   u32 *part_cur;             // [P + 512] fine cursors, coarse cursors, coarse tile starts
   u32 *part_tag;             // [n_mem] page slot and position of each record (bucket kernel)
   u32 *br_a, *br_b;          // [n_branch] radix ping-pong
-  u32 *br_cnt;               // [256 * br_tiles]
+  u32 *br_cnt;               // [256 * br_tiles]; after the sort: (start, end) ranges
+                             // left to the hash-table windows kernel
+  u32 *br_hot_list;          // [2 * br_hot_cap] (start, end) of hot site segments
+  unsigned long long *br_hot_tab; // [br_hot_cap << m] n0 | n1 << 32 per history
+  u32 br_hot_cap;            // hot segments with a table (0: none)
+  u32 pad2;
   u32 *pat_hist;             // [2^m] windows per history pattern (pattern entropy)
   u32 *scan_tmp;             // block sums for the generic scan
   // result (device)
@@ -217,6 +223,7 @@ struct BatchDims {
   bool any_two_level = false, any_one_level = false;   // memory scatter paths in use
   bool any_local = false, any_global = false;   // branch history variants present
   bool any_pattern = false;                     // some trace wants the pattern entropy
+  bool any_hot = false;                         // some trace has hot-segment tables
   u32 max_pattern_bins = 0;
   bool vec = true;                    // every address / kind array 16 / 4 B aligned
   bool ops_vec = true;                // every opcode array 16 B aligned

@@ -368,8 +368,8 @@ __device__ __forceinline__ u32 win_insert(WinShared &S, u64 key, u32 a, u32 b, b
   }
 }
 
-// LISTED: the blocks are those the sorting kernel left in the list
-// (br_cnt, br_big_n entries), taken from a second queue.
+// LISTED: the ranges the sorting kernel left in the list (br_cnt, br_big_n
+// (start, end) pairs), taken from a second queue.
 template <bool BATCH, bool GLOBAL, bool LISTED>
 __global__ void __launch_bounds__(WIN_BLOCK) k_br_windows(TraceArgs A0, const TraceArgs *batch) {
   using R = typename std::conditional<GLOBAL, u64, u32>::type;
@@ -399,11 +399,11 @@ __global__ void __launch_bounds__(WIN_BLOCK) k_br_windows(TraceArgs A0, const Tr
   while (true) {
     const u64 q = S.next;
     if (q >= nblk) break;
-    const u64 b = LISTED ? (u64)A.br_cnt[q] : q;
     __syncthreads();
     // the next work block is fetched while this one is processed
     if (tid == 0) S.next = (u32)atomicAdd(queue, 1ull);
-    const u64 r0 = range_begin(A, sorted, b), r1 = range_begin(A, sorted, b + 1);
+    const u64 r0 = LISTED ? (u64)A.br_cnt[2 * q] : range_begin(A, sorted, q);
+    const u64 r1 = LISTED ? (u64)A.br_cnt[2 * q + 1] : range_begin(A, sorted, q + 1);
     if (r1 <= r0) { __syncthreads(); continue; }
     // a block holds at most r1 - r0 keys: split by key-hash bits up front so
     // that each pass stays within the table's cap (a pass that still
@@ -548,31 +548,40 @@ __global__ void __launch_bounds__(WIN_BLOCK) k_br_windows(TraceArgs A0, const Tr
 }
 
 // ------------------------------------------------ windows by LDS sort
-// A work block whose windows fit on chip (at most SORT_CAP of them, and
-// keys of at most 31 bits) is counted by sorting.  Each windowed execution
-// becomes the word (site - block's first site) << (m + 1) | history << 1 |
-// outcome; an LSD radix sort in LDS (digits of at most 9 bits; each
-// element's digit rank from wavefront ballots, kept in registers from the
-// counting step to the scatter step) puts equal words together; between
-// the boundaries of equal words, a key's run with outcome 0 is n0 and the
-// run with outcome 1 is n1.  One read of the block's records, no hashing,
-// no table passes.  Blocks that do not fit are listed (br_cnt, br_big_n)
-// for the hash-table kernel, which runs next on the same stream.
-constexpr u32 SORT_CAP = 16384;
+// A work block whose windows fit on chip is counted here rather than in a
+// hash table.  Each windowed execution becomes the word
+// (site - range's first site) << (m + 1) | history << 1 | outcome.
+//  - Few keys (key bits <= DENSE_BITS): a direct LDS table of counters, n0
+//    in the low and n1 in the high half of a key's word, in passes of
+//    DENSE_WORDS keys; each wave lists the keys it touched first, and only
+//    listed words are read back (and cleared).
+//  - More keys: an LSD radix sort of the words in LDS (digits of at most 9
+//    bits; each element's digit rank from wavefront ballots, kept in
+//    registers from the counting step to the scatter step); between the
+//    boundaries of equal words, a key's run with outcome 0 is n0 and the
+//    run with outcome 1 is n1.
+// A block larger than a sort block is its leading whole segments (fewer
+// than WIN_T records) and its last segment; a last segment longer than a
+// sort block with m <= 16 is a hot segment: it gets a table of 2^m 64-bit
+// counters (n0 | n1 << 32) in scratch, k_br_windows_hot counts its pieces
+// in parallel into that table and k_br_hot_terms reads it.  Ranges that fit
+// none of these are listed (br_cnt, br_big_n) for the hash-table kernel,
+// which runs last on the same stream.
+constexpr u32 SORT_CAP = AIWC_SORT_CAP;
 constexpr u32 SORT_WAVES = WIN_BLOCK / AIWC_WAVE;   // 16
 constexpr u32 SORT_CH = SORT_CAP / WIN_BLOCK;       // chunks of 64 per wave and pass
 constexpr u32 DIG_MAX = 9;
 constexpr u32 NBIN = 1u << DIG_MAX;
 constexpr u32 DENSE_BITS = 16;                      // key bits counted in a direct table
-constexpr u32 DENSE_WORDS = 2 * SORT_CAP;           // table words per pass (ka and kb)
+constexpr u32 DENSE_WORDS = 2 * SORT_CAP;           // table words per pass
 
 struct SortShared {
   u32 keys[2 * SORT_CAP];           // two key buffers, or one direct count table
-  uint16_t off[SORT_WAVES][NBIN];   // per wave digit counts, then offsets
+  uint16_t off[SORT_WAVES][NBIN];   // per wave digit counts / offsets, or key lists
   u64 tlo[256], thi[256];
   u32 wsum[NBIN / AIWC_WAVE];
   u64 minsum, windows, ylo, yhi;
-  u32 n, next, dirty, over;
+  u32 n, next, dirty, over, hidx, total;
 };
 
 // Smallest set bit at position >= p (a set bit at or after p must exist).
@@ -581,6 +590,340 @@ __device__ __forceinline__ u32 next_set(const u32 *bm, u32 p) {
   u32 x = bm[w] & (~0u << (p & 31));
   while (x == 0) x = bm[++w];
   return (w << 5) + (u32)__builtin_ctz(x);
+}
+
+// The records [r0, r1) of the site-sorted stream, s0 the site of r0.
+struct WordRange {
+  const u32 *sorted;
+  u64 r0, r1;
+  u32 s0, m;
+  u64 hmask;
+  bool zero;
+};
+
+// The range's windowed executions as words (~0 where the execution forms no
+// window), handed chunk by chunk to emit(t, word) with the whole wavefront
+// present.  Each wave takes a run of consecutive 64-record chunks, all of
+// whose loads are in flight at once; the chunk before its first supplies
+// the carried ballots (it may lie before r0: the previous records of the
+// same site give the history).  History: m outcome bits cut from the
+// ballots of two chunks (bit j = the execution m - j back).  Records are
+// sorted by site, so an execution has m earlier ones of its site exactly
+// when no site boundary lies among the last m positions; the zero-history
+// variant clears the history bits before the latest boundary.
+template <class Emit>
+__device__ __forceinline__ void range_words(const WordRange &R, u32 wave, int lane, Emit &&emit) {
+  const u32 m = R.m;
+  const u64 nch = (R.r1 - R.r0 + AIWC_WAVE - 1) / AIWC_WAVE;
+  const u64 cpw = (nch + SORT_WAVES - 1) / SORT_WAVES;     // <= 16
+  const u64 c0 = (u64)wave * cpw;
+  const u64 p0 = R.r0 + c0 * AIWC_WAVE;                    // first record of the wave
+  u32 pv[SORT_CH];
+#pragma unroll
+  for (u32 t = 0; t < SORT_CH; ++t) {
+    const u64 i = p0 + (u64)t * AIWC_WAVE + lane;
+    pv[t] = (t < cpw && i < R.r1) ? R.sorted[i] : 0u;
+  }
+  const bool have_prev = p0 >= AIWC_WAVE && c0 < nch;
+  const u32 vprev = have_prev ? R.sorted[p0 - AIWC_WAVE + lane] : 0u;
+  u64 Bo = __ballot(have_prev && (vprev & 1u));
+  const u32 sp = (u32)__shfl((int)(vprev >> 1), (int)(lane == 0 ? 0 : lane - 1), AIWC_WAVE);
+  u64 Bs = have_prev ? __ballot((vprev >> 1) != sp) : ~0ull;
+  u32 last_site = (u32)__builtin_amdgcn_readlane((int)(vprev >> 1), 63);
+  if (!have_prev) last_site = 0xFFFFFFFFu;
+#pragma unroll
+  for (u32 t = 0; t < SORT_CH; ++t) {
+    if (t >= cpw || c0 + t >= nch) { emit(t, ~0u); continue; }
+    const u64 i = p0 + (u64)t * AIWC_WAVE + lane;
+    const bool valid = i < R.r1;
+    const u32 v = pv[t], st = v >> 1;
+    const u32 left = (u32)__shfl((int)st, (int)(lane == 0 ? 0 : lane - 1), AIWC_WAVE);
+    const u32 before = lane == 0 ? last_site : left;
+    const u64 B = __ballot(valid && (v & 1u));
+    const u64 Bb = __ballot(!valid || st != before);
+    const u32 sh = 64u + (u32)lane - m;                 // in [34, 126]
+    u64 E = (sh >= 64) ? (B >> (sh - 64)) : ((Bo >> sh) | (B << (64 - sh)));
+    E &= R.hmask;
+    const u32 sb = sh + 1;                              // boundaries at the last m positions
+    u64 F = (sb >= 64) ? (Bb >> (sb - 64)) : ((Bs >> sb) | (Bb << (64 - sb)));
+    F &= R.hmask;
+    bool windowed;
+    if (R.zero) {
+      // a boundary at window bit j starts the segment at history bit j: the
+      // bits below it precede the site's first execution
+      if (F) {
+        const u32 q = 63u - (u32)__builtin_clzll(F);
+        E &= ~((2ull << q) - 1ull);
+      }
+      windowed = valid;
+    } else {
+      windowed = valid && F == 0;
+    }
+    emit(t, windowed ? (u32)((((u64)(st - R.s0)) << (m + 1)) | (E << 1) | (v & 1u)) : ~0u);
+    Bo = B;
+    Bs = Bb;
+    last_site = (u32)__builtin_amdgcn_readlane((int)st, 63);
+  }
+}
+
+// Direct-table count of the range's words (keys below 2^kb); take(key, n0,
+// n1) for every key present.  The table is left cleared.
+template <class Take>
+__device__ __forceinline__ void dense_count(SortShared &S, const WordRange &R, u32 kb, int tid,
+                                            u32 wave, int lane, u64 below, Take &&take) {
+  u32 *T = S.keys;
+  if (S.dirty) {
+    for (u32 j = tid; j < DENSE_WORDS; j += WIN_BLOCK) T[j] = 0;
+    __syncthreads();
+  }
+  const u32 nkeys = 1u << kb;
+  const u32 pk = nkeys < DENSE_WORDS ? nkeys : DENSE_WORDS;
+  uint16_t *const list = &S.off[wave][0];
+  for (u32 pass = 0; pass * pk < nkeys; ++pass) {
+    u32 nl = 0;   // wave-uniform list length
+    range_words(R, wave, lane, [&](u32, u32 w) {
+      const bool mine = w != ~0u && (w >> 1) / pk == pass;
+      u32 old = 1;
+      if (mine) old = atomicAdd(&T[(w >> 1) % pk], (w & 1u) ? 0x10000u : 1u);
+      const u64 F = __ballot(mine && old == 0);
+      const u32 at = nl + (u32)__builtin_popcountll(F & below);
+      if (mine && old == 0 && at < NBIN) list[at] = (uint16_t)((w >> 1) % pk);
+      nl += (u32)__builtin_popcountll(F);
+    });
+    if (lane == 0 && nl > NBIN) S.over = 1;   // a list overflowed: read every word
+    __syncthreads();
+    auto one = [&](u32 j) {
+      const u32 x = T[j];
+      if (!x) return;
+      T[j] = 0;
+      take(pass * pk + j, x & 0xFFFFu, x >> 16);
+    };
+    if (S.over) {
+      for (u32 j = tid; j < pk; j += WIN_BLOCK) one(j);
+    } else {
+      for (u32 q = (u32)lane; q < nl; q += AIWC_WAVE) one((u32)list[q]);
+    }
+    __syncthreads();
+    if (tid == 0) S.over = 0;
+    __syncthreads();
+  }
+  if (tid == 0) S.dirty = 0;
+}
+
+// Sorted count of the range's words (kbits <= 31 bits with the outcome, at
+// most SORT_CAP records); take(key, n0, n1) for every key present.
+template <class Take>
+__device__ __forceinline__ void sort_count(SortShared &S, const WordRange &R, u32 kbits, int tid,
+                                           u32 wave, int lane, u64 below, Take &&take) {
+  {
+    u32 kw[SORT_CH];
+    range_words(R, wave, lane, [&](u32 t, u32 w) { kw[t] = w; });
+    u32 cnt = 0;
+#pragma unroll
+    for (u32 t = 0; t < SORT_CH; ++t) cnt += (u32)__builtin_popcountll(__ballot(kw[t] != ~0u));
+    u32 base = 0;
+    if (lane == 0 && cnt) base = atomicAdd(&S.n, cnt);
+    base = (u32)__builtin_amdgcn_readfirstlane((int)base);
+#pragma unroll
+    for (u32 t = 0; t < SORT_CH; ++t) {
+      const u64 W = __ballot(kw[t] != ~0u);
+      if (kw[t] != ~0u) S.keys[base + (u32)__builtin_popcountll(W & below)] = kw[t];
+      base += (u32)__builtin_popcountll(W);
+    }
+  }
+  if (tid == 0) S.dirty = 1;
+  __syncthreads();
+  const u32 N = S.n;
+  // LSD radix passes over bits [0, kbits)
+  u32 *src = S.keys, *dst = S.keys + SORT_CAP;
+  const u32 per = ((N + SORT_WAVES - 1) / SORT_WAVES + 63u) & ~63u;   // <= 1024
+  const u32 w0 = wave * per;
+  const u32 passes = (kbits + DIG_MAX - 1) / DIG_MAX;
+  u32 shift = 0;
+  for (u32 p = 0; p < passes; ++p) {
+    const u32 db = (kbits - shift + (passes - p) - 1) / (passes - p);
+    const u32 nbin = 1u << db, dmask = nbin - 1u;
+    for (u32 j = (u32)lane; j < nbin; j += AIWC_WAVE) S.off[wave][j] = 0;
+    // per element: the key, and its in-chunk rank | group leader << 6 |
+    // group size << 12 (the size on the leader only); ranks from ballots ...
+    u32 key[SORT_CH], rk[SORT_CH];
+#pragma unroll
+    for (u32 c = 0; c < SORT_CH; ++c) {
+      const u32 e = w0 + c * AIWC_WAVE + (u32)lane;
+      const bool ok = c * AIWC_WAVE < per && e < N;
+      const u32 kv = ok ? src[e] : 0u;
+      key[c] = kv;
+      rk[c] = (u32)lane << 6;
+      const u64 any = __ballot(ok);
+      if (any == 0) continue;
+      const u32 dg = (kv >> shift) & dmask;
+      u64 peers = any;
+      for (u32 bb = 0; bb < db; ++bb) {
+        const bool bit = (dg >> bb) & 1u;
+        const u64 bm = __ballot(bit);
+        peers &= bit ? bm : ~bm;
+      }
+      if (ok) {
+        const u32 ld = (u32)__builtin_ctzll(peers);
+        rk[c] = (u32)__builtin_popcountll(peers & below) | (ld << 6);
+        if ((u32)lane == ld) rk[c] |= (u32)__builtin_popcountll(peers) << 12;
+      }
+    }
+    // ... every chunk's group counts added in chunk order (LDS atomics of one
+    // wave complete in issue order), two u16 counters per word ...
+    u32 pos[SORT_CH];
+#pragma unroll
+    for (u32 c = 0; c < SORT_CH; ++c) {
+      pos[c] = 0;
+      const u32 g = rk[c] >> 12;
+      if (g) {
+        const u32 dg = (key[c] >> shift) & dmask, hs = (dg & 1u) * 16u;
+        u32 *w = reinterpret_cast<u32 *>(&S.off[wave][dg & ~1u]);
+        pos[c] = (atomicAdd(w, g << hs) >> hs) & 0xFFFFu;
+      }
+    }
+    // ... and the groups' bases handed to their lanes: pos = rank in wave
+#pragma unroll
+    for (u32 c = 0; c < SORT_CH; ++c)
+      pos[c] = (u32)__shfl((int)pos[c], (int)((rk[c] >> 6) & 63u), AIWC_WAVE) + (rk[c] & 63u);
+    __syncthreads();
+    // offsets in (digit, wave) order
+    u32 excl = 0;
+    if ((u32)tid < nbin) {
+      u32 run = 0;
+#pragma unroll
+      for (u32 w = 0; w < SORT_WAVES; ++w) run += S.off[w][tid];
+      u32 x = run;
+      for (int o = 1; o < AIWC_WAVE; o <<= 1) {
+        const u32 y = (u32)__shfl_up((int)x, o, AIWC_WAVE);
+        if (lane >= o) x += y;
+      }
+      const u32 last = nbin < AIWC_WAVE ? nbin - 1u : (u32)AIWC_WAVE - 1u;
+      if ((u32)lane == last) S.wsum[wave] = x;
+      excl = x - run;
+    }
+    __syncthreads();
+    if ((u32)tid < nbin) {
+      u32 base = excl;
+      for (u32 w = 0; w < wave; ++w) base += S.wsum[w];
+#pragma unroll
+      for (u32 w = 0; w < SORT_WAVES; ++w) {
+        const u32 c = S.off[w][tid];
+        S.off[w][tid] = (uint16_t)base;
+        base += c;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (u32 c = 0; c < SORT_CH; ++c) {
+      const u32 e = w0 + c * AIWC_WAVE + (u32)lane;
+      if (c * AIWC_WAVE < per && e < N) {
+        const u32 dg = (key[c] >> shift) & dmask;
+        dst[S.off[wave][dg] + pos[c]] = key[c];
+      }
+    }
+    __syncthreads();
+    u32 *t = src; src = dst; dst = t;
+    shift += db;
+  }
+  // boundaries of equal words as a bitmap (bit N: a sentinel), for the runs
+  // that leave their chunk
+  u32 *bm = dst;
+  for (u32 cb = wave * AIWC_WAVE; cb < N; cb += WIN_BLOCK) {
+    const u32 e = cb + (u32)lane;
+    const bool ok = e < N;
+    const u32 v = ok ? src[e] : 0u;
+    const u32 vq = (ok && e > 0) ? src[e - 1] : 0u;
+    const u64 Bd = __ballot(ok && (e == 0 || v != vq));
+    if (lane == 0) bm[cb >> 5] = (u32)Bd;
+    if (lane == 1) bm[(cb >> 5) + 1] = (u32)(Bd >> 32);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    if ((N & 63) == 0) { bm[N >> 5] = 0; bm[(N >> 5) + 1] = 0; }
+    bm[N >> 5] |= 1u << (N & 31);
+  }
+  __syncthreads();
+  // every key's (n0, n1) from its runs: a run's end is the next boundary,
+  // found in the chunk's boundary ballot unless the run leaves the chunk
+  for (u32 cb = wave * AIWC_WAVE; cb < N; cb += WIN_BLOCK) {
+    const u32 e = cb + (u32)lane;
+    const bool ok = e < N;
+    const u32 v = ok ? src[e] : 0u;
+    const u32 vq = (ok && e > 0) ? src[e - 1] : 0u;
+    u64 Bd = __ballot(ok && (e == 0 || v != vq));
+    if (N - cb < 64) Bd |= 1ull << (N - cb);            // the sentinel
+    const bool head = ok && ((Bd >> lane) & 1ull);
+    const u64 above = (lane == 63) ? 0ull : (Bd & ~((2ull << lane) - 1ull));
+    const u32 e1 = above ? cb + (u32)__builtin_ctzll(above) : 0u;
+    const u32 j1 = above ? (u32)__builtin_ctzll(above) : 0u;
+    const u32 v1s = (u32)__shfl((int)v, (int)(j1 & 63u), AIWC_WAVE);
+    if (!head) continue;
+    if ((v & 1u) && e > 0 && (vq >> 1) == (v >> 1)) continue;   // its key's second run
+    const u32 end1 = above ? e1 : next_set(bm, cb + AIWC_WAVE);
+    u32 a, c;
+    if (v & 1u) { a = 0; c = end1 - e; }
+    else {
+      a = end1 - e;
+      c = 0;
+      if (end1 < N) {
+        const bool inside = end1 < cb + AIWC_WAVE;
+        const u32 v1 = inside ? v1s : src[end1];
+        if (v1 == (v | 1u)) {
+          u64 above2 = 0;
+          if (inside) {
+            const u32 j = end1 - cb;
+            above2 = (j == 63) ? 0ull : (Bd & ~((2ull << j) - 1ull));
+          }
+          const u32 end2 = above2 ? cb + (u32)__builtin_ctzll(above2)
+                                  : next_set(bm, inside ? cb + AIWC_WAVE : end1 + 1);
+          c = end2 - end1;
+        }
+      }
+    }
+    take(v >> 1, a, c);
+  }
+}
+
+// Window statistics of keys with counts (n0, n1): exact integer sums and
+// 2^-64 fixed-point Yokota terms (order independent).
+struct Terms {
+  u64 mins = 0, wins = 0, lo = 0, hi = 0;
+  __device__ __forceinline__ void add(u32 a, u32 c, const u64 *tlo, const u64 *thi) {
+    mins += a < c ? a : c;
+    wins += (u64)a + c;
+    u64 tl, th;
+    if (a < 16 && c < 16) { tl = tlo[a * 16 + c]; th = thi[a * 16 + c]; }
+    else yterm(a, c, tl, th);
+    const u64 nl = lo + tl;
+    hi += th + (nl < lo);
+    lo = nl;
+  }
+  // block reduction into the trace's accumulators (all threads call it)
+  __device__ __forceinline__ void flush(const TraceArgs &A, u64 *sm) {
+    mins = wave_sum_u64(mins);
+    wins = wave_sum_u64(wins);
+    wave_sum_u128(lo, hi);
+    if (threadIdx.x == 0) sm[0] = sm[1] = sm[2] = sm[3] = 0;
+    __syncthreads();
+    if (lane_id() == 0) {
+      if (mins) atomicAdd(&sm[0], mins);
+      if (wins) atomicAdd(&sm[1], wins);
+      atomic_add_u128(&sm[2], &sm[3], lo, hi);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      if (sm[0]) atomicAdd(&A.acc->br_minsum, sm[0]);
+      if (sm[1]) atomicAdd(&A.acc->br_windows, sm[1]);
+      atomic_add_u128(&A.acc->yok_lo, &A.acc->yok_hi, sm[2], sm[3]);
+    }
+  }
+};
+
+__device__ __forceinline__ void list_range(const TraceArgs &A, u64 r0, u64 r1) {
+  const u64 k = atomicAdd(&A.acc->br_big_n, 1ull);
+  A.br_cnt[2 * k] = (u32)r0;
+  A.br_cnt[2 * k + 1] = (u32)r1;
 }
 
 template <bool BATCH>
@@ -598,12 +941,31 @@ __global__ void __launch_bounds__(WIN_BLOCK) k_br_windows_sort(TraceArgs A0, con
   const u64 below = (1ull << lane) - 1ull;
   if (tid < 256) yterm(tid >> 4, tid & 15, S.tlo[tid], S.thi[tid]);
   if (tid == 0) {
-    S.minsum = S.windows = S.ylo = S.yhi = 0;
     S.dirty = 1;
     S.over = 0;
     S.next = (u32)atomicAdd(&A.acc->br_queue, 1ull);
   }
-  u64 mins = 0, wins = 0, lo = 0, hi = 0;
+  Terms acc;
+  auto take = [&](u32 key, u32 a, u32 c) {
+    acc.add(a, c, S.tlo, S.thi);
+    if (pat) atomicAdd(&pat[key & hmask], a + c);
+  };
+  // a range of whole segments of at most SORT_CAP records: counted here, or
+  // listed for the hash-table kernel when its keys exceed 31 bits
+  auto count_range = [&](u64 ra, u64 rb) {
+    const u32 s0 = sorted[ra] >> 1, sl = sorted[rb - 1] >> 1;
+    const u32 sbits = (sl == s0) ? 0u : 32u - (u32)__builtin_clz(sl - s0);
+    if (sbits + m + 1 > 31) {
+      if (tid == 0) list_range(A, ra, rb);
+      return;
+    }
+    if (tid == 0) S.n = 0;
+    __syncthreads();
+    const WordRange R{sorted, ra, rb, s0, m, hmask, zero};
+    if (sbits + m <= DENSE_BITS) dense_count(S, R, sbits + m, tid, wave, lane, below, take);
+    else sort_count(S, R, sbits + m + 1, tid, wave, lane, below, take);
+    __syncthreads();
+  };
   // the next work block, fetched at a block's start and published at its
   // end (the queue's latency hides behind the block's work)
   u32 pending = 0;
@@ -612,342 +974,111 @@ __global__ void __launch_bounds__(WIN_BLOCK) k_br_windows_sort(TraceArgs A0, con
     const u64 b = S.next;
     if (b >= A.br_blocks) break;
     __syncthreads();
-    if (tid == 0) { pending = (u32)atomicAdd(&A.acc->br_queue, 1ull); S.n = 0; }
+    if (tid == 0) pending = (u32)atomicAdd(&A.acc->br_queue, 1ull);
     const u64 r0 = range_begin(A, sorted, b), r1 = range_begin(A, sorted, b + 1);
-    if (r1 <= r0) {
-      if (tid == 0) S.next = pending;
-      __syncthreads();
-      continue;
-    }
-    const u32 s0 = sorted[r0] >> 1, sl = sorted[r1 - 1] >> 1;
-    const u32 sbits = (sl == s0) ? 0u : 32u - (u32)__builtin_clz(sl - s0);
-    const u32 kbits = sbits + m + 1;
-    if (r1 - r0 > SORT_CAP || kbits > 31) {
-      if (tid == 0) {
-        A.br_cnt[atomicAdd(&A.acc->br_big_n, 1ull)] = (u32)b;
-        S.next = pending;
-      }
-      __syncthreads();
-      continue;
-    }
-    __syncthreads();
-    // 1. the block's windowed executions as words (~0 where the execution
-    //    forms no window), handed chunk by chunk to emit(t, word) with the
-    //    whole wavefront present.  Each wave takes a run of consecutive
-    //    64-record chunks, all of whose loads are in flight at once; the
-    //    chunk before its first supplies the carried ballots.  History: m
-    //    outcome bits cut from the ballots of two chunks (bit j = the
-    //    execution m - j back).  Records are sorted by site, so an execution
-    //    has m earlier ones of its site exactly when no site boundary lies
-    //    among the last m positions; the zero-history variant clears the
-    //    history bits before the latest boundary.
-    const u64 nch = (r1 - r0 + AIWC_WAVE - 1) / AIWC_WAVE;
-    const u64 cpw = (nch + SORT_WAVES - 1) / SORT_WAVES;     // <= 16
-    const u64 c0 = (u64)wave * cpw;
-    const u64 p0 = r0 + c0 * AIWC_WAVE;                      // first record of the wave
-    auto for_each_word = [&](auto &&emit) {
-      u32 pv[SORT_CH];
-#pragma unroll
-      for (u32 t = 0; t < SORT_CH; ++t) {
-        const u64 i = p0 + (u64)t * AIWC_WAVE + lane;
-        pv[t] = (t < cpw && i < r1) ? sorted[i] : 0u;
-      }
-      const bool have_prev = p0 >= AIWC_WAVE && c0 < nch;
-      const u32 vprev = have_prev ? sorted[p0 - AIWC_WAVE + lane] : 0u;
-      // carried state: outcome and site-boundary ballots of the previous
-      // chunk, and the site of its last record
-      u64 Bo = __ballot(have_prev && (vprev & 1u));
-      const u32 sp = (u32)__shfl((int)(vprev >> 1), (int)(lane == 0 ? 0 : lane - 1), AIWC_WAVE);
-      u64 Bs = have_prev ? __ballot((vprev >> 1) != sp) : ~0ull;
-      u32 last_site = (u32)__builtin_amdgcn_readlane((int)(vprev >> 1), 63);
-      if (!have_prev) last_site = 0xFFFFFFFFu;
-#pragma unroll
-      for (u32 t = 0; t < SORT_CH; ++t) {
-        if (t >= cpw || c0 + t >= nch) { emit(t, ~0u); continue; }
-        const u64 i = p0 + (u64)t * AIWC_WAVE + lane;
-        const bool valid = i < r1;
-        const u32 v = pv[t], st = v >> 1;
-        const u32 left = (u32)__shfl((int)st, (int)(lane == 0 ? 0 : lane - 1), AIWC_WAVE);
-        const u32 before = lane == 0 ? last_site : left;
-        const u64 B = __ballot(valid && (v & 1u));
-        const u64 Bb = __ballot(!valid || st != before);
-        // m outcome bits before the execution
-        const u32 sh = 64u + (u32)lane - m;                 // in [34, 126]
-        u64 E = (sh >= 64) ? (B >> (sh - 64)) : ((Bo >> sh) | (B << (64 - sh)));
-        E &= hmask;
-        // site boundaries at the last m positions, this one included
-        const u32 sb = sh + 1;
-        u64 F = (sb >= 64) ? (Bb >> (sb - 64)) : ((Bs >> sb) | (Bb << (64 - sb)));
-        F &= hmask;
-        bool windowed;
-        if (zero) {
-          // a boundary at window bit j starts the segment at history bit j:
-          // the bits below it precede the site's first execution
-          if (F) {
-            const u32 q = 63u - (u32)__builtin_clzll(F);
-            E &= ~((2ull << q) - 1ull);
-          }
-          windowed = valid;
-        } else {
-          windowed = valid && F == 0;
-        }
-        emit(t, windowed ? (u32)((((u64)(st - s0)) << (m + 1)) | (E << 1) | (v & 1u)) : ~0u);
-        Bo = B;
-        Bs = Bb;
-        last_site = (u32)__builtin_amdgcn_readlane((int)st, 63);
-      }
-    };
-    if (sbits + m <= DENSE_BITS) {
-      // 2'. few keys: count them in a direct LDS table, n0 in the low and
-      //     n1 in the high half of a key's word (a block holds < 2^16
-      //     executions), in passes of DENSE_WORDS keys; each word is read
-      //     and cleared once
-      u32 *T = S.keys;
-      if (S.dirty) {
-        for (u32 j = tid; j < DENSE_WORDS; j += WIN_BLOCK) T[j] = 0;
-        __syncthreads();
-      }
-      const u32 nkeys = 1u << (sbits + m);
-      const u32 pk = nkeys < DENSE_WORDS ? nkeys : DENSE_WORDS;
-      // each wave lists the keys it touched first (from the counters' old
-      // values); only listed words are read back, unless a list overflowed
-      uint16_t *const list = &S.off[wave][0];
-      for (u32 pass = 0; pass * pk < nkeys; ++pass) {
-        u32 nl = 0;   // wave-uniform list length
-        for_each_word([&](u32, u32 w) {
-          const bool mine = w != ~0u && (w >> 1) / pk == pass;
-          u32 old = 1;
-          if (mine) old = atomicAdd(&T[(w >> 1) % pk], (w & 1u) ? 0x10000u : 1u);
-          const u64 F = __ballot(mine && old == 0);
-          const u32 at = nl + (u32)__builtin_popcountll(F & below);
-          if (mine && old == 0 && at < NBIN) list[at] = (uint16_t)((w >> 1) % pk);
-          nl += (u32)__builtin_popcountll(F);
-        });
-        if (lane == 0 && nl > NBIN) S.over = 1;   // a list overflowed
-        __syncthreads();
-        const bool full = S.over != 0;
-        // one key's word: its counts, then cleared for the next pass
-        auto take = [&](u32 j) {
-          const u32 x = T[j];
-          if (!x) return;
-          T[j] = 0;
-          const u32 a = x & 0xFFFFu, c = x >> 16;
-          mins += a < c ? a : c;
-          wins += (u64)a + c;
-          u64 tl, th;
-          if (a < 16 && c < 16) { tl = S.tlo[a * 16 + c]; th = S.thi[a * 16 + c]; }
-          else yterm(a, c, tl, th);
-          u64 nl2 = lo + tl; hi += th + (nl2 < lo); lo = nl2;
-          if (pat) atomicAdd(&pat[(pass * pk + j) & hmask], a + c);
-        };
-        if (full) {
-          for (u32 j = tid; j < pk; j += WIN_BLOCK) take(j);
-        } else {
-          for (u32 q = (u32)lane; q < nl; q += AIWC_WAVE) take((u32)list[q]);
+    if (r1 > r0 && r1 - r0 <= SORT_CAP) {
+      count_range(r0, r1);
+    } else if (r1 > r0) {
+      // leading whole segments (within one WIN_T stride) and the last segment
+      const u64 ls = A.seg_start[sorted[r1 - 1] >> 1];
+      if (ls > r0) count_range(r0, ls);
+      if (r1 - ls <= SORT_CAP) {
+        count_range(ls, r1);
+      } else if (A.br_hot_cap && m <= 16) {
+        if (tid == 0) {
+          const u32 k = (u32)atomicAdd(&A.acc->br_hot_n, 1ull);
+          S.hidx = k;
+          if (k < A.br_hot_cap) { A.br_hot_list[2 * k] = (u32)ls; A.br_hot_list[2 * k + 1] = (u32)r1; }
+          else list_range(A, ls, r1);
         }
         __syncthreads();
-        if (tid == 0) S.over = 0;
-        __syncthreads();
+        const u32 k = S.hidx;
+        if (k < A.br_hot_cap)   // its table starts at zero
+          for (u32 j = tid; j < (1u << m); j += WIN_BLOCK) A.br_hot_tab[((u64)k << m) + j] = 0;
+      } else if (tid == 0) {
+        list_range(A, ls, r1);
       }
-      if (tid == 0) { S.dirty = 0; S.next = pending; }
-      __syncthreads();
-      continue;
-    }
-    // 2. more keys: the windowed words go to LDS (one counter update per
-    //    wave), then are sorted
-    {
-      u32 kw[SORT_CH];
-      for_each_word([&](u32 t, u32 w) { kw[t] = w; });
-      u32 cnt = 0;
-#pragma unroll
-      for (u32 t = 0; t < SORT_CH; ++t) cnt += (u32)__builtin_popcountll(__ballot(kw[t] != ~0u));
-      u32 base = 0;
-      if (lane == 0 && cnt) base = atomicAdd(&S.n, cnt);
-      base = (u32)__builtin_amdgcn_readfirstlane((int)base);
-#pragma unroll
-      for (u32 t = 0; t < SORT_CH; ++t) {
-        const u64 W = __ballot(kw[t] != ~0u);
-        if (kw[t] != ~0u) S.keys[base + (u32)__builtin_popcountll(W & below)] = kw[t];
-        base += (u32)__builtin_popcountll(W);
-      }
-    }
-    if (tid == 0) S.dirty = 1;
-    __syncthreads();
-    const u32 N = S.n;
-    // 2. LSD radix passes over bits [0, kbits)
-    u32 *src = S.keys, *dst = S.keys + SORT_CAP;
-    const u32 per = ((N + SORT_WAVES - 1) / SORT_WAVES + 63u) & ~63u;   // <= 1024
-    const u32 w0 = wave * per;
-    const u32 passes = (kbits + DIG_MAX - 1) / DIG_MAX;
-    u32 shift = 0;
-    for (u32 p = 0; p < passes; ++p) {
-      const u32 db = (kbits - shift + (passes - p) - 1) / (passes - p);
-      const u32 nbin = 1u << db, dmask = nbin - 1u;
-      for (u32 j = (u32)lane; j < nbin; j += AIWC_WAVE) S.off[wave][j] = 0;
-      // per element: the key, and its in-chunk rank | group leader << 6 |
-      // group size << 12 (the size on the leader only)
-      u32 key[SORT_CH], rk[SORT_CH];
-      // ranks inside each chunk from ballots (no memory traffic) ...
-#pragma unroll
-      for (u32 c = 0; c < SORT_CH; ++c) {
-        const u32 e = w0 + c * AIWC_WAVE + (u32)lane;
-        const bool ok = c * AIWC_WAVE < per && e < N;
-        const u32 kv = ok ? src[e] : 0u;
-        key[c] = kv;
-        rk[c] = (u32)lane << 6;
-        const u64 any = __ballot(ok);
-        if (any == 0) continue;
-        const u32 dg = (kv >> shift) & dmask;
-        u64 peers = any;
-        for (u32 bb = 0; bb < db; ++bb) {
-          const bool bit = (dg >> bb) & 1u;
-          const u64 bm = __ballot(bit);
-          peers &= bit ? bm : ~bm;
-        }
-        if (ok) {
-          const u32 ld = (u32)__builtin_ctzll(peers);
-          rk[c] = (u32)__builtin_popcountll(peers & below) | (ld << 6);
-          if ((u32)lane == ld) rk[c] |= (u32)__builtin_popcountll(peers) << 12;
-        }
-      }
-      // ... then every chunk's group counts added in chunk order (LDS atomics
-      // of one wave complete in issue order), two u16 counters per word ...
-      u32 pos[SORT_CH];
-#pragma unroll
-      for (u32 c = 0; c < SORT_CH; ++c) {
-        pos[c] = 0;
-        const u32 g = rk[c] >> 12;
-        if (g) {
-          const u32 dg = (key[c] >> shift) & dmask, hs = (dg & 1u) * 16u;
-          u32 *w = reinterpret_cast<u32 *>(&S.off[wave][dg & ~1u]);
-          pos[c] = (atomicAdd(w, g << hs) >> hs) & 0xFFFFu;
-        }
-      }
-      // ... and the groups' bases handed to their lanes: pos = rank in wave
-#pragma unroll
-      for (u32 c = 0; c < SORT_CH; ++c)
-        pos[c] = (u32)__shfl((int)pos[c], (int)((rk[c] >> 6) & 63u), AIWC_WAVE) + (rk[c] & 63u);
-      __syncthreads();
-      // offsets in (digit, wave) order
-      u32 excl = 0;
-      if ((u32)tid < nbin) {
-        u32 run = 0;
-#pragma unroll
-        for (u32 w = 0; w < SORT_WAVES; ++w) run += S.off[w][tid];
-        u32 x = run;
-        for (int o = 1; o < AIWC_WAVE; o <<= 1) {
-          const u32 y = (u32)__shfl_up((int)x, o, AIWC_WAVE);
-          if (lane >= o) x += y;
-        }
-        const u32 last = nbin < AIWC_WAVE ? nbin - 1u : (u32)AIWC_WAVE - 1u;
-        if ((u32)lane == last) S.wsum[wave] = x;
-        excl = x - run;
-      }
-      __syncthreads();
-      if ((u32)tid < nbin) {
-        u32 base = excl;
-        for (u32 w = 0; w < wave; ++w) base += S.wsum[w];
-#pragma unroll
-        for (u32 w = 0; w < SORT_WAVES; ++w) {
-          const u32 c = S.off[w][tid];
-          S.off[w][tid] = (uint16_t)base;
-          base += c;
-        }
-      }
-      __syncthreads();
-#pragma unroll
-      for (u32 c = 0; c < SORT_CH; ++c) {
-        const u32 e = w0 + c * AIWC_WAVE + (u32)lane;
-        if (c * AIWC_WAVE < per && e < N) {
-          const u32 dg = (key[c] >> shift) & dmask;
-          dst[S.off[wave][dg] + pos[c]] = key[c];
-        }
-      }
-      __syncthreads();
-      u32 *t = src; src = dst; dst = t;
-      shift += db;
-    }
-    // 3. boundaries of equal words as a bitmap (bit N: a sentinel), for the
-    //    runs that leave their chunk
-    u32 *bm = dst;
-    for (u32 cb = wave * AIWC_WAVE; cb < N; cb += WIN_BLOCK) {
-      const u32 e = cb + (u32)lane;
-      const bool ok = e < N;
-      const u32 v = ok ? src[e] : 0u;
-      const u32 vq = (ok && e > 0) ? src[e - 1] : 0u;
-      const u64 Bd = __ballot(ok && (e == 0 || v != vq));
-      if (lane == 0) bm[cb >> 5] = (u32)Bd;
-      if (lane == 1) bm[(cb >> 5) + 1] = (u32)(Bd >> 32);
-    }
-    __syncthreads();
-    if (tid == 0) {
-      if ((N & 63) == 0) { bm[N >> 5] = 0; bm[(N >> 5) + 1] = 0; }
-      bm[N >> 5] |= 1u << (N & 31);
-    }
-    __syncthreads();
-    // 4. every key's (n0, n1) from its runs: a run's end is the next
-    //    boundary, found in the chunk's boundary ballot unless the run
-    //    leaves the chunk
-    for (u32 cb = wave * AIWC_WAVE; cb < N; cb += WIN_BLOCK) {
-      const u32 e = cb + (u32)lane;
-      const bool ok = e < N;
-      const u32 v = ok ? src[e] : 0u;
-      const u32 vq = (ok && e > 0) ? src[e - 1] : 0u;
-      u64 Bd = __ballot(ok && (e == 0 || v != vq));
-      if (N - cb < 64) Bd |= 1ull << (N - cb);            // the sentinel
-      const bool head = ok && ((Bd >> lane) & 1ull);
-      const u64 above = (lane == 63) ? 0ull : (Bd & ~((2ull << lane) - 1ull));
-      const u32 e1 = above ? cb + (u32)__builtin_ctzll(above) : 0u;
-      const u32 j1 = above ? (u32)__builtin_ctzll(above) : 0u;
-      const u32 v1s = (u32)__shfl((int)v, (int)(j1 & 63u), AIWC_WAVE);
-      if (!head) continue;
-      if ((v & 1u) && e > 0 && (vq >> 1) == (v >> 1)) continue;   // its key's second run
-      const u32 end1 = above ? e1 : next_set(bm, cb + AIWC_WAVE);
-      u32 a, c;
-      if (v & 1u) { a = 0; c = end1 - e; }
-      else {
-        a = end1 - e;
-        c = 0;
-        if (end1 < N) {
-          const bool inside = end1 < cb + AIWC_WAVE;
-          const u32 v1 = inside ? v1s : src[end1];
-          if (v1 == (v | 1u)) {
-            u64 above2 = 0;
-            if (inside) {
-              const u32 j = end1 - cb;
-              above2 = (j == 63) ? 0ull : (Bd & ~((2ull << j) - 1ull));
-            }
-            const u32 end2 = above2 ? cb + (u32)__builtin_ctzll(above2)
-                                    : next_set(bm, inside ? cb + AIWC_WAVE : end1 + 1);
-            c = end2 - end1;
-          }
-        }
-      }
-      mins += a < c ? a : c;
-      wins += (u64)a + c;
-      u64 tl, th;
-      if (a < 16 && c < 16) { tl = S.tlo[a * 16 + c]; th = S.thi[a * 16 + c]; }
-      else yterm(a, c, tl, th);
-      u64 nl = lo + tl; hi += th + (nl < lo); lo = nl;
-      if (pat) atomicAdd(&pat[(v >> 1) & hmask], a + c);
     }
     if (tid == 0) S.next = pending;
     __syncthreads();
   }
-  mins = wave_sum_u64(mins);
-  wins = wave_sum_u64(wins);
-  wave_sum_u128(lo, hi);
-  if (lane == 0) {
-    if (mins) atomicAdd(&S.minsum, mins);
-    if (wins) atomicAdd(&S.windows, wins);
-    atomic_add_u128(&S.ylo, &S.yhi, lo, hi);
-  }
-  __syncthreads();
+  acc.flush(A, &S.minsum);
+}
+
+// Pieces of SORT_CAP records of the hot segments, counted in LDS and added
+// to their segment's table with 64-bit atomics.
+template <bool BATCH>
+__global__ void __launch_bounds__(WIN_BLOCK) k_br_windows_hot(TraceArgs A0, const TraceArgs *batch) {
+  __shared__ SortShared S;
+  const TraceArgs A = trace_args<BATCH>(A0, batch);
+  if (A.n_branch == 0 || global_history(A) || A.br_hot_cap == 0) return;
+  const u32 nh = (u32)(A.acc->br_hot_n < A.br_hot_cap ? A.acc->br_hot_n : A.br_hot_cap);
+  if (nh == 0) return;
+  const u32 *sorted = A.br_sorted;
+  const int tid = threadIdx.x, lane = lane_id();
+  const u32 wave = (u32)__builtin_amdgcn_readfirstlane(tid / AIWC_WAVE);
+  const u32 m = A.m;
+  const u64 hmask = (1ull << m) - 1ull;
+  const u64 below = (1ull << lane) - 1ull;
+  const bool zero = (A.br_flags & AIWC_BRANCH_ZERO_HISTORY) != 0;
   if (tid == 0) {
-    if (S.minsum) atomicAdd(&A.acc->br_minsum, S.minsum);
-    if (S.windows) atomicAdd(&A.acc->br_windows, S.windows);
-    atomic_add_u128(&A.acc->yok_lo, &A.acc->yok_hi, S.ylo, S.yhi);
+    u32 total = 0;
+    for (u32 e = 0; e < nh; ++e)
+      total += (A.br_hot_list[2 * e + 1] - A.br_hot_list[2 * e] + SORT_CAP - 1) / SORT_CAP;
+    S.total = total;
+    S.dirty = 1;
+    S.over = 0;
+    S.next = (u32)atomicAdd(&A.acc->br_piece_q, 1ull);
   }
+  u32 pending = 0;
+  __syncthreads();
+  while (true) {
+    u32 p = S.next;
+    if (p >= S.total) break;
+    __syncthreads();
+    if (tid == 0) pending = (u32)atomicAdd(&A.acc->br_piece_q, 1ull);
+    u32 e = 0, st = 0, en = 0;
+    for (; e < nh; ++e) {
+      st = A.br_hot_list[2 * e];
+      en = A.br_hot_list[2 * e + 1];
+      const u32 np = (en - st + SORT_CAP - 1) / SORT_CAP;
+      if (p < np) break;
+      p -= np;
+    }
+    const u64 x0 = (u64)st + (u64)p * SORT_CAP;
+    const u64 x1 = (u64)en < x0 + SORT_CAP ? (u64)en : x0 + SORT_CAP;
+    const WordRange R{sorted, x0, x1, sorted[st] >> 1, m, hmask, zero};
+    unsigned long long *tab = A.br_hot_tab + ((u64)e << m);
+    dense_count(S, R, m, tid, wave, lane, below, [&](u32 key, u32 a, u32 c) {
+      atomicAdd(&tab[key], (unsigned long long)a | ((unsigned long long)c << 32));
+    });
+    if (tid == 0) S.next = pending;
+    __syncthreads();
+  }
+}
+
+// The hot segments' tables: every history's (n0, n1) to the window sums.
+template <bool BATCH>
+__global__ void __launch_bounds__(256) k_br_hot_terms(TraceArgs A0, const TraceArgs *batch) {
+  __shared__ u64 tlo[256], thi[256], sm[4];
+  const TraceArgs A = trace_args<BATCH>(A0, batch);
+  if (A.n_branch == 0 || global_history(A) || A.br_hot_cap == 0) return;
+  const u64 nh = A.acc->br_hot_n < A.br_hot_cap ? A.acc->br_hot_n : A.br_hot_cap;
+  if (nh == 0) return;
+  yterm(threadIdx.x >> 4, threadIdx.x & 15, tlo[threadIdx.x], thi[threadIdx.x]);
+  __syncthreads();
+  const u32 m = A.m;
+  const u64 hmask = (1ull << m) - 1ull;
+  Terms acc;
+  const u64 n = nh << m;
+  for (u64 i = (u64)blockIdx.x * 256 + threadIdx.x; i < n; i += (u64)gridDim.x * 256) {
+    const unsigned long long x = A.br_hot_tab[i];
+    if (!x) continue;
+    const u32 a = (u32)x, c = (u32)(x >> 32);
+    acc.add(a, c, tlo, thi);
+    if (A.pat_hist) atomicAdd(&A.pat_hist[i & hmask], a + c);
+  }
+  acc.flush(A, sm);
 }
 
 // Pattern entropy: sum over the 2^m history patterns of c log2(N_w / c),
@@ -1015,6 +1146,10 @@ static void branch_launches(const TraceArgs &a, const BatchDims &d, hipStream_t 
   const dim3 gw((unsigned)nb, d.n);
   if (d.any_local) {
     hipLaunchKernelGGL((k_br_windows_sort<B>), gw, dim3(WIN_BLOCK), 0, s, a, b);
+    if (d.any_hot) {
+      hipLaunchKernelGGL((k_br_windows_hot<B>), dim3(256, d.n), dim3(WIN_BLOCK), 0, s, a, b);
+      hipLaunchKernelGGL((k_br_hot_terms<B>), dim3(256, d.n), dim3(256), 0, s, a, b);
+    }
     hipLaunchKernelGGL((k_br_windows<B, false, true>), gw, dim3(WIN_BLOCK), 0, s, a, b);
   }
   if (d.any_global)
