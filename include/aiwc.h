@@ -295,12 +295,15 @@ aiwc_status aiwc_characterize(aiwc_ctx *ctx, const aiwc_trace *trace,
  * process) race and must be serialized by the caller (same stream, or
  * events).  The array keeps the last call's contents; each call clears what
  * it needs zeroed with a kernel.  Limit: traces whose plan needs more than
- * AIWC_STATIC_SCRATCH_BYTES of scratch (8 B per memory event for its
- * partition record, per-block partition histograms, 8 B per branch event
- * for the radix buffers, ~1.2 MiB of fixed tables: about 2.5 MiB for a trace
- * of 5e5 events, 41 MiB for 1.3e7 events with 4e6 memory events; up to
- * about 5.6e6 memory events at the 30% memory / 5% branch mix) return
- * UNSUPPORTED before anything is enqueued; use aiwc_characterize for those.
+ * AIWC_STATIC_SCRATCH_BYTES of scratch return UNSUPPORTED before anything
+ * is enqueued; use aiwc_characterize for those.  The plan takes 12 B per
+ * memory event (partition record and page tag; 20 B from 2^12 partitions
+ * on, where the scatter runs in two passes), per-block partition
+ * histograms, 8.25 B per branch event (radix buffers and digit counts),
+ * 512 KiB per 65536 branch events for hot-site tables (history 16) and
+ * ~1.2 MiB of fixed tables: at the 30% memory / 5% branch mix about 5 MiB
+ * for 1e6 events, 30 MiB for 6.7e6 events, 62 MiB for 9e6 events (2.7e6
+ * memory events), the largest that fit.
  * Errors: INVALID_ARG (null, foreign trace, result_bytes too small),
  * UNSUPPORTED (over the limit), HIP (launch failure, or the array's address
  * could not be found at context creation).                                  */

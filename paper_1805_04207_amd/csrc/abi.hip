@@ -120,11 +120,12 @@ void plan_trace(const aiwc_trace *t, u32 pbits, TracePlan &p, const Tune *tune, 
   p.o_br_b = take(rec * std::max<u64>(1, d.n_branch));
   p.o_br_cnt = take(4ull * 256 * std::max<u64>(1, p.br_tiles));
   p.o_scan_tmp = take(4ull * aiwc_kernels::scan_tmp_elems(256 * std::max<u64>(1, p.br_tiles)));
-  // hot site segments (longer than a windows work block, per-site
-  // histories of m <= 16): a table of 2^m 64-bit counters each, for up to 64
+  // hot site segments (at least AIWC_HOT_MIN records, per-site histories of
+  // m <= 16): a table of 2^m 64-bit counters each, for up to 64 of them
+  // (at most 8 B per branch event)
   p.br_hot_cap = 0;
-  if (!(d.flags & AIWC_BRANCH_GLOBAL_HISTORY) && d.history_len <= 16 && d.n_branch > AIWC_SORT_CAP)
-    p.br_hot_cap = (u32)std::min<u64>(64, d.n_branch / AIWC_SORT_CAP);
+  if (!(d.flags & AIWC_BRANCH_GLOBAL_HISTORY) && d.history_len <= 16 && d.n_branch >= AIWC_HOT_MIN)
+    p.br_hot_cap = (u32)std::min<u64>(64, d.n_branch / AIWC_HOT_MIN);
   p.o_br_hot_list = take(8ull * std::max<u32>(1, p.br_hot_cap));
   p.o_br_hot_tab = take(p.br_hot_cap ? (8ull << d.history_len) * p.br_hot_cap : 8);
   p.scratch_bytes = o;

@@ -20,6 +20,7 @@ typedef unsigned int u32;
 #define VAL_DENSE 65536      // ITB / IPT value histograms are dense below this
 #define TWO_LEVEL_PBITS 12   // partitions from 2^12 on are scattered in two passes
 #define AIWC_SORT_CAP 16384  // branch records one windows work block counts on chip
+#define AIWC_HOT_MIN 65536   // site segments counted in parallel pieces from this length on
 struct DevAccum {
   u64 itb_min_inv, itb_max, itb_cnt, itb_sum;   // min stored as max of ~v
   u64 ipt_min_inv, ipt_max, ipt_cnt, ipt_sum;

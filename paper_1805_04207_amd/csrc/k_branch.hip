@@ -561,10 +561,10 @@ __global__ void __launch_bounds__(WIN_BLOCK) k_br_windows(TraceArgs A0, const Tr
 //    boundaries of equal words, a key's run with outcome 0 is n0 and the
 //    run with outcome 1 is n1.
 // A block larger than a sort block is its leading whole segments (fewer
-// than WIN_T records) and its last segment; a last segment longer than a
-// sort block with m <= 16 is a hot segment: it gets a table of 2^m 64-bit
-// counters (n0 | n1 << 32) in scratch, k_br_windows_hot counts its pieces
-// in parallel into that table and k_br_hot_terms reads it.  Ranges that fit
+// than WIN_T records) and its last segment; a last segment of at least
+// AIWC_HOT_MIN records with m <= 16 is a hot segment: it gets a table of 2^m
+// 64-bit counters (n0 | n1 << 32) in scratch, k_br_windows_hot counts its
+// pieces in parallel into that table and k_br_hot_terms reads it.  Ranges that fit
 // none of these are listed (br_cnt, br_big_n) for the hash-table kernel,
 // which runs last on the same stream.
 constexpr u32 SORT_CAP = AIWC_SORT_CAP;
@@ -984,7 +984,7 @@ __global__ void __launch_bounds__(WIN_BLOCK) k_br_windows_sort(TraceArgs A0, con
       if (ls > r0) count_range(r0, ls);
       if (r1 - ls <= SORT_CAP) {
         count_range(ls, r1);
-      } else if (A.br_hot_cap && m <= 16) {
+      } else if (A.br_hot_cap && m <= 16 && r1 - ls >= AIWC_HOT_MIN) {
         if (tid == 0) {
           const u32 k = (u32)atomicAdd(&A.acc->br_hot_n, 1ull);
           S.hidx = k;

@@ -1,7 +1,8 @@
 """Branch streams dominated by a few hot sites (run with -m gpu): segments
-far longer than a windows work block are counted in pieces that add into a
-per-site table; more hot segments than tables, and histories too long for a
-table, take the hash-table kernel.  Every case against the oracle."""
+of 65536 executions and more are counted in pieces that add into a per-site
+table; shorter long segments, more hot segments than tables, and histories
+too long for a table, take the hash-table kernel.  Every case against the
+oracle."""
 import numpy as np
 import pytest
 
@@ -55,17 +56,17 @@ def test_hot_sites_beside_small_ones():
     # hot segments after runs of small ones: a work block's leading segments
     # are counted apart from its last, hot, segment
     rng = np.random.default_rng(77)
-    n = 400000
+    n = 800000
     s = np.where(rng.random(n) < 0.5, rng.integers(0, 4000, size=n), 4000 + rng.integers(0, 4, size=n))
     s = s.astype(np.uint32)
     check(branch_trace(s, outcomes(rng, s, 4004), 4004, 16))
 
 
 def test_more_hot_segments_than_tables():
-    # 80 sites of 20000 executions each: 64 get tables, the rest go to the
+    # 80 sites of 70000 executions each: 64 get tables, the rest go to the
     # hash-table kernel
     rng = np.random.default_rng(78)
-    s = np.repeat(np.arange(80, dtype=np.uint32), 20000)
+    s = np.repeat(np.arange(80, dtype=np.uint32), 70000)
     rng.shuffle(s)
     check(branch_trace(s, outcomes(rng, s, 80), 80, 16))
 
