@@ -112,6 +112,12 @@ void plan_trace(const aiwc_trace *t, u32 pbits, TracePlan &p, const Tune *tune, 
   // the two-level scatter: coarse-bucket records and the cursors
   p.o_part_tmp = (d.n_mem && p.pbits >= TWO_LEVEL_PBITS) ? take(8ull * nrec) : 0;
   p.o_part_cur = take(4ull * (P + 512));
+  // hot pages: the state and tables, and a buffer for the compacted rest
+  // (the coarse-bucket records' buffer when there is one: free by then)
+  if (d.n_mem >= AIWC_HOT_PART) {
+    p.o_mem_hot = take(4ull * AIWC_HOT_WORDS);
+    p.o_part_cmp = p.o_part_tmp ? p.o_part_tmp : take(8ull * nrec);
+  }
   p.o_ops_wlo = take(8ull * (p.ops_tasks + 1));
   // radix records: site << 1 | outcome (u32), or with the global history
   // site << 33 | history << 1 | outcome (u64)
@@ -196,6 +202,8 @@ void fill_args(const aiwc_trace *t, const TracePlan &p, char *scratch, char *res
   a.br_a = (u32 *)(scratch + p.o_br_a);
   a.br_b = (u32 *)(scratch + p.o_br_b);
   a.br_cnt = (u32 *)(scratch + p.o_br_cnt);
+  a.mem_hot = p.o_mem_hot ? (u32 *)(scratch + p.o_mem_hot) : nullptr;
+  a.part_cmp = p.o_mem_hot ? (u64 *)(scratch + p.o_part_cmp) : nullptr;
   a.br_hot_list = (u32 *)(scratch + p.o_br_hot_list);
   a.br_hot_tab = (unsigned long long *)(scratch + p.o_br_hot_tab);
   a.br_hot_cap = p.br_hot_cap;
@@ -225,6 +233,7 @@ void add_dims(const aiwc_trace *t, const TracePlan &p, const TraceArgs &a, Batch
     d.max_hist_blocks = std::max<u64>(d.max_hist_blocks, p.n_hist_blocks);
     d.max_parts = std::max<u64>(d.max_parts, 1ull << p.pbits);
     if (a.part_tmp) d.any_two_level = true; else d.any_one_level = true;
+    if (a.mem_hot) d.any_hot_mem = true;
     if ((uintptr_t)a.addr % 16 || (uintptr_t)a.mem_kind % 8) d.vec = false;
   }
   if (D.n_branch) {

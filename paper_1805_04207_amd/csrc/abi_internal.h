@@ -32,7 +32,7 @@ struct TracePlan {
   u64 o_itb_large = 0, o_ipt_large = 0, o_part_hist = 0, o_part_off = 0, o_part_rec = 0;
   u64 o_part_order = 0, o_part_tag = 0, o_ops_wlo = 0, o_part_tmp = 0, o_part_cur = 0;
   u64 o_br_a = 0, o_br_b = 0, o_br_cnt = 0, o_scan_tmp = 0, o_pat_hist = 0;
-  u64 o_br_hot_list = 0, o_br_hot_tab = 0;
+  u64 o_br_hot_list = 0, o_br_hot_tab = 0, o_mem_hot = 0, o_part_cmp = 0;
   u32 br_hot_cap = 0;
   u64 scratch_bytes = 0;
   // result buffer offsets (bytes)

@@ -21,6 +21,10 @@ typedef unsigned int u32;
 #define TWO_LEVEL_PBITS 12   // partitions from 2^12 on are scattered in two passes
 #define AIWC_SORT_CAP 16384  // branch records one windows work block counts on chip
 #define AIWC_HOT_MIN 65536   // site segments counted in parallel pieces from this length on
+#define AIWC_HOT_PART (1u << 18)  // partitions split into hot-page tables + the rest from this size
+#define AIWC_HOT_PMAX 64          // hot partitions per trace
+#define AIWC_HOT_CAND 8           // candidate pages per hot partition
+#define AIWC_HOT_WORDS (2048 + AIWC_HOT_PMAX * AIWC_HOT_CAND * (1024 + 64))  // u32 words of the state
 struct DevAccum {
   u64 itb_min_inv, itb_max, itb_cnt, itb_sum;   // min stored as max of ~v
   u64 ipt_min_inv, ipt_max, ipt_cnt, ipt_sum;
@@ -85,6 +89,9 @@ struct TraceArgs {
   u64 *part_tmp;             // [n_mem] coarse-bucket records of the two-level scatter (or null)
   u32 *part_cur;             // [P + 512] fine cursors, coarse cursors, coarse tile starts
   u32 *part_tag;             // [n_mem] page slot and position of each record (bucket kernel)
+  u64 *part_cmp;             // [n_mem] hot partitions' records off their candidate pages
+  u32 *mem_hot;              // [AIWC_HOT_WORDS] hot partitions, candidate pages, their tables
+                             // (null: no hot-page path)
   u32 *br_a, *br_b;          // [n_branch] radix ping-pong
   u32 *br_cnt;               // [256 * br_tiles]; after the sort: (start, end) ranges
                              // left to the hash-table windows kernel
@@ -225,6 +232,7 @@ struct BatchDims {
   bool any_local = false, any_global = false;   // branch history variants present
   bool any_pattern = false;                     // some trace wants the pattern entropy
   bool any_hot = false;                         // some trace has hot-segment tables
+  bool any_hot_mem = false;                     // some trace has the hot-page path
   u32 max_pattern_bins = 0;
   bool vec = true;                    // every address / kind array 16 / 4 B aligned
   bool ops_vec = true;                // every opcode array 16 B aligned

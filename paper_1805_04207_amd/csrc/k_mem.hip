@@ -109,6 +109,38 @@ __global__ void __launch_bounds__(MEM_BLOCK) k_mem_hist(TraceArgs A0, const Trac
   }
 }
 
+// ------------------------------------------------------------- hot pages
+// A partition of AIWC_HOT_PART records or more usually holds pages that take
+// most of them (a work-group's local tile, a histogram's bins), and one
+// bucket block would stream it alone.  Such a partition (up to
+// AIWC_HOT_PMAX of them) gets up to AIWC_HOT_CAND candidate pages: the pages
+// with HOT_CAND_MIN or more of its first HOT_SAMPLE records.  Every record
+// of a candidate page is counted, by many blocks in parallel, into the
+// page's table (1024 byte-offset counters, then 32 read- and 32
+// write-bitmap words); the partition's other records are compacted into
+// part_cmp and reduced by k_mem_bucket as usual, which then evaluates each
+// candidate from its table exactly as a heavy page.  Which pages are
+// candidates only decides how the work is split: every page takes one path
+// whole.
+//   state (u32 words): [0] hot partitions, [1] pieces, [2] piece queue,
+//   then HotPart[AIWC_HOT_PMAX], the candidates' page keys (u64), and from
+//   word 2048 the tables.
+constexpr u32 HOT_SAMPLE = 16384, HOT_CAND_MIN = 1024, HOT_PIECE = 65536;
+constexpr u32 HOT_TAB = 1024 + 64;
+constexpr u32 HOT_SLOTS = 4096;                   // page table of the sample
+struct HotPart { u32 p, first_piece, kept, ncand, pad[4]; };
+static_assert(4 + 8 * AIWC_HOT_PMAX + 2 * AIWC_HOT_PMAX * AIWC_HOT_CAND <= 2048,
+              "hot-partition headers fit below the tables");
+static_assert(AIWC_HOT_PMAX <= AIWC_WAVE, "a wavefront looks up the hot partitions, one per lane");
+__device__ __forceinline__ HotPart *hot_parts(u32 *h) { return reinterpret_cast<HotPart *>(h + 4); }
+__device__ __forceinline__ u64 *hot_keys(u32 *h) {
+  return reinterpret_cast<u64 *>(h + 4 + 8 * AIWC_HOT_PMAX);
+}
+__device__ __forceinline__ u32 *hot_tab(u32 *h, u32 hp, u32 c) {
+  return h + 2048 + (hp * AIWC_HOT_CAND + c) * HOT_TAB;
+}
+__device__ __forceinline__ u32 hot_pieces(u32 n) { return (n + HOT_PIECE - 1) / HOT_PIECE; }
+
 // Per partition: exclusive prefix over the histogram blocks (in place);
 // the partition total goes to part_off[b].
 template <bool BATCH>
@@ -161,12 +193,36 @@ __global__ void __launch_bounds__(1024) k_mem_binscan(TraceArgs A0, const TraceA
   // (several rounds, or heavy pages whose records are read once per page)
   // first, so that the longest ones do not start last; the order of the
   // rest is free (results do not depend on it)
-  __shared__ u32 nbig, nsmall;
-  if (threadIdx.x == 0) { nbig = 0; nsmall = 0; }
+  // The hot partitions (AIWC_HOT_PART records or more, the first
+  // AIWC_HOT_PMAX found) and where their pieces start in the piece queue.
+  __shared__ u32 nbig, nsmall, nhot, hot[AIWC_HOT_PMAX];
+  if (threadIdx.x == 0) { nbig = 0; nsmall = 0; nhot = 0; }
   __syncthreads();
-  for (u32 i = threadIdx.x; i < P; i += 1024)
-    if (A.part_off[i + 1] - A.part_off[i] > AIWC_STAGE_CAP) A.part_order[atomicAdd(&nbig, 1u)] = i;
+  for (u32 i = threadIdx.x; i < P; i += 1024) {
+    const u32 sz = A.part_off[i + 1] - A.part_off[i];
+    if (sz > AIWC_STAGE_CAP) A.part_order[atomicAdd(&nbig, 1u)] = i;
+    if (A.mem_hot && sz >= AIWC_HOT_PART) {
+      const u32 k = atomicAdd(&nhot, 1u);
+      if (k < AIWC_HOT_PMAX) hot[k] = i;
+    }
+  }
   __syncthreads();
+  if (A.mem_hot && threadIdx.x == 0) {
+    u32 *H = A.mem_hot;
+    const u32 nh = nhot < AIWC_HOT_PMAX ? nhot : AIWC_HOT_PMAX;
+    u32 pieces = 0;
+    for (u32 h = 0; h < nh; ++h) {
+      HotPart &hp = hot_parts(H)[h];
+      hp.p = hot[h];
+      hp.first_piece = pieces;
+      hp.kept = 0;
+      hp.ncand = 0;
+      pieces += hot_pieces(A.part_off[hot[h] + 1] - A.part_off[hot[h]]);
+    }
+    H[0] = nh;
+    H[1] = pieces;
+    H[2] = 0;
+  }
   const u32 nb = nbig;
   for (u32 i = threadIdx.x; i < P; i += 1024)
     if (A.part_off[i + 1] - A.part_off[i] <= AIWC_STAGE_CAP)
@@ -463,6 +519,180 @@ __global__ void __launch_bounds__(GRP_BLOCK) k_mem_scatter_range(TraceArgs A, u3
   }
 }
 
+// Candidate pages of one hot partition (one block each) from the pages of
+// its first HOT_SAMPLE records; their tables start at zero.
+template <bool BATCH>
+__global__ void __launch_bounds__(1024) k_mem_hot_pick(TraceArgs A0, const TraceArgs *batch) {
+  __shared__ u64 key[HOT_SLOTS];
+  __shared__ u32 cnt[HOT_SLOTS];
+  __shared__ u32 nc;
+  const TraceArgs A = trace_args<BATCH>(A0, batch);
+  if (!A.mem_hot || A.n_mem == 0) return;
+  u32 *H = A.mem_hot;
+  const u32 h = blockIdx.x;
+  if (h >= H[0]) return;
+  HotPart &hp = hot_parts(H)[h];
+  const u64 base = A.part_off[hp.p];
+  const u32 size = A.part_off[hp.p + 1] - (u32)base;
+  for (u32 i = threadIdx.x; i < HOT_SLOTS; i += 1024) { key[i] = EMPTY; cnt[i] = 0; }
+  if (threadIdx.x == 0) nc = 0;
+  __syncthreads();
+  const u32 ns = size < HOT_SAMPLE ? size : HOT_SAMPLE;
+  const int lane = lane_id();
+  for (u32 i0 = threadIdx.x - lane; i0 < ns; i0 += 1024) {
+    const u32 i = i0 + (u32)lane;
+    const bool valid = i < ns;
+    const u64 pk = valid ? A.part_rec[base + i] >> 11 : EMPTY;
+    // the lanes on lane 0's page add once (a hot page takes most lanes)
+    const u64 pk0 = ((u64)__builtin_amdgcn_readfirstlane((int)(u32)(pk >> 32)) << 32) |
+                    (u32)__builtin_amdgcn_readfirstlane((int)(u32)pk);
+    const u64 B = __ballot(valid && pk == pk0);
+    u32 add = 0;
+    if (valid && pk == pk0) add = lane == 0 ? (u32)__builtin_popcountll(B) : 0u;
+    else if (valid) add = 1;
+    if (add) {
+      u32 slot = hash_slot(pk, HOT_SLOTS);
+      for (u32 probe = 0; probe < HOT_SLOTS; ++probe) {   // a full table: the page is skipped
+        u64 w = key[slot];
+        if (w == EMPTY) {
+          const u64 old = atomicCAS(&key[slot], EMPTY, pk);
+          w = old == EMPTY ? pk : old;
+        }
+        if (w == pk) { atomicAdd(&cnt[slot], add); break; }
+        slot = slot + 1 == HOT_SLOTS ? 0 : slot + 1;
+      }
+    }
+  }
+  __syncthreads();
+  u64 *keys = hot_keys(H) + (u64)h * AIWC_HOT_CAND;
+  for (u32 i = threadIdx.x; i < HOT_SLOTS; i += 1024) {
+    if (cnt[i] >= HOT_CAND_MIN) {
+      const u32 k = atomicAdd(&nc, 1u);
+      if (k < AIWC_HOT_CAND) keys[k] = key[i];
+    }
+  }
+  __syncthreads();
+  const u32 ncand = nc < AIWC_HOT_CAND ? nc : AIWC_HOT_CAND;
+  if (threadIdx.x == 0) hp.ncand = ncand;
+  for (u32 c = 0; c < ncand; ++c) {
+    u32 *t = hot_tab(H, h, c);
+    for (u32 j = threadIdx.x; j < HOT_TAB; j += 1024) t[j] = 0;
+  }
+}
+
+// Pieces of the hot partitions: candidate records into LDS tables (added to
+// the candidates' tables), the others compacted to part_cmp.  The others are
+// staged in LDS and written once per piece; a piece with more of them than
+// the staging array holds reads its records a second time to write them.
+// The counters sit at hot_slot(offset), which spreads 4-byte-aligned
+// offsets over all banks.
+constexpr u32 HOT_REST_CAP = 4096;
+__device__ __forceinline__ u32 hot_slot(u32 off) { return ((off & 3u) << 8) | (off >> 2); }
+template <bool BATCH>
+__global__ void __launch_bounds__(1024) k_mem_hot_count(TraceArgs A0, const TraceArgs *batch) {
+  __shared__ u32 tc[AIWC_HOT_CAND][1024];
+  __shared__ u32 tb[AIWC_HOT_CAND][64];
+  __shared__ u64 stage[HOT_REST_CAP];
+  __shared__ u32 piece, nstage, wrest[17];
+  const TraceArgs A = trace_args<BATCH>(A0, batch);
+  if (!A.mem_hot || A.n_mem == 0) return;
+  u32 *H = A.mem_hot;
+  const u32 nh = H[0], total = H[1];
+  if (nh == 0) return;
+  const int tid = threadIdx.x, lane = lane_id(), wave = tid / AIWC_WAVE;
+  const u64 below = (1ull << lane) - 1ull;
+  while (true) {
+    if (tid == 0) { piece = atomicAdd(&H[2], 1u); nstage = 0; }
+    __syncthreads();
+    const u32 pc = piece;
+    if (pc >= total) break;
+    u32 h = 0;
+    while (h + 1 < nh && pc >= hot_parts(H)[h + 1].first_piece) ++h;
+    HotPart &hp = hot_parts(H)[h];
+    const u64 base = A.part_off[hp.p];
+    const u32 size = A.part_off[hp.p + 1] - (u32)base;
+    const u32 r0 = (pc - hp.first_piece) * HOT_PIECE;
+    const u32 r1 = size - r0 < HOT_PIECE ? size : r0 + HOT_PIECE;
+    const u32 ncand = hp.ncand;
+    u64 ck[AIWC_HOT_CAND];
+#pragma unroll
+    for (u32 c = 0; c < AIWC_HOT_CAND; ++c) ck[c] = c < ncand ? hot_keys(H)[h * AIWC_HOT_CAND + c] : EMPTY;
+    for (u32 i = tid; i < AIWC_HOT_CAND * 1024; i += 1024) (&tc[0][0])[i] = 0;
+    for (u32 i = tid; i < AIWC_HOT_CAND * 64; i += 1024) (&tb[0][0])[i] = 0;
+    __syncthreads();
+    // a wave takes a contiguous run of the piece: candidates counted, the
+    // other records counted per wave and staged
+    const u32 per = ((r1 - r0 + 1023u) / 1024u) * AIWC_WAVE;
+    const u32 w0 = r0 + (u32)wave * per, w1 = w0 + per < r1 ? w0 + per : r1;
+    auto cand = [&](u64 rec) {
+      const u64 pk = rec >> 11;
+      u32 c = AIWC_HOT_CAND;
+#pragma unroll
+      for (u32 q = 0; q < AIWC_HOT_CAND; ++q)
+        if (pk == ck[q]) c = q;
+      return c;
+    };
+    u32 nrest = 0;
+    for (u32 i0 = w0; i0 < w1; i0 += AIWC_WAVE) {
+      const u32 i = i0 + (u32)lane;
+      const bool valid = i < w1;
+      const u64 rec = valid ? A.part_rec[base + i] : EMPTY;
+      const u32 c = valid ? cand(rec) : 0u;
+      if (valid && c < AIWC_HOT_CAND) {
+        const u32 off = (u32)(rec >> 1) & 1023u;
+        atomicAdd(&tc[c][hot_slot(off)], 1u);
+        u32 *w = &tb[c][((u32)rec & 1u) * 32u + (off >> 5)];
+        const u32 bit = 1u << (off & 31u);
+        if (!(*w & bit)) atomicOr(w, bit);   // a set bit stays set
+      }
+      const bool rest = valid && c == AIWC_HOT_CAND;
+      const u64 W = __ballot(rest);
+      if (W) {
+        const u32 k = (u32)__builtin_popcountll(W);
+        u32 at = 0;
+        if (lane == 0) at = atomicAdd(&nstage, k);
+        at = (u32)__shfl((int)at, 0, AIWC_WAVE) + (u32)__builtin_popcountll(W & below);
+        if (rest && at < HOT_REST_CAP) stage[at] = rec;
+        nrest += k;
+      }
+    }
+    if (lane == 0) wrest[wave] = nrest;
+    __syncthreads();
+    const u32 ns = nstage;
+    if (tid == 0) {
+      u32 run = 0;
+      for (int w = 0; w < 16; ++w) { const u32 x = wrest[w]; wrest[w] = run; run += x; }
+      wrest[16] = run ? atomicAdd(&hp.kept, run) : 0u;
+    }
+    __syncthreads();
+    if (ns <= HOT_REST_CAP) {
+      u64 *dst = A.part_cmp + base + wrest[16];
+      for (u32 j = tid; j < ns; j += 1024) dst[j] = stage[j];
+    } else {
+      // ... too many to stage: one more read, each wave writing its own
+      u32 at = wrest[16] + wrest[wave];
+      for (u32 i0 = w0; i0 < w1; i0 += AIWC_WAVE) {
+        const u32 i = i0 + (u32)lane;
+        const bool valid = i < w1;
+        const u64 rec = valid ? A.part_rec[base + i] : EMPTY;
+        const bool rest = valid && cand(rec) == AIWC_HOT_CAND;
+        const u64 W = __ballot(rest);
+        if (rest) A.part_cmp[base + at + (u32)__builtin_popcountll(W & below)] = rec;
+        at += (u32)__builtin_popcountll(W);
+      }
+    }
+    for (u32 c = 0; c < ncand; ++c) {
+      u32 *t = hot_tab(H, h, c);
+      for (u32 j = tid; j < 1024; j += 1024) {
+        const u32 v = tc[c][hot_slot(j)];
+        if (v) atomicAdd(&t[j], v);
+      }
+      if (tid < 64 && tb[c][tid]) atomicOr(&t[1024 + tid], tb[c][tid]);
+    }
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------------- bucket
 // One block per partition at a time (persistent, partitions from a queue).
 //  1. page pass   : an LDS table of the partition's pages (record >> 11, which
@@ -521,6 +751,7 @@ struct BucketShared {
   u32 pend[PT_CAP];                // staging cursor, then end, of compact index
   u32 dense[BK_WAVES][1024];       // per-wave byte-offset counters
   u32 rbits[32], wbits[32];        // read / write bitmaps of a heavy page
+  u32 hotp[AIWC_HOT_PMAX];         // the hot partitions' indices
   u64 term[2][256];                // c*log2(N_s/c) for c < 256, 2^-40 units
   u32 spec[2][SPEC_LDS];           // level-0 nodes of count c, 2 <= c < SPEC_LDS
   u64 spf[2][SPEC_SLOTS], spm[2][SPEC_SLOTS];
@@ -956,6 +1187,9 @@ __global__ void __launch_bounds__(BK_BLOCK) k_mem_bucket(TraceArgs A0, const Tra
   }
   if (tid < 2) { S.ur[tid] = 0; S.uw[tid] = 0; }
   if (tid == 0) { S.redos = 0; S.npages = 0; S.overflow = 0; S.nblist = 0; }
+  // the hot partitions (set before this kernel), read once
+  const u32 nhot = A.mem_hot ? A.mem_hot[0] : 0u;
+  if ((u32)tid < nhot) S.hotp[tid] = hot_parts(A.mem_hot)[tid].p;
   __syncthreads();
 
   const u32 Q = A.part_queue ? A.part_queue : P;   // entries of part_order to take
@@ -965,7 +1199,19 @@ __global__ void __launch_bounds__(BK_BLOCK) k_mem_bucket(TraceArgs A0, const Tra
     if (S.work >= Q) break;
     const u32 p = A.part_order[S.work];
     const u64 base = A.part_off[p];
-    const u32 n = A.part_off[p + 1] - (u32)base;
+    u32 n = A.part_off[p + 1] - (u32)base;
+    // a hot partition: its records off the candidate pages (compacted), the
+    // candidates afterwards from their tables
+    const u64 *prec = A.part_rec;
+    int hidx = -1;
+    if (nhot) {   // one entry per lane (nhot <= 64)
+      const u64 hb = __ballot((u32)lane < nhot && S.hotp[lane < (int)nhot ? lane : 0] == p);
+      if (hb) {
+        hidx = __builtin_ctzll(hb);
+        prec = A.part_cmp;
+        n = hot_parts(A.mem_hot)[hidx].kept;
+      }
+    }
     if (tid == 0) { S.sp_top = 1; S.stack_m[0] = 1; S.stack_c[0] = 0; }
     __syncthreads();
     while (S.sp_top > 0) {
@@ -984,7 +1230,7 @@ __global__ void __launch_bounds__(BK_BLOCK) k_mem_bucket(TraceArgs A0, const Tra
 #pragma unroll
       for (int u = 0; u < UNROLL; ++u) {
         const u32 i = (u32)tid + (u32)u * BK_BLOCK;
-        nx[u] = i < n ? A.part_rec[base + i] : EMPTY;
+        nx[u] = i < n ? prec[base + i] : EMPTY;
       }
       for (u32 w0 = (u32)(tid - lane); w0 < n; w0 += BK_BLOCK * UNROLL) {
         u64 rv[UNROLL];
@@ -992,7 +1238,7 @@ __global__ void __launch_bounds__(BK_BLOCK) k_mem_bucket(TraceArgs A0, const Tra
         for (int u = 0; u < UNROLL; ++u) {
           rv[u] = nx[u];
           const u32 i = w0 + (u32)(BK_BLOCK * UNROLL) + (u32)u * BK_BLOCK + (u32)lane;
-          nx[u] = i < n ? A.part_rec[base + i] : EMPTY;
+          nx[u] = i < n ? prec[base + i] : EMPTY;
         }
         // run heads and their first probe slots for all records at once
         u32 hs[UNROLL], run[UNROLL];
@@ -1178,7 +1424,7 @@ __global__ void __launch_bounds__(BK_BLOCK) k_mem_bucket(TraceArgs A0, const Tra
 #pragma unroll
       for (int u = 0; u < UNROLL; ++u) {
         const u32 i = (u32)tid + (u32)u * BK_BLOCK;
-        nr[u] = i < n ? A.part_rec[base + i] : EMPTY;
+        nr[u] = i < n ? prec[base + i] : EMPTY;
         nt[u] = i < n ? A.part_tag[base + i] : 0u;
       }
       for (u32 w0 = (u32)tid; w0 < n; w0 += BK_BLOCK * UNROLL) {
@@ -1189,7 +1435,7 @@ __global__ void __launch_bounds__(BK_BLOCK) k_mem_bucket(TraceArgs A0, const Tra
           rv[u] = nr[u];
           tg[u] = nt[u];
           const u32 i = w0 + (u32)(BK_BLOCK * UNROLL) + (u32)u * BK_BLOCK;
-          nr[u] = i < n ? A.part_rec[base + i] : EMPTY;
+          nr[u] = i < n ? prec[base + i] : EMPTY;
           nt[u] = i < n ? A.part_tag[base + i] : 0u;
         }
 #pragma unroll
@@ -1219,7 +1465,7 @@ __global__ void __launch_bounds__(BK_BLOCK) k_mem_bucket(TraceArgs A0, const Tra
 #pragma unroll
             for (int u = 0; u < UNROLL; ++u) {
               const u32 i = i0 + (u32)u * BK_BLOCK;
-              rv[u] = i < n ? A.part_rec[base + i] : EMPTY;
+              rv[u] = i < n ? prec[base + i] : EMPTY;
             }
 #pragma unroll
             for (int u = 0; u < UNROLL; ++u) {
@@ -1328,6 +1574,26 @@ __global__ void __launch_bounds__(BK_BLOCK) k_mem_bucket(TraceArgs A0, const Tra
       __syncthreads();
       if (tid == 0) S.npages = 0;
       __syncthreads();
+    }
+    // ---- a hot partition's candidate pages, each from its table (counts by
+    // byte offset, read and write bitmaps), evaluated as a heavy page
+    if (hidx >= 0) {
+      const u32 nc = hot_parts(A.mem_hot)[hidx].ncand;
+      for (u32 c = 0; c < nc; ++c) {
+        const u32 *t = hot_tab(A.mem_hot, (u32)hidx, c);
+        const u64 hk = hot_keys(A.mem_hot)[(u32)hidx * AIWC_HOT_CAND + c];
+        for (u32 i = tid; i < 1024; i += BK_BLOCK) S.dense[0][cslot(i)] = t[i];
+        if (tid < 32) { S.rbits[tid] = t[1024 + tid]; S.wbits[tid] = t[1056 + tid]; }
+        __syncthreads();
+        if (wave == 0) {
+          const int sp = (int)((hk >> sbit) & 1ull);
+          LaneAcc HL;
+          lacc_clear(HL, sp);
+          page_levels<false, false>(HL, S, G, S.dense[0], S.rbits, S.wbits, sp ? N1 : N0);
+          lacc_flush(HL, S);
+        }
+        __syncthreads();
+      }
     }
   }
   // ---- flush the block's accumulators
@@ -1459,6 +1725,16 @@ hipError_t launch_mem_partition(const TraceArgs &a, const BatchDims &d, hipStrea
       if (d.vec) hipLaunchKernelGGL((k_mem_scatter_a<true, false>), gt, dim3(SC_BLOCK), 0, s, a, b);
       else hipLaunchKernelGGL((k_mem_scatter_a<false, false>), gt, dim3(SC_BLOCK), 0, s, a, b);
       hipLaunchKernelGGL(k_mem_scatter_b<false>, gt, dim3(SC_BLOCK), 0, s, a, b);
+    }
+  }
+  if (d.any_hot_mem) {   // counted in the scatter's stage time
+    const dim3 gp(AIWC_HOT_PMAX, d.n), gc(512, d.n);
+    if (b) {
+      hipLaunchKernelGGL(k_mem_hot_pick<true>, gp, dim3(1024), 0, s, a, b);
+      hipLaunchKernelGGL(k_mem_hot_count<true>, gc, dim3(1024), 0, s, a, b);
+    } else {
+      hipLaunchKernelGGL(k_mem_hot_pick<false>, gp, dim3(1024), 0, s, a, b);
+      hipLaunchKernelGGL(k_mem_hot_count<false>, gc, dim3(1024), 0, s, a, b);
     }
   }
   AIWC_MARK(pm, "k_mem_scatter", s);

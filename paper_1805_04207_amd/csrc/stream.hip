@@ -340,6 +340,8 @@ static aiwc_status grouped_memory_stage(aiwc_stream *st, aiwc_trace &mt, u64 cap
   fill_args(&mt, p, ctx->arena, (char *)m->buf, a);
   a.addr = nullptr;        // the memory stream reaches the kernels by chunks only
   a.mem_kind = nullptr;
+  a.mem_hot = nullptr;     // groups are reduced without the hot-page path
+  a.part_cmp = nullptr;
   point_at_state(st, a);
   add_dims(&mt, p, a, dims);
   hipError_t e = aiwc_kernels::launch_zero(a, dims, s);
