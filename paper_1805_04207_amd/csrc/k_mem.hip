@@ -1047,9 +1047,15 @@ __device__ __forceinline__ void page_levels(LaneAcc &L, BucketShared &S, SpecRef
   const u32 sh = sw >> 2;                  // which 16-byte chunk
   const bool s0 = (sw & 1u) != 0, s1 = (sw & 2u) != 0;   // order inside it
   u32 c[16];
+  // the four loads are issued together (the scheduler would otherwise wait
+  // for each before the next)
+  uint4 xs[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) xs[q] = src[q ^ sh];
+  __builtin_amdgcn_sched_group_barrier(0x0100, 4, 0);
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    uint4 x = src[q ^ sh];
+    const uint4 x = xs[q];
     // element e of the chunk holds position e ^ (sw & 3)
     u32 a0 = s0 ? x.y : x.x, a1 = s0 ? x.x : x.y, a2 = s0 ? x.w : x.z, a3 = s0 ? x.z : x.w;
     c[4 * q] = s1 ? a2 : a0; c[4 * q + 1] = s1 ? a3 : a1;
@@ -1535,15 +1541,18 @@ __global__ void __launch_bounds__(BK_BLOCK) k_mem_bucket(TraceArgs A0, const Tra
           for (int q = 0; q < 4; ++q) z[q] = make_uint4(0, 0, 0, 0);
           __builtin_amdgcn_wave_barrier();
           for (u32 i0 = o0 + lane; i0 < o1; i0 += AIWC_WAVE * 4) {
+            // four loads in flight together (an index past the page reads
+            // the page's first record, which is then not counted)
             u32 vv[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
               const u32 i = i0 + (u32)u * AIWC_WAVE;
-              vv[u] = i < o1 ? S.stage[i] : ~0u;
+              vv[u] = S.stage[i < o1 ? i : o0];
             }
+            __builtin_amdgcn_sched_group_barrier(0x0100, 4, 0);
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-              if (vv[u] == ~0u) continue;
+              if (i0 + (u32)u * AIWC_WAVE >= o1) continue;
               const u32 off = (vv[u] >> 1) & 1023u;
               atomicAdd(&dn[cslot(off)], (vv[u] & 1u) ? 0x10000u : 1u);
             }
