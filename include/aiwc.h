@@ -297,13 +297,15 @@ aiwc_status aiwc_characterize(aiwc_ctx *ctx, const aiwc_trace *trace,
  * it needs zeroed with a kernel.  Limit: traces whose plan needs more than
  * AIWC_STATIC_SCRATCH_BYTES of scratch return UNSUPPORTED before anything
  * is enqueued; use aiwc_characterize for those.  The plan takes 12 B per
- * memory event (partition record and page tag; 20 B from 2^12 partitions
- * on, where the scatter runs in two passes), per-block partition
- * histograms, 8.25 B per branch event (radix buffers and digit counts),
- * 512 KiB per 65536 branch events for hot-site tables (history 16) and
- * ~1.2 MiB of fixed tables: at the 30% memory / 5% branch mix about 5 MiB
- * for 1e6 events, 30 MiB for 6.7e6 events, 62 MiB for 9e6 events (2.7e6
- * memory events), the largest that fit.
+ * memory event (partition record and page tag), 8 B more from 2^18 memory
+ * events or from 2^12 partitions on (one buffer: the two-level scatter's
+ * coarse buckets and the hot partitions' remaining records) with 2.1 MiB of
+ * hot-page tables from 2^18 memory events, per-block partition histograms,
+ * 8.25 B per branch event (radix buffers and digit counts), 512 KiB per
+ * 65536 branch events for hot-site tables (history 16) and ~1.2 MiB of
+ * fixed tables: at the 30% memory / 5% branch mix about 3 MiB for 5e5
+ * events, 9.4 MiB for 1e6, 48 MiB for 6.7e6, 63.5 MiB for 8.9e6 events
+ * (2.7e6 memory events), the largest that fit.
  * Errors: INVALID_ARG (null, foreign trace, result_bytes too small),
  * UNSUPPORTED (over the limit), HIP (launch failure, or the array's address
  * could not be found at context creation).                                  */
