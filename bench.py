@@ -610,10 +610,10 @@ def main() -> int:
         cpu = cpu_leg(args, small)
         if small is not None:
             small["parity_with_oracle"] = cpu["checks"]["config1_parity"]["ok"]
-    if small is not None:
-        small.pop("metrics", None)
         print(f"# cpu oracle: {cpu['value']:.3e} events/s on {cpu['cores']} threads, "
               f"{cpu['single_thread']['value']:.3e} on one", file=sys.stderr, flush=True)
+    if small is not None:
+        small.pop("metrics", None)
 
     out = {
         "metric": METRIC, "value": value, "unit": "events/s", "n_gpus": 1, "steps": args.steps,
