@@ -57,6 +57,40 @@ def test_static_equals_characterize_on_consecutive_calls():
     assert same(again[0], want[0][0], drop=()) and again[1] == want[0][1]
 
 
+
+def test_static_with_hot_partitions():
+    """A memory stream whose accesses pile onto two local pages (the hot-page
+    path: candidate tables and compacted records in the static array) and a
+    global one: the static entry equals aiwc_characterize, on two calls in a
+    row, the second on a smaller trace."""
+    import paper_1805_04207_amd as aiwc
+    from helpers import mem_trace
+    c = ctx()
+    rng = np.random.default_rng(21)
+    hs = []
+    for n, pages, local in ((1200000, [0, 1], True), (700000, [77], False)):
+        k = int(n * 0.9)
+        a_hot = rng.choice(np.asarray(pages, dtype=np.uint64), size=k) * np.uint64(1024) + \
+            rng.integers(0, 1024, size=k, dtype=np.uint64)
+        a = np.concatenate([a_hot, rng.integers(0, 1 << 26, size=n - k, dtype=np.uint64)])
+        kinds = (rng.random(n) < 0.3).astype(np.uint8)
+        if local:
+            kinds[:k] |= 2
+        order = rng.permutation(n)
+        hs.append(mem_trace(a[order], kinds[order]))
+    assert hs[0].addr.size >= 1 << 18 and hs[1].addr.size >= 1 << 18
+    n_cls = int(hs[0].table["op_class"].max()) + 1
+    devs = [aiwc.host_to_device(h, 0) for h in hs]
+    trs = [aiwc.device_trace(c, d, h.table, int(h.n_sites), int(h.history_len), 0)
+           for d, h in zip(devs, hs)]
+    want = [plain_run(c, t, n_cls) for t in trs]
+    for i in (0, 1):
+        print(f"[static] hot-page trace {i}: {hs[i].addr.size} memory events", flush=True)
+        got, cls = static_run(c, trs[i], n_cls)
+        assert same(got, want[i][0], drop=()), f"metrics differ on hot-page trace {i}"
+        assert cls == want[i][1], f"class histogram differs on hot-page trace {i}"
+
+
 def test_static_size_checks():
     import paper_1805_04207_amd as aiwc
     import paper_1805_04207_amd.aiwc as A
