@@ -113,8 +113,9 @@ void plan_trace(const aiwc_trace *t, u32 pbits, TracePlan &p, const Tune *tune, 
   p.o_part_tmp = (d.n_mem && p.pbits >= TWO_LEVEL_PBITS) ? take(8ull * nrec) : 0;
   p.o_part_cur = take(4ull * (P + 512));
   // hot pages: the state and tables, and a buffer for the compacted rest
-  // (the coarse-bucket records' buffer when there is one: free by then)
-  if (d.n_mem >= AIWC_HOT_PART) {
+  // (the coarse-bucket records' buffer when there is one: free by then);
+  // not for the partition groups of a stream, reduced without them
+  if (d.n_mem >= AIWC_HOT_PART && rec_cap == ~0ull) {
     p.o_mem_hot = take(4ull * AIWC_HOT_WORDS);
     p.o_part_cmp = p.o_part_tmp ? p.o_part_tmp : take(8ull * nrec);
   }

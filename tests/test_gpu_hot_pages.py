@@ -90,3 +90,50 @@ def test_produced_tiled_matmul():
     want = oracle.characterize(oracle.produce(p, L.global_size, L.local_size, L.fresh_args()))
     bad = compare(got, want)
     assert not bad, "\n".join(bad[:20])
+
+
+def test_hot_pages_through_batch_graph_and_stream():
+    """The hot-page path in the other entry points: a batch with hot and
+    ordinary traces (eager, and a captured graph replayed), a stream of the
+    same chunks (one memory stage over the concatenation) and the same stream
+    out of core (partition groups, where hot partitions are reduced by the
+    ordinary bucket kernel): each equal to the plain path or to the oracle on
+    the concatenation."""
+    import paper_1805_04207_amd as aiwc
+    from gpu_util import ctx, same
+    from helpers import random_trace
+    c = ctx()
+    rng = np.random.default_rng(31)
+    a0, k0 = hot_stream(rng, 1200000, [0, 1], 0.9, local=True)
+    a2, k2 = hot_stream(rng, 700000, [77, 5000], 0.85)
+    trs = [mem_trace(a0, k0), random_trace(rng, 64, 3000, 40, 16, addr_bits=20),
+           mem_trace(a2, k2)]
+    keep, hs = [], []
+    for tr in trs:
+        dev = aiwc.host_to_device(tr, 0)
+        keep.append(dev)
+        hs.append(aiwc.device_trace(c, dev, tr.table, int(tr.n_sites), int(tr.history_len)))
+    plain = [c.characterize(h).read() for h in hs]
+    print("batch, eager", flush=True)
+    got = [m.read() for m in c.characterize_batch(hs)]
+    for i in range(3):
+        assert same(got[i], plain[i]), f"batch, trace {i}"
+    print("batch, graph", flush=True)
+    for rep in range(3):
+        got = [m.read() for m in c.characterize_batch(hs, use_graph=True)]
+        for i in range(3):
+            assert same(got[i], plain[i]), f"graph replay {rep}, trace {i}"
+    # the concatenation (one history length, the largest site count)
+    want = oracle.characterize(oracle.MergedTrace(trs))
+    for budget in (0, 12 * (sum(t.addr.size for t in trs) // 3)):
+        print(f"stream, device budget {budget}", flush=True)
+        st = c.stream()
+        if budget:
+            st.set_device_budget(budget)
+        for h in hs:
+            st.append(h)
+        got = st.finish().read()
+        if budget:
+            assert st.stats()["groups"] >= 2
+        bad = compare(got, want)
+        assert not bad, "\n".join(bad[:20])
