@@ -145,12 +145,19 @@ __global__ void __launch_bounds__(BR_BLOCK) k_br_upsweep(TraceArgs A0, const Tra
   cnt[(u64)threadIdx.x * n_tiles + t] = h[threadIdx.x];
 }
 
+// The stable scatter of one tile: each record's rank among the tile's
+// records of its digit comes from wavefront ballots (rounds of BR_BLOCK
+// records in order); the tile is then staged in LDS in digit order and
+// written out in runs, one run per digit, instead of one scattered store per
+// record.
 template <bool BATCH, typename R>
 __global__ void __launch_bounds__(BR_BLOCK) k_br_downsweep(TraceArgs A0, const TraceArgs *batch,
                                                           u32 pass) {
   __shared__ u32 gofs[256];
   __shared__ u32 running[256];
+  __shared__ u32 start[256];
   __shared__ u32 wcnt[BR_BLOCK / AIWC_WAVE][256];
+  __shared__ R staged[BR_TILE];
   const TraceArgs A = trace_args<BATCH>(A0, batch);
   if (pass >= A.br_passes || blockIdx.x >= A.br_tiles || !rec_matches<R>(A)) return;
   const R *in = reinterpret_cast<const R *>((pass & 1) ? A.br_b : A.br_a);
@@ -163,6 +170,7 @@ __global__ void __launch_bounds__(BR_BLOCK) k_br_downsweep(TraceArgs A0, const T
   gofs[tid] = ofs[(u64)tid * n_tiles + t];
   running[tid] = 0;
   const u64 base = t * BR_TILE;
+  const u32 nt = (u32)((n - base) < (u64)BR_TILE ? (n - base) : (u64)BR_TILE);
   const u64 lt = (1ull << lane) - 1ull;
   R vals[BR_ROUNDS];
 #pragma unroll
@@ -170,15 +178,16 @@ __global__ void __launch_bounds__(BR_BLOCK) k_br_downsweep(TraceArgs A0, const T
     const u64 i = base + (u64)r * BR_BLOCK + tid;
     vals[r] = i < n ? in[i] : (R)0;
   }
+  // digit << 16 | rank among the tile's records of that digit (< BR_TILE)
+  u32 slot[BR_ROUNDS];
 #pragma unroll
   for (int r = 0; r < BR_ROUNDS; ++r) {
 #pragma unroll
     for (int w = 0; w < BR_BLOCK / AIWC_WAVE; ++w) wcnt[w][tid] = 0;
     __syncthreads();
-    const u64 i = base + (u64)r * BR_BLOCK + tid;
-    const bool valid = i < n;
-    const R v = vals[r];
-    const u32 d = (u32)(v >> shift) & 255u;
+    const u32 k = (u32)r * BR_BLOCK + (u32)tid;
+    const bool valid = k < nt;
+    const u32 d = (u32)(vals[r] >> shift) & 255u;
     u64 peers = __ballot(valid);
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
@@ -188,16 +197,45 @@ __global__ void __launch_bounds__(BR_BLOCK) k_br_downsweep(TraceArgs A0, const T
     const u32 rank = (u32)__builtin_popcountll(peers & lt);
     if (valid && rank == 0) wcnt[wave][d] = (u32)__builtin_popcountll(peers);
     __syncthreads();
-    if (valid) {
-      u32 before = running[d];
-      for (int w = 0; w < wave; ++w) before += wcnt[w][d];
-      out[gofs[d] + before + rank] = v;
-    }
+    u32 before = running[d];
+#pragma unroll
+    for (int w = 0; w < BR_BLOCK / AIWC_WAVE; ++w) before += w < wave ? wcnt[w][d] : 0u;
+    slot[r] = (d << 16) | (before + rank);
     __syncthreads();
     u32 add = 0;
 #pragma unroll
     for (int w = 0; w < BR_BLOCK / AIWC_WAVE; ++w) add += wcnt[w][tid];
     running[tid] += add;
+  }
+  __syncthreads();
+  // where each digit's records start in the tile: exclusive prefix of the
+  // tile's digit counts (one per thread, 256 threads)
+  {
+    const u32 x = running[tid];
+    u32 incl = x;
+#pragma unroll
+    for (int o = 1; o < AIWC_WAVE; o <<= 1) {
+      const u32 y = __shfl_up(incl, o, AIWC_WAVE);
+      if (lane >= o) incl += y;
+    }
+    if (lane == AIWC_WAVE - 1) wcnt[0][wave] = incl;
+    __syncthreads();
+    u32 off = 0;
+#pragma unroll
+    for (int w = 0; w < BR_BLOCK / AIWC_WAVE; ++w) off += w < wave ? wcnt[0][w] : 0u;
+    start[tid] = off + incl - x;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < BR_ROUNDS; ++r) {
+    const u32 k = (u32)r * BR_BLOCK + (u32)tid;
+    if (k < nt) staged[start[slot[r] >> 16] + (slot[r] & 0xFFFFu)] = vals[r];
+  }
+  __syncthreads();
+  for (u32 i = (u32)tid; i < nt; i += BR_BLOCK) {
+    const R v = staged[i];
+    const u32 d = (u32)(v >> shift) & 255u;
+    out[gofs[d] + (i - start[d])] = v;
   }
 }
 
