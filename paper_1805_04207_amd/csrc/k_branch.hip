@@ -145,18 +145,23 @@ __global__ void __launch_bounds__(BR_BLOCK) k_br_upsweep(TraceArgs A0, const Tra
   cnt[(u64)threadIdx.x * n_tiles + t] = h[threadIdx.x];
 }
 
-// The stable scatter of one tile: each record's rank among the tile's
-// records of its digit comes from wavefront ballots (rounds of BR_BLOCK
-// records in order); the tile is then staged in LDS in digit order and
-// written out in runs, one run per digit, instead of one scattered store per
-// record.
+// The stable scatter of one tile.  Each wavefront takes a contiguous quarter
+// of the tile and ranks its records among its own records of the same digit
+// (wavefront ballots, a running count per digit and wavefront in LDS: no
+// block barrier per round); the quarters' counts then give each digit's
+// start in the tile and each quarter's offset inside it, the tile is staged
+// in LDS in digit order (stable: quarters, rounds and lanes in index order)
+// and written out in runs, one run per digit.
 template <bool BATCH, typename R>
 __global__ void __launch_bounds__(BR_BLOCK) k_br_downsweep(TraceArgs A0, const TraceArgs *batch,
                                                           u32 pass) {
+  constexpr int NW = BR_BLOCK / AIWC_WAVE;
+  constexpr u32 SUB = BR_TILE / NW;            // records per wavefront
+  constexpr int WR = (int)(SUB / AIWC_WAVE);   // rounds per wavefront
   __shared__ u32 gofs[256];
-  __shared__ u32 running[256];
   __shared__ u32 start[256];
-  __shared__ u32 wcnt[BR_BLOCK / AIWC_WAVE][256];
+  __shared__ u32 wrun[NW][256];
+  __shared__ u32 wsum[NW];
   __shared__ R staged[BR_TILE];
   const TraceArgs A = trace_args<BATCH>(A0, batch);
   if (pass >= A.br_passes || blockIdx.x >= A.br_tiles || !rec_matches<R>(A)) return;
@@ -168,25 +173,25 @@ __global__ void __launch_bounds__(BR_BLOCK) k_br_downsweep(TraceArgs A0, const T
   const int tid = threadIdx.x, lane = lane_id(), wave = tid / AIWC_WAVE;
   const u64 t = blockIdx.x;
   gofs[tid] = ofs[(u64)tid * n_tiles + t];
-  running[tid] = 0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) wrun[w][tid] = 0;
   const u64 base = t * BR_TILE;
   const u32 nt = (u32)((n - base) < (u64)BR_TILE ? (n - base) : (u64)BR_TILE);
   const u64 lt = (1ull << lane) - 1ull;
-  R vals[BR_ROUNDS];
+  const u32 k0 = (u32)wave * SUB + (u32)lane;
+  R vals[WR];
 #pragma unroll
-  for (int r = 0; r < BR_ROUNDS; ++r) {
-    const u64 i = base + (u64)r * BR_BLOCK + tid;
-    vals[r] = i < n ? in[i] : (R)0;
+  for (int r = 0; r < WR; ++r) {
+    const u32 k = k0 + (u32)r * AIWC_WAVE;
+    vals[r] = k < nt ? in[base + k] : (R)0;
   }
-  // digit << 16 | rank among the tile's records of that digit (< BR_TILE)
-  u32 slot[BR_ROUNDS];
+  __syncthreads();
+  // digit << 16 | rank among this wavefront's records of that digit
+  u32 slot[WR];
+  u32 *run = wrun[wave];
 #pragma unroll
-  for (int r = 0; r < BR_ROUNDS; ++r) {
-#pragma unroll
-    for (int w = 0; w < BR_BLOCK / AIWC_WAVE; ++w) wcnt[w][tid] = 0;
-    __syncthreads();
-    const u32 k = (u32)r * BR_BLOCK + (u32)tid;
-    const bool valid = k < nt;
+  for (int r = 0; r < WR; ++r) {
+    const bool valid = k0 + (u32)r * AIWC_WAVE < nt;
     const u32 d = (u32)(vals[r] >> shift) & 255u;
     u64 peers = __ballot(valid);
 #pragma unroll
@@ -195,41 +200,42 @@ __global__ void __launch_bounds__(BR_BLOCK) k_br_downsweep(TraceArgs A0, const T
       peers &= ((d >> b) & 1u) ? m : ~m;
     }
     const u32 rank = (u32)__builtin_popcountll(peers & lt);
-    if (valid && rank == 0) wcnt[wave][d] = (u32)__builtin_popcountll(peers);
-    __syncthreads();
-    u32 before = running[d];
-#pragma unroll
-    for (int w = 0; w < BR_BLOCK / AIWC_WAVE; ++w) before += w < wave ? wcnt[w][d] : 0u;
+    // every lane reads its digit's count before the group's first lane
+    // adds the group (LDS operations of a wavefront complete in order)
+    const u32 before = run[d];
     slot[r] = (d << 16) | (before + rank);
-    __syncthreads();
-    u32 add = 0;
-#pragma unroll
-    for (int w = 0; w < BR_BLOCK / AIWC_WAVE; ++w) add += wcnt[w][tid];
-    running[tid] += add;
+    if (valid && rank == 0) run[d] = before + (u32)__builtin_popcountll(peers);
   }
   __syncthreads();
-  // where each digit's records start in the tile: exclusive prefix of the
-  // tile's digit counts (one per thread, 256 threads)
+  // per digit (one per thread): the quarters' exclusive prefix, in place,
+  // and the tile's count; then the digits' starts in the tile
   {
-    const u32 x = running[tid];
+    u32 x = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      const u32 c = wrun[w][tid];
+      wrun[w][tid] = x;
+      x += c;
+    }
     u32 incl = x;
 #pragma unroll
     for (int o = 1; o < AIWC_WAVE; o <<= 1) {
       const u32 y = __shfl_up(incl, o, AIWC_WAVE);
       if (lane >= o) incl += y;
     }
-    if (lane == AIWC_WAVE - 1) wcnt[0][wave] = incl;
+    if (lane == AIWC_WAVE - 1) wsum[wave] = incl;
     __syncthreads();
     u32 off = 0;
 #pragma unroll
-    for (int w = 0; w < BR_BLOCK / AIWC_WAVE; ++w) off += w < wave ? wcnt[0][w] : 0u;
+    for (int w = 0; w < NW; ++w) off += w < wave ? wsum[w] : 0u;
     start[tid] = off + incl - x;
   }
   __syncthreads();
 #pragma unroll
-  for (int r = 0; r < BR_ROUNDS; ++r) {
-    const u32 k = (u32)r * BR_BLOCK + (u32)tid;
-    if (k < nt) staged[start[slot[r] >> 16] + (slot[r] & 0xFFFFu)] = vals[r];
+  for (int r = 0; r < WR; ++r) {
+    if (k0 + (u32)r * AIWC_WAVE >= nt) continue;
+    const u32 d = slot[r] >> 16;
+    staged[start[d] + run[d] + (slot[r] & 0xFFFFu)] = vals[r];
   }
   __syncthreads();
   for (u32 i = (u32)tid; i < nt; i += BR_BLOCK) {
