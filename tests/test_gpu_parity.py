@@ -80,6 +80,25 @@ def test_long_segments():
     check(mk(op, [70_000, 80_000]))
 
 
+
+@pytest.mark.parametrize("n_bar", [0, 1, 2, 3, 5])
+def test_barrier_ids(n_bar):
+    """Work-item streams long enough for the vectorised chunks, with 0, 1, 2
+    (barrier ids compared directly) and 3 or 5 (kinds looked up per event)
+    opcode ids of barrier kind."""
+    rng = np.random.default_rng(60 + n_bar)
+    n_ids = 40
+    bars = set(rng.choice(n_ids, size=n_bar, replace=False).tolist())
+    tab = table([(i % 7, 1, BARRIER if i in bars else COMPUTE) for i in range(n_ids)])
+    lens = rng.integers(0, 6000, size=64)
+    op = rng.integers(0, n_ids, size=int(lens.sum())).astype(np.uint16)
+    # barriers rare, as in kernels: most drawn barrier ids become other ids
+    other = np.asarray([i for i in range(n_ids) if i not in bars], dtype=np.uint16)
+    drop = np.isin(op, list(bars)) & (rng.random(op.size) < 0.98)
+    op[drop] = rng.choice(other, size=int(drop.sum()))
+    check(mk(op, list(lens), tab=tab))
+
+
 def test_many_opcode_ids_global_path():
     # more than 8192 ids: histogram in global memory
     n = 10000
