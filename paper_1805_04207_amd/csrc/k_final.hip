@@ -54,6 +54,41 @@ __device__ u64 block_max(u64 v, FinShared &S) {
 template <typename Get>
 __device__ u64 coverage90(u64 n_items, u64 total, Get get, FinShared &S) {
   if (total == 0) return 0;
+  constexpr int R = 8;
+  if (n_items <= (u64)R * FB) {
+    // at most R items per thread: read once into registers, then the same
+    // search over them
+    u64 f[R], m[R], fmax = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const u64 i = threadIdx.x + (u64)r * FB;
+      f[r] = 0;
+      m[r] = 0;
+      if (i < n_items) get(i, f[r], m[r]);
+      if (!m[r]) f[r] = 0;
+      fmax = f[r] > fmax ? f[r] : fmax;
+    }
+    fmax = block_max(fmax, S);
+    u64 lo = 1, hi = fmax;
+    while (lo < hi) {
+      const u64 mid = lo + (hi - lo + 1) / 2;
+      u64 mass = 0;
+#pragma unroll
+      for (int r = 0; r < R; ++r) mass += f[r] >= mid ? m[r] * f[r] : 0ull;
+      mass = block_sum(mass, S);
+      if ((unsigned __int128)mass * 10 >= (unsigned __int128)total * 9) lo = mid; else hi = mid - 1;
+    }
+    const u64 t = lo;
+    u64 above = 0, above_n = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (f[r] > t) { above += m[r] * f[r]; above_n += m[r]; }
+    above = block_sum(above, S);
+    above_n = block_sum(above_n, S);
+    const unsigned __int128 need = (unsigned __int128)total * 9 - (unsigned __int128)above * 10;
+    const unsigned __int128 per = (unsigned __int128)t * 10;
+    return above_n + (u64)((need + per - 1) / per);
+  }
   u64 fmax = 0;
   for (u64 i = threadIdx.x; i < n_items; i += FB) {
     u64 f, m;
@@ -222,10 +257,16 @@ __global__ void __launch_bounds__(FB) k_finalize(TraceArgs A0, const TraceArgs *
     __syncthreads();
     if (tid == 0) S.nc = 0;
     __syncthreads();
-    for (u64 i = tid; i < A.sp_cap; i += FB) {
-      if (!F[i]) continue;
-      const u32 j = atomicAdd(&S.nc, 1u);
-      if (j < SPEC_LDS) { S.cf[j] = F[i]; S.cm[j] = M[i]; }
+    for (u64 i0 = tid; i0 < A.sp_cap; i0 += 8 * FB) {
+      u64 f[8];   // eight loads in flight before any is tested
+#pragma unroll
+      for (int q = 0; q < 8; ++q) f[q] = i0 + (u64)q * FB < A.sp_cap ? F[i0 + (u64)q * FB] : 0;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        if (!f[q]) continue;
+        const u32 j = atomicAdd(&S.nc, 1u);
+        if (j < SPEC_LDS) { S.cf[j] = f[q]; S.cm[j] = M[i0 + (u64)q * FB]; }
+      }
     }
     __syncthreads();
     const u32 nc = S.nc;
@@ -255,10 +296,16 @@ __global__ void __launch_bounds__(FB) k_finalize(TraceArgs A0, const TraceArgs *
   for (int s = 0; s < 2; ++s) {
     const u64 *F = A.sp_f + (u64)s * A.sp_cap, *M = A.sp_m + (u64)s * A.sp_cap;
     u64 *dst = A.out_spec + (u64)s * 2 * A.spec_export_cap;
-    for (u64 i = tid; i < A.sp_cap; i += FB) {
-      if (!F[i]) continue;
-      const u64 j = atomicAdd((u64 *)&S.bcast[1 + s], 1ull);
-      if (j < A.spec_export_cap) { dst[2 * j] = F[i]; dst[2 * j + 1] = M[i]; }
+    for (u64 i0 = tid; i0 < A.sp_cap; i0 += 8 * FB) {
+      u64 f[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) f[q] = i0 + (u64)q * FB < A.sp_cap ? F[i0 + (u64)q * FB] : 0;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        if (!f[q]) continue;
+        const u64 j = atomicAdd((u64 *)&S.bcast[1 + s], 1ull);
+        if (j < A.spec_export_cap) { dst[2 * j] = f[q]; dst[2 * j + 1] = M[i0 + (u64)q * FB]; }
+      }
     }
   }
   __syncthreads();
