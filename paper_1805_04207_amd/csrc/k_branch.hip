@@ -10,7 +10,8 @@
 //
 // GPU plan:
 //  1. k_br_pack     : (site, taken) -> u32 (site << 1 | taken), validated.
-//  2. stable LSD radix sort by site, 8 bits per pass: per-tile digit counts
+//  2. stable LSD radix sort by site, the site bits split evenly over passes
+//     of at most 8 bits (4096 sites: 6 + 6): per-tile digit counts
 //     (k_br_upsweep), one exclusive scan, and a stable scatter whose ranks
 //     come from wavefront ballots (k_br_downsweep).  After it every site's
 //     outcomes are contiguous and in stream order.
@@ -118,6 +119,14 @@ template <typename R> __device__ __forceinline__ bool rec_matches(const TraceArg
   return (sizeof(R) == 8) == global_history(A);
 }
 
+// The site bits split evenly over the passes (at most 8 per pass): with 4096
+// sites two passes of 6 bits, 64 digits each, rather than 8 + 4.
+__device__ __forceinline__ u32 radix_bits(const TraceArgs &A) {
+  u32 bits = 0;
+  while (bits < 32 && (1u << bits) < A.n_sites) ++bits;
+  return (bits + A.br_passes - 1) / A.br_passes;
+}
+
 template <bool BATCH, typename R>
 __global__ void __launch_bounds__(BR_BLOCK) k_br_upsweep(TraceArgs A0, const TraceArgs *batch,
                                                         u32 pass) {
@@ -126,7 +135,9 @@ __global__ void __launch_bounds__(BR_BLOCK) k_br_upsweep(TraceArgs A0, const Tra
   if (pass >= A.br_passes || blockIdx.x >= A.br_tiles || !rec_matches<R>(A)) return;
   const R *in = reinterpret_cast<const R *>((pass & 1) ? A.br_b : A.br_a);
   const u64 n = A.n_branch, n_tiles = A.br_tiles;
-  const u32 shift = (sizeof(R) == 8 ? 33u : 1u) + 8u * pass;
+  const u32 bpp = radix_bits(A);
+  const u32 shift = (sizeof(R) == 8 ? 33u : 1u) + bpp * pass;
+  const u32 dmask = (1u << bpp) - 1u;
   u32 *cnt = A.br_cnt;
   h[threadIdx.x] = 0;
   const u64 t = blockIdx.x;
@@ -140,7 +151,7 @@ __global__ void __launch_bounds__(BR_BLOCK) k_br_upsweep(TraceArgs A0, const Tra
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < BR_ROUNDS; ++r)
-    if (vals[r] != ~(R)0) atomicAdd(&h[(u32)(vals[r] >> shift) & 255u], 1u);
+    if (vals[r] != ~(R)0) atomicAdd(&h[(u32)(vals[r] >> shift) & dmask], 1u);
   __syncthreads();
   cnt[(u64)threadIdx.x * n_tiles + t] = h[threadIdx.x];
 }
@@ -168,7 +179,9 @@ __global__ void __launch_bounds__(BR_BLOCK) k_br_downsweep(TraceArgs A0, const T
   const R *in = reinterpret_cast<const R *>((pass & 1) ? A.br_b : A.br_a);
   R *out = reinterpret_cast<R *>((pass & 1) ? A.br_a : A.br_b);
   const u64 n = A.n_branch, n_tiles = A.br_tiles;
-  const u32 shift = (sizeof(R) == 8 ? 33u : 1u) + 8u * pass;
+  const u32 bpp = radix_bits(A);
+  const u32 shift = (sizeof(R) == 8 ? 33u : 1u) + bpp * pass;
+  const u32 dmask = (1u << bpp) - 1u;
   const u32 *ofs = A.br_cnt;
   const int tid = threadIdx.x, lane = lane_id(), wave = tid / AIWC_WAVE;
   const u64 t = blockIdx.x;
@@ -192,10 +205,9 @@ __global__ void __launch_bounds__(BR_BLOCK) k_br_downsweep(TraceArgs A0, const T
 #pragma unroll
   for (int r = 0; r < WR; ++r) {
     const bool valid = k0 + (u32)r * AIWC_WAVE < nt;
-    const u32 d = (u32)(vals[r] >> shift) & 255u;
+    const u32 d = (u32)(vals[r] >> shift) & dmask;
     u64 peers = __ballot(valid);
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
+    for (u32 b = 0; b < bpp; ++b) {
       const u64 m = __ballot((d >> b) & 1u);
       peers &= ((d >> b) & 1u) ? m : ~m;
     }
@@ -240,7 +252,7 @@ __global__ void __launch_bounds__(BR_BLOCK) k_br_downsweep(TraceArgs A0, const T
   __syncthreads();
   for (u32 i = (u32)tid; i < nt; i += BR_BLOCK) {
     const R v = staged[i];
-    const u32 d = (u32)(v >> shift) & 255u;
+    const u32 d = (u32)(v >> shift) & dmask;
     out[gofs[d] + (i - start[d])] = v;
   }
 }
