@@ -281,8 +281,9 @@ __device__ __forceinline__ void tile_scan(TileShared &S) {
 
 // Stage the tile's records by digit and write them out in runs: dst[gbase[d]
 // + rank among the tile's records of digit d].  Every thread calls it with
-// its own records (nv of them, digits dg).
-template <int R>
+// its own records (nv of them, digits dg).  TOP: the digit is the record's
+// top byte, cleared on the way out (no digit array in LDS).
+template <int R, bool TOP>
 __device__ __forceinline__ void tile_write(TileShared &S, const u64 (&rec)[R], const u32 (&dg)[R],
                                            int nv, u32 n, u64 *dst, u32 ndig, u32 *cursor) {
   const int tid = threadIdx.x;
@@ -300,13 +301,14 @@ __device__ __forceinline__ void tile_write(TileShared &S, const u64 (&rec)[R], c
     if (j < nv) {
       const u32 r = atomicAdd(&S.cnt[dg[j]], 1u);
       S.stage[r] = rec[j];
-      S.dig[r] = (uint8_t)dg[j];
+      if (!TOP) S.dig[r] = (uint8_t)dg[j];
     }
   }
   __syncthreads();
   for (u32 i = tid; i < n; i += SC_BLOCK) {
-    const u32 d = S.dig[i];
-    dst[S.gbase[d] + (i - S.start[d])] = S.stage[i];
+    const u64 v = S.stage[i];
+    const u32 d = TOP ? (u32)(v >> 56) : S.dig[i];
+    dst[S.gbase[d] + (i - S.start[d])] = TOP ? v & ((1ull << 56) - 1ull) : v;
   }
   __syncthreads();
 }
@@ -359,7 +361,7 @@ __global__ void __launch_bounds__(SC_BLOCK, 8) k_mem_scatter_a(TraceArgs A0, con
         atomicAdd(&S.cnt[dg[j]], 1u);
       }
     }
-    tile_write<8>(S, rec, dg, nv, n, A.part_tmp, NC, ccur);
+    tile_write<8, false>(S, rec, dg, nv, n, A.part_tmp, NC, ccur);
   }
 }
 
@@ -399,12 +401,12 @@ __global__ void __launch_bounds__(SC_BLOCK, 8) k_mem_scatter_b(TraceArgs A0, con
       if (k < n) {
         const u64 r = A.part_tmp[t0 + k];
         dg[j] = (u32)(r >> 56);
-        rec[j] = r & ((1ull << 56) - 1ull);
+        rec[j] = r;   // the fine digit stays in the top byte until written out
         atomicAdd(&S.cnt[dg[j]], 1u);
         nv = j + 1;
       }
     }
-    tile_write<8>(S, rec, dg, nv, n, A.part_rec, 256u, A.part_cur + (c << FINE_BITS));
+    tile_write<8, true>(S, rec, dg, nv, n, A.part_rec, 256u, A.part_cur + (c << FINE_BITS));
   }
 }
 
