@@ -9,18 +9,30 @@
 // the addresses are radix-partitioned once by a bijective hash of their
 // 1 KiB page (a >> 10).  Every bucket a >> k with k <= 10 lies inside one
 // page, hence inside one partition, and partitions are independent.
-//   k_mem_hist    : per-block partition histogram of the address stream
-//   k_mem_colscan : exclusive scan over blocks, per partition
-//   k_mem_binscan : exclusive scan over partitions
-//   k_mem_scatter : write one 64-bit record per access into its partition
-//   k_mem_bucket  : per partition, an LDS open-addressing table of the
-//                   distinct addresses (count + read/write flags), coarsened
-//                   level by level (key >> 1) up to k = 10; each level adds
-//                   its distinct count and its entropy terms
-//                   c * log2(N / c) (exact 128-bit fixed point, so the sum is
-//                   order independent), level 0 also its count spectrum.
-//                   A partition whose distinct set overflows the table is
-//                   split by further hash bits and redone (exact).
+//   k_mem_hist      : per-block partition histogram of the address stream
+//                     (and the reads / writes of each space)
+//   k_mem_colscan   : exclusive scan over blocks, per partition
+//   k_mem_binscan   : exclusive scan over partitions; the bucket kernel's
+//                     queue (longest partitions first), the hot partitions,
+//                     and the cursors of the two-level scatter
+//   k_mem_scatter   : one 64-bit record per access into its partition
+//                     (below 2^12 partitions), or
+//   k_mem_scatter_a : tiles sorted in LDS by coarse bucket (256 partitions)
+//   k_mem_scatter_b : and within each bucket by partition, written in runs
+//   k_mem_hot_pick  : candidate pages of each hot partition (2^18 records
+//                     and more) from a sample of its records
+//   k_mem_hot_count : the candidates' offsets counted in parallel pieces into
+//                     per-page tables, the other records compacted
+//   k_mem_bucket    : per partition (persistent blocks, a queue): an LDS table
+//                     of its pages, the records regrouped page by page in
+//                     LDS, and every level's nodes (the records of a page
+//                     whose offsets agree on bits k..9) from wavefront
+//                     ballots (small pages) or 1024 LDS offset counters
+//                     (larger pages); each node adds 1 to distinct_k and
+//                     c * log2(N / c) to level k (fixed point, integer sums,
+//                     so the result is order independent), level 0 also its
+//                     count spectrum.  A partition whose pages overflow the
+//                     table is split by further hash bits and redone (exact).
 //
 // Record layout (64 bits; P = 2^pbits partitions, h = mix54(a >> 10)):
 //   [0]                  write flag
