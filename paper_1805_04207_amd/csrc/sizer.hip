@@ -73,67 +73,72 @@ __device__ void ft_insert(FeatShared &S, u64 key) {
 __device__ float flog2p1(double x) { return (float)log2(1.0 + x); }
 
 // One block per trace: raw features into out[40].
+// One block per trace (blockIdx.x) and per (skip, space) pair of the prefix
+// distinct counts (blockIdx.y = 2 * skip + space): the 22 counts are
+// independent, so they run side by side; block y = 0 also takes the scalar
+// counts and the growth curve.
 __global__ void __launch_bounds__(1024) k_features(const TraceArgs *batch, float *out) {
   __shared__ FeatShared S;
   const TraceArgs &A = batch[blockIdx.x];
   float *f = out + (u64)blockIdx.x * NF;
   const int tid = threadIdx.x;
   const u32 np = (u32)(A.n_mem < PREFIX ? A.n_mem : PREFIX);
-  // scalar counts of the prefix
-  u32 nloc = 0, nwr = 0, nal = 0, near = 0;
-  u64 mn0 = ~0ull, mx0 = 0, mn1 = ~0ull, mx1 = 0;
-  for (u32 i = tid; i < np; i += 1024) {
-    const u64 a = A.addr[i];
-    const uint8_t k = A.mem_kind[i];
-    nloc += (k >> 1) & 1u;
-    nwr += k & 1u;
-    nal += (a & 3ull) == 0;
-    if (i > 0) {
-      const u64 b = A.addr[i - 1];
-      const u64 d = a > b ? a - b : b - a;
-      near += d <= 256;
-    }
-    if (k & 2u) { mn1 = a < mn1 ? a : mn1; mx1 = a > mx1 ? a : mx1; }
-    else { mn0 = a < mn0 ? a : mn0; mx0 = a > mx0 ? a : mx0; }
-  }
-  if (tid < 2) { S.mn[tid] = ~0ull; S.mx[tid] = 0; }
-  if (tid < 32) S.red[tid] = 0;
-  __syncthreads();
-  u32 v4[4] = {nloc, nwr, nal, near};
-  for (int j = 0; j < 4; ++j) {
-    u32 x = (u32)wave_sum_u64(v4[j]);
-    if (lane_id() == 0 && x) atomicAdd(&S.red[j], x);
-  }
-  if (mn0 != ~0ull) { atomicMin(&S.mn[0], mn0); atomicMax(&S.mx[0], mx0); }
-  if (mn1 != ~0ull) { atomicMin(&S.mn[1], mn1); atomicMax(&S.mx[1], mx1); }
-  __syncthreads();
-  float dist[2][AIWC_NSKIP];
-  float grow[4];
-  // distinct counts of the prefix per space and skip; growth curve at k = 0
-  for (int k = 0; k < AIWC_NSKIP; ++k) {
-    for (int sp = 0; sp < 2; ++sp) {
-      for (u32 i = tid; i < FT_SLOTS; i += 1024) S.key[i] = ~0ull;
-      if (tid == 0) S.claimed = 0;
-      __syncthreads();
-      const u32 stops[4] = {1024, 2048, 4096, 8192};
-      u32 done = 0;
-      for (int g = 0; g < 4; ++g) {
-        const u32 end = stops[g] < np ? stops[g] : np;
-        for (u32 i = done + tid; i < end; i += 1024) {
-          const uint8_t kk = A.mem_kind[i];
-          if ((int)((kk >> 1) & 1u) != sp) continue;
-          ft_insert(S, A.addr[i] >> k);
-        }
-        done = end > done ? end : done;
-        __syncthreads();
-        if (k == 0 && sp == 0) grow[g] = flog2p1((double)S.claimed);
-        __syncthreads();
+  const int k = (int)blockIdx.y >> 1, sp = (int)blockIdx.y & 1;
+  const bool first = blockIdx.y == 0;
+  if (first) {
+    // scalar counts of the prefix
+    u32 nloc = 0, nwr = 0, nal = 0, near = 0;
+    u64 mn0 = ~0ull, mx0 = 0, mn1 = ~0ull, mx1 = 0;
+    for (u32 i = tid; i < np; i += 1024) {
+      const u64 a = A.addr[i];
+      const uint8_t kd = A.mem_kind[i];
+      nloc += (kd >> 1) & 1u;
+      nwr += kd & 1u;
+      nal += (a & 3ull) == 0;
+      if (i > 0) {
+        const u64 b = A.addr[i - 1];
+        const u64 d = a > b ? a - b : b - a;
+        near += d <= 256;
       }
-      dist[sp][k] = flog2p1((double)S.claimed);
-      __syncthreads();
+      if (kd & 2u) { mn1 = a < mn1 ? a : mn1; mx1 = a > mx1 ? a : mx1; }
+      else { mn0 = a < mn0 ? a : mn0; mx0 = a > mx0 ? a : mx0; }
     }
+    if (tid < 2) { S.mn[tid] = ~0ull; S.mx[tid] = 0; }
+    if (tid < 32) S.red[tid] = 0;
+    __syncthreads();
+    u32 v4[4] = {nloc, nwr, nal, near};
+    for (int j = 0; j < 4; ++j) {
+      u32 x = (u32)wave_sum_u64(v4[j]);
+      if (lane_id() == 0 && x) atomicAdd(&S.red[j], x);
+    }
+    if (mn0 != ~0ull) { atomicMin(&S.mn[0], mn0); atomicMax(&S.mx[0], mx0); }
+    if (mn1 != ~0ull) { atomicMin(&S.mn[1], mn1); atomicMax(&S.mx[1], mx1); }
+    __syncthreads();
   }
+  // the distinct count of this block's (skip, space) over the prefix; the
+  // growth curve at skip 0 in space 0
+  float grow[4];
+  for (u32 i = tid; i < FT_SLOTS; i += 1024) S.key[i] = ~0ull;
+  if (tid == 0) S.claimed = 0;
+  __syncthreads();
+  const u32 stops[4] = {1024, 2048, 4096, 8192};
+  u32 done = 0;
+  for (int g = 0; g < 4; ++g) {
+    const u32 end = stops[g] < np ? stops[g] : np;
+    for (u32 i = done + tid; i < end; i += 1024) {
+      const uint8_t kk = A.mem_kind[i];
+      if ((int)((kk >> 1) & 1u) != sp) continue;
+      ft_insert(S, A.addr[i] >> k);
+    }
+    done = end > done ? end : done;
+    __syncthreads();
+    if (first) grow[g] = flog2p1((double)S.claimed);
+    __syncthreads();
+  }
+  const float dist = flog2p1((double)S.claimed);
   if (tid != 0) return;
+  f[(sp ? 19 : 8) + k] = dist;
+  if (!first) return;
   const double npd = np ? (double)np : 1.0;
   f[0] = flog2p1((double)A.n_events);
   f[1] = flog2p1((double)A.n_mem);
@@ -143,7 +148,6 @@ __global__ void __launch_bounds__(1024) k_features(const TraceArgs *batch, float
   f[5] = flog2p1((double)A.n_sites);
   f[6] = (float)(S.red[0] / npd);
   f[7] = (float)(S.red[1] / npd);
-  for (int k = 0; k < AIWC_NSKIP; ++k) { f[8 + k] = dist[0][k]; f[19 + k] = dist[1][k]; }
   for (int g = 0; g < 4; ++g) f[30 + g] = grow[g];
   f[34] = flog2p1(npd);
   f[35] = S.mx[0] >= S.mn[0] && S.mn[0] != ~0ull ? flog2p1((double)(S.mx[0] - S.mn[0])) : 0.f;
@@ -425,7 +429,7 @@ static aiwc_status features_impl(aiwc_ctx *ctx, const aiwc_trace *const *traces,
     return AIWC_ERR_OUT_OF_MEMORY;
   }
   hipMemcpy(d, args.data(), sizeof(TraceArgs) * n, hipMemcpyHostToDevice);
-  hipLaunchKernelGGL(k_features, dim3((unsigned)n), dim3(1024), 0, s, d, dev_out);
+  hipLaunchKernelGGL(k_features, dim3((unsigned)n, 2 * AIWC_NSKIP), dim3(1024), 0, s, d, dev_out);
   hipError_t e = hipStreamSynchronize(s);
   hipFree(d);
   if (e != hipSuccess || hipGetLastError() != hipSuccess) {
