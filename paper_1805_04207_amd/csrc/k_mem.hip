@@ -161,12 +161,19 @@ __global__ void k_mem_colscan(TraceArgs A0, const TraceArgs *batch) {
   const u32 P = 1u << A.pbits;
   const u32 b = blockIdx.x * blockDim.x + threadIdx.x;
   if (A.n_mem == 0 || b >= P) return;
+  // sixteen loads in flight, then their prefix written back
   u32 s = 0;
-  for (u32 w = 0; w < A.n_hist_blocks; ++w) {
-    u32 *p = A.part_hist + (u64)w * P + b;
-    u32 v = *p;
-    *p = s;
-    s += v;
+  const u32 nb = A.n_hist_blocks;
+  for (u32 w0 = 0; w0 < nb; w0 += 16) {
+    u32 v[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) v[j] = w0 + j < nb ? A.part_hist[(u64)(w0 + j) * P + b] : 0u;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      if (w0 + j >= nb) break;
+      A.part_hist[(u64)(w0 + j) * P + b] = s;
+      s += v[j];
+    }
   }
   A.part_off[b] = s;
 }
@@ -210,13 +217,24 @@ __global__ void __launch_bounds__(1024) k_mem_binscan(TraceArgs A0, const TraceA
   __shared__ u32 nbig, nsmall, nhot, hot[AIWC_HOT_PMAX];
   if (threadIdx.x == 0) { nbig = 0; nsmall = 0; nhot = 0; }
   __syncthreads();
-  for (u32 i = threadIdx.x; i < P; i += 1024) {
-    const u32 sz = A.part_off[i + 1] - A.part_off[i];
-    if (sz > AIWC_STAGE_CAP) A.part_order[atomicAdd(&nbig, 1u)] = i;
-    if (A.mem_hot && sz >= AIWC_HOT_PART) {
-      const u32 k = atomicAdd(&nhot, 1u);
-      if (k < AIWC_HOT_PMAX) hot[k] = i;
-    }
+  // list appends: one LDS atomic per wavefront and list, ranks from ballots
+  const int lane = lane_id();
+  const u64 lt = (1ull << lane) - 1ull;
+  auto append = [&](u32 &count, bool mine) {
+    const u64 B = __ballot(mine);
+    u32 base = 0;
+    if (lane == 0 && B) base = atomicAdd(&count, (u32)__builtin_popcountll(B));
+    return (u32)__builtin_amdgcn_readfirstlane((int)base) + (u32)__builtin_popcountll(B & lt);
+  };
+  for (u32 i0 = 0; i0 < P; i0 += 1024) {
+    const u32 i = i0 + threadIdx.x;
+    const u32 sz = i < P ? A.part_off[i + 1] - A.part_off[i] : 0u;
+    const bool big = i < P && sz > AIWC_STAGE_CAP;
+    const u32 kb = append(nbig, big);
+    if (big) A.part_order[kb] = i;
+    const bool isHot = i < P && A.mem_hot && sz >= AIWC_HOT_PART;
+    const u32 kh = append(nhot, isHot);
+    if (isHot && kh < AIWC_HOT_PMAX) hot[kh] = i;
   }
   __syncthreads();
   if (A.mem_hot && threadIdx.x == 0) {
@@ -236,9 +254,12 @@ __global__ void __launch_bounds__(1024) k_mem_binscan(TraceArgs A0, const TraceA
     H[2] = 0;
   }
   const u32 nb = nbig;
-  for (u32 i = threadIdx.x; i < P; i += 1024)
-    if (A.part_off[i + 1] - A.part_off[i] <= AIWC_STAGE_CAP)
-      A.part_order[nb + atomicAdd(&nsmall, 1u)] = i;
+  for (u32 i0 = 0; i0 < P; i0 += 1024) {
+    const u32 i = i0 + threadIdx.x;
+    const bool small = i < P && A.part_off[i + 1] - A.part_off[i] <= AIWC_STAGE_CAP;
+    const u32 ks = append(nsmall, small);
+    if (small) A.part_order[nb + ks] = i;
+  }
   if (!A.part_tmp) return;
   // two-level scatter: fine cursors (one per partition), coarse cursors
   // (one per 256 partitions), and where each coarse bucket's tiles start
