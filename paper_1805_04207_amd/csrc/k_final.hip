@@ -182,6 +182,68 @@ __device__ double median_of(const u64 *hist, const u64 *large, u64 n_large, u64 
   return ((double)a + (double)b) * 0.5;
 }
 
+// The memory spaces' 90% footprints from their level-0 spectra (each
+// compacted into LDS when it fits) and the spectra's export (block 2 of
+// k_finalize).
+__device__ void spectrum_part(const TraceArgs &A, FinShared &S, aiwc_metrics_host *o,
+                              u64 *status) {
+  const int tid = threadIdx.x;
+  DevAccum *acc = A.acc;
+  u64 fp90[2];
+  for (int s = 0; s < 2; ++s) {
+    const u64 *F = A.sp_f + (u64)s * A.sp_cap, *M = A.sp_m + (u64)s * A.sp_cap;
+    const u64 N = acc->sp_reads[s] + acc->sp_writes[s];
+    __syncthreads();
+    if (tid == 0) S.nc = 0;
+    __syncthreads();
+    for (u64 i0 = tid; i0 < A.sp_cap; i0 += 8 * FB) {
+      u64 f[8];   // eight loads in flight before any is tested
+#pragma unroll
+      for (int q = 0; q < 8; ++q) f[q] = i0 + (u64)q * FB < A.sp_cap ? F[i0 + (u64)q * FB] : 0;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        if (!f[q]) continue;
+        const u32 j = atomicAdd(&S.nc, 1u);
+        if (j < SPEC_LDS) { S.cf[j] = f[q]; S.cm[j] = M[i0 + (u64)q * FB]; }
+      }
+    }
+    __syncthreads();
+    const u32 nc = S.nc;
+    if (nc <= SPEC_LDS) {
+      const u64 *cf = S.cf, *cm = S.cm;
+      fp90[s] = coverage90((u64)nc, N, [cf, cm](u64 i, u64 &f, u64 &m) { f = cf[i]; m = cm[i]; }, S);
+    } else {
+      fp90[s] = coverage90((u64)A.sp_cap, N,
+                           [F, M](u64 i, u64 &f, u64 &m) { f = F[i]; m = f ? M[i] : 0; }, S);
+    }
+  }
+
+  if (tid == 0) { S.bcast[1] = 0; S.bcast[2] = 0; }
+  __syncthreads();
+  for (int s = 0; s < 2; ++s) {
+    const u64 *F = A.sp_f + (u64)s * A.sp_cap, *M = A.sp_m + (u64)s * A.sp_cap;
+    u64 *dst = A.out_spec + (u64)s * 2 * A.spec_export_cap;
+    for (u64 i0 = tid; i0 < A.sp_cap; i0 += 8 * FB) {
+      u64 f[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) f[q] = i0 + (u64)q * FB < A.sp_cap ? F[i0 + (u64)q * FB] : 0;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        if (!f[q]) continue;
+        const u64 j = atomicAdd((u64 *)&S.bcast[1 + s], 1ull);
+        if (j < A.spec_export_cap) { dst[2 * j] = f[q]; dst[2 * j + 1] = M[i0 + (u64)q * FB]; }
+      }
+    }
+  }
+  __syncthreads();
+
+  if (tid == 0) {
+    o->space[0].footprint_90 = fp90[0];
+    o->space[1].footprint_90 = fp90[1];
+    status[2] = S.bcast[1] | (S.bcast[2] << 32);
+  }
+}
+
 template <bool BATCH>
 __global__ void __launch_bounds__(FB) k_finalize(TraceArgs A0, const TraceArgs *batch) {
   __shared__ FinShared S;
@@ -190,6 +252,20 @@ __global__ void __launch_bounds__(FB) k_finalize(TraceArgs A0, const TraceArgs *
   DevAccum *acc = A.acc;
   aiwc_metrics_host *o = A.out;
   u64 *status = reinterpret_cast<u64 *>(o + 1);
+  // Three blocks per trace, each writing fields of its own: block 1 the IPT
+  // median, block 2 the 90% footprints and the spectrum exports, block 0
+  // everything else.
+  const int part = blockIdx.x;
+  if (part == 1) {
+    const u64 nl_ipt = acc->ipt_large_n < A.large_cap ? acc->ipt_large_n : A.large_cap;
+    const double ipt_med = median_of(A.ipt_hist, A.ipt_large, nl_ipt, acc->ipt_cnt, S);
+    if (tid == 0) o->ipt_median = ipt_med;
+    return;
+  }
+  if (part == 2) {
+    spectrum_part(A, S, o, status);
+    return;
+  }
 
   // ---- compute: class histogram, SIMD sums, kind counts
   u64 s1 = 0, s2lo = 0, s2hi = 0, wmax = 0, nload = 0, nstore = 0, natom = 0, nbr = 0;
@@ -245,39 +321,7 @@ __global__ void __launch_bounds__(FB) k_finalize(TraceArgs A0, const TraceArgs *
 
   // ---- parallelism
   const u64 nl_itb = acc->itb_large_n < A.large_cap ? acc->itb_large_n : A.large_cap;
-  const u64 nl_ipt = acc->ipt_large_n < A.large_cap ? acc->ipt_large_n : A.large_cap;
   const double itb_med = median_of(A.itb_hist, A.itb_large, nl_itb, acc->itb_cnt, S);
-  const double ipt_med = median_of(A.ipt_hist, A.ipt_large, nl_ipt, acc->ipt_cnt, S);
-
-  // ---- memory: compact each space's sparse spectrum, then the coverage scan
-  u64 fp90[2];
-  for (int s = 0; s < 2; ++s) {
-    const u64 *F = A.sp_f + (u64)s * A.sp_cap, *M = A.sp_m + (u64)s * A.sp_cap;
-    const u64 N = acc->sp_reads[s] + acc->sp_writes[s];
-    __syncthreads();
-    if (tid == 0) S.nc = 0;
-    __syncthreads();
-    for (u64 i0 = tid; i0 < A.sp_cap; i0 += 8 * FB) {
-      u64 f[8];   // eight loads in flight before any is tested
-#pragma unroll
-      for (int q = 0; q < 8; ++q) f[q] = i0 + (u64)q * FB < A.sp_cap ? F[i0 + (u64)q * FB] : 0;
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        if (!f[q]) continue;
-        const u32 j = atomicAdd(&S.nc, 1u);
-        if (j < SPEC_LDS) { S.cf[j] = f[q]; S.cm[j] = M[i0 + (u64)q * FB]; }
-      }
-    }
-    __syncthreads();
-    const u32 nc = S.nc;
-    if (nc <= SPEC_LDS) {
-      const u64 *cf = S.cf, *cm = S.cm;
-      fp90[s] = coverage90((u64)nc, N, [cf, cm](u64 i, u64 &f, u64 &m) { f = cf[i]; m = cm[i]; }, S);
-    } else {
-      fp90[s] = coverage90((u64)A.sp_cap, N,
-                           [F, M](u64 i, u64 &f, u64 &m) { f = F[i]; m = f ? M[i] : 0; }, S);
-    }
-  }
 
   // ---- branches
   const u32 *ss = A.seg_start, *se = A.seg_end;
@@ -288,26 +332,8 @@ __global__ void __launch_bounds__(FB) k_finalize(TraceArgs A0, const TraceArgs *
       : coverage90((u64)A.n_sites, A.n_branch,
                    [ss, se](u64 i, u64 &f, u64 &m) { f = se[i] - ss[i]; m = f ? 1 : 0; }, S);
 
-  // ---- exports: class histogram and the level-0 spectra
+  // ---- export: class histogram
   for (u32 c = tid; c < A.n_classes; c += FB) A.out_class_hist[c] = A.class_hist[c];
-  __syncthreads();
-  if (tid == 0) { S.bcast[1] = 0; S.bcast[2] = 0; }
-  __syncthreads();
-  for (int s = 0; s < 2; ++s) {
-    const u64 *F = A.sp_f + (u64)s * A.sp_cap, *M = A.sp_m + (u64)s * A.sp_cap;
-    u64 *dst = A.out_spec + (u64)s * 2 * A.spec_export_cap;
-    for (u64 i0 = tid; i0 < A.sp_cap; i0 += 8 * FB) {
-      u64 f[8];
-#pragma unroll
-      for (int q = 0; q < 8; ++q) f[q] = i0 + (u64)q * FB < A.sp_cap ? F[i0 + (u64)q * FB] : 0;
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        if (!f[q]) continue;
-        const u64 j = atomicAdd((u64 *)&S.bcast[1 + s], 1ull);
-        if (j < A.spec_export_cap) { dst[2 * j] = f[q]; dst[2 * j + 1] = M[i0 + (u64)q * FB]; }
-      }
-    }
-  }
   __syncthreads();
 
   if (tid != 0) return;
@@ -342,7 +368,6 @@ __global__ void __launch_bounds__(FB) k_finalize(TraceArgs A0, const TraceArgs *
   o->itb_median = itb_med;
   o->ipt_min = acc->ipt_cnt ? ~acc->ipt_min_inv : 0;
   o->ipt_max = acc->ipt_max;
-  o->ipt_median = ipt_med;
   for (int s = 0; s < 2; ++s) {
     aiwc_space_metrics &m = o->space[s];
     const u64 N = acc->sp_reads[s] + acc->sp_writes[s];
@@ -352,7 +377,6 @@ __global__ void __launch_bounds__(FB) k_finalize(TraceArgs A0, const TraceArgs *
     m.unique_reads = acc->uniq_r[s];
     m.unique_writes = acc->uniq_w[s];
     m.footprint = acc->distinct[s][0];
-    m.footprint_90 = fp90[s];
     for (int k = 0; k < AIWC_NSKIP; ++k) {
       m.distinct[k] = acc->distinct[s][k];
       m.entropy[k] = N ? fx64_to_double(acc->ent_lo[s][k], acc->ent_hi[s][k]) / (double)N : 0.0;
@@ -390,7 +414,6 @@ __global__ void __launch_bounds__(FB) k_finalize(TraceArgs A0, const TraceArgs *
   status[0] = acc->bad_ids + acc->bad_mem;
   status[3] = acc->split_fail;
   status[1] = (nload + nstore + 2 * natom != A.n_mem || nbr != A.n_branch) ? 1ull : 0ull;
-  status[2] = S.bcast[1] | (S.bcast[2] << 32);
 }
 
 }  // namespace
@@ -398,8 +421,8 @@ __global__ void __launch_bounds__(FB) k_finalize(TraceArgs A0, const TraceArgs *
 namespace aiwc_kernels {
 
 hipError_t launch_finalize(const TraceArgs &a, const BatchDims &d, hipStream_t s, StageMarks *pm) {
-  if (d.batch) hipLaunchKernelGGL(k_finalize<true>, dim3(1, d.n), dim3(FB), 0, s, a, d.batch);
-  else hipLaunchKernelGGL(k_finalize<false>, dim3(1), dim3(FB), 0, s, a, nullptr);
+  if (d.batch) hipLaunchKernelGGL(k_finalize<true>, dim3(3, d.n), dim3(FB), 0, s, a, d.batch);
+  else hipLaunchKernelGGL(k_finalize<false>, dim3(3), dim3(FB), 0, s, a, nullptr);
   AIWC_MARK(pm, "k_finalize", s);
   return hipGetLastError();
 }
