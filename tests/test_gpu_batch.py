@@ -1,6 +1,8 @@
 """Batched path: bit-identical to the single-trace path and to the oracle,
 with and without a captured hipGraph, across admission waves and forced
 partition overflow (run with -m gpu)."""
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -8,6 +10,7 @@ import oracle
 import tracegen as tg
 from oracle.compare import compare
 from gpu_util import same
+from helpers import COMPUTE, DEFAULT_TABLE, random_trace, table
 
 pytestmark = pytest.mark.gpu
 
@@ -108,3 +111,40 @@ def test_graph_cache_after_destroy_and_recreate():
         assert not bad, "\n".join(bad[:10])
         t.close()
         del dev
+
+
+def _wide(tr, n_ids, rng):
+    """The trace with half of its compute instructions moved to the compute
+    ids 10 .. n_ids - 1 of a wider table (kinds unchanged, so still consistent)."""
+    if n_ids == len(DEFAULT_TABLE):
+        return tr
+    tab = table([tuple(e) for e in DEFAULT_TABLE.tolist()] +
+                [(4 + i % 5, 1 + i % 7, COMPUTE) for i in range(n_ids - len(DEFAULT_TABLE))])
+    op = tr.opcode.copy()
+    move = (op < 4) & (rng.random(op.size) < 0.5)
+    op[move] = rng.integers(len(DEFAULT_TABLE), n_ids, size=int(move.sum()))
+    return dataclasses.replace(tr, opcode=op, table=tab)
+
+
+@pytest.mark.parametrize("with_global", [False, True])
+def test_batch_mixed_opcode_tables(with_global):
+    # one batch over traces whose opcode tables differ in size: the ops
+    # kernel's LDS is sized for the largest need of any trace (the counter
+    # copies per id shrink as a table grows), and a table above 8192 ids
+    # sends the whole batch to the global-memory histogram
+    import paper_1805_04207_amd as aiwc
+    from gpu_util import ctx
+    sizes = [10, 66, 300, 520, 4100] + ([10000] if with_global else [])
+    rng = np.random.default_rng(31)
+    hosts = [_wide(random_trace(rng, 200, 300, 7, 5), n, rng) for n in sizes]
+    c = ctx()
+    keep, trs = [], []
+    for h in hosts:
+        dev = aiwc.host_to_device(h, 0)
+        keep.append(dev)
+        trs.append(aiwc.device_trace(c, dev, h.table, int(h.n_sites), int(h.history_len), 0))
+    got = [m.read() for m in c.characterize_batch(trs)]
+    for n, h, t, g in zip(sizes, hosts, trs, got):
+        assert same(g, c.characterize(t).read(), drop=()), f"{n} ids: batch differs from single"
+        bad = compare(g, oracle.characterize(h))
+        assert not bad, f"{n} ids:\n" + "\n".join(bad[:10])
