@@ -49,6 +49,7 @@ constexpr int MEM_BLOCK = 1024;
 constexpr u32 FINE_BITS = 8;
 constexpr int SC_BLOCK = 1024;
 constexpr u32 SC_T = 8192;                 // records per tile (8 per thread)
+static_assert(SC_T <= (1u << 24), "a rank travels above an 8-bit digit in 32 bits");
 constexpr u32 SPEC_SLOTS = 64;    // per-space LDS cache of the level-0 spectrum
 constexpr u64 EMPTY = ~0ull;
 
@@ -314,10 +315,13 @@ __device__ __forceinline__ void tile_scan(TileShared &S) {
 
 // Stage the tile's records by digit and write them out in runs: dst[gbase[d]
 // + rank among the tile's records of digit d].  Every thread calls it with
-// its own records (nv of them, digits dg).  TOP: the digit is the record's
-// top byte, cleared on the way out (no digit array in LDS).
-template <int R, bool TOP>
-__device__ __forceinline__ void tile_write(TileShared &S, const u64 (&rec)[R], const u32 (&dg)[R],
+// its own records (nv of them), dk = digit | rank << 8.  RANKED: the rank is
+// the value the record's counting atomic returned, so no second atomic is
+// needed; otherwise dk holds the digit alone and the ranks come from atomics
+// after the scan.  TOP: the digit is the record's top byte, cleared on the
+// way out (no digit array in LDS).
+template <int R, bool TOP, bool RANKED>
+__device__ __forceinline__ void tile_write(TileShared &S, const u64 (&rec)[R], const u32 (&dk)[R],
                                            int nv, u32 n, u64 *dst, u32 ndig, u32 *cursor) {
   const int tid = threadIdx.x;
   __syncthreads();
@@ -326,15 +330,16 @@ __device__ __forceinline__ void tile_write(TileShared &S, const u64 (&rec)[R], c
   if (tid < (int)ndig) {
     const u32 c = S.cnt[tid];
     if (c) S.gbase[tid] = atomicAdd(&cursor[tid], c);
-    S.cnt[tid] = S.start[tid];
+    if (!RANKED) S.cnt[tid] = S.start[tid];
   }
   __syncthreads();
 #pragma unroll
   for (int j = 0; j < R; ++j) {
     if (j < nv) {
-      const u32 r = atomicAdd(&S.cnt[dg[j]], 1u);
+      const u32 d = dk[j] & 255u;
+      const u32 r = RANKED ? S.start[d] + (dk[j] >> 8) : atomicAdd(&S.cnt[d], 1u);
       S.stage[r] = rec[j];
-      if (!TOP) S.dig[r] = (uint8_t)dg[j];
+      if (!TOP) S.dig[r] = (uint8_t)d;
     }
   }
   __syncthreads();
@@ -381,20 +386,21 @@ __global__ void __launch_bounds__(SC_BLOCK, 8) k_mem_scatter_a(TraceArgs A0, con
       }
     }
     u64 rec[8];
-    u32 dg[8];
+    u32 dk[8];   // the coarse digit (ranked after the scan: the ranks'
+                 // registers would spill here, and ranking early gained nothing)
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       rec[j] = 0;
-      dg[j] = 0;
+      dk[j] = 0;
       if (j < nv) {
         u32 bin;
         const uint8_t k = (uint8_t)((j < 4 ? kk2.x : kk2.y) >> (8 * (j & 3)));
         rec[j] = make_record(a[j], k, A.pbits, bin) | ((u64)(bin & 255u) << 56);
-        dg[j] = bin >> FINE_BITS;
-        atomicAdd(&S.cnt[dg[j]], 1u);
+        dk[j] = bin >> FINE_BITS;
+        atomicAdd(&S.cnt[dk[j]], 1u);
       }
     }
-    tile_write<8, false>(S, rec, dg, nv, n, A.part_tmp, NC, ccur);
+    tile_write<8, false, false>(S, rec, dk, nv, n, A.part_tmp, NC, ccur);
   }
 }
 
@@ -423,23 +429,23 @@ __global__ void __launch_bounds__(SC_BLOCK, 8) k_mem_scatter_b(TraceArgs A0, con
     if (tid < 256) S.cnt[tid] = 0;
     __syncthreads();
     u64 rec[8];
-    u32 dg[8];
+    u32 dk[8];   // fine digit | rank << 8
     int nv = 0;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       // record j of this thread: t0 + j * SC_BLOCK + tid (coalesced)
       const u32 k = (u32)j * SC_BLOCK + (u32)tid;
       rec[j] = 0;
-      dg[j] = 0;
+      dk[j] = 0;
       if (k < n) {
         const u64 r = A.part_tmp[t0 + k];
-        dg[j] = (u32)(r >> 56);
+        const u32 d = (u32)(r >> 56);
         rec[j] = r;   // the fine digit stays in the top byte until written out
-        atomicAdd(&S.cnt[dg[j]], 1u);
+        dk[j] = d | (atomicAdd(&S.cnt[d], 1u) << 8);
         nv = j + 1;
       }
     }
-    tile_write<8, true>(S, rec, dg, nv, n, A.part_rec, 256u, A.part_cur + (c << FINE_BITS));
+    tile_write<8, true, true>(S, rec, dk, nv, n, A.part_rec, 256u, A.part_cur + (c << FINE_BITS));
   }
 }
 
