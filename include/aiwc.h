@@ -494,7 +494,9 @@ aiwc_status aiwc_profile_read(aiwc_ctx *ctx, char *names, size_t names_cap,
  * (exact prefix distinct counts per space and skip, the growth of the
  * distinct count over the prefix, spans, alignment and locality fractions,
  * and the trace's sizes).  The predictions size the memory partitions;
- * overflow is redone, so results never depend on them.
+ * overflow is redone, so results never depend on them.  A trace of more
+ * than 2^27 memory events gets the most partitions from its record count
+ * alone; batched sizing computes no features for it.
  */
 #define AIWC_N_FEATURES 40
 #define AIWC_N_TARGETS 11

@@ -684,25 +684,40 @@ aiwc_status sizer_plan_pbits(aiwc_ctx *ctx, const aiwc_trace *const *traces, siz
     ctx_error(ctx, "LEARNED sizing needs a trained or loaded sizing network");
     return AIWC_ERR_INVALID_ARG;
   }
+  // a trace whose record count alone asks for the most partitions gets them
+  // whatever its page count: its features would not change the answer
+  std::vector<const aiwc_trace *> sub;
+  std::vector<size_t> idx;
+  for (size_t i = 0; i < n; ++i) {
+    if (pbits_for_pages(1.0, (double)traces[i]->d.n_mem) >= 15) {
+      pbits[i] = 15;
+    } else {
+      sub.push_back(traces[i]);
+      idx.push_back(i);
+    }
+  }
+  const size_t m = sub.size();
+  if (m == 0) return AIWC_OK;
   float *feat = nullptr, *pred = nullptr;
-  if (hipMalloc(&feat, 4 * n * NF) != hipSuccess || hipMalloc(&pred, 4 * n * NT) != hipSuccess) {
+  if (hipMalloc(&feat, 4 * m * NF) != hipSuccess || hipMalloc(&pred, 4 * m * NT) != hipSuccess) {
     hipGetLastError();
     hipFree(feat);
     ctx_error(ctx, "out of device memory for sizing");
     return AIWC_ERR_OUT_OF_MEMORY;
   }
-  aiwc_status st = features_impl(ctx, traces, n, s, feat);
-  if (st == AIWC_OK && mode == AIWC_SIZING_LEARNED) st = aiwc_sizer_predict(ctx, feat, n, s, pred);
-  std::vector<float> hf(n * NF), hp(n * NT);
+  aiwc_status st = features_impl(ctx, sub.data(), m, s, feat);
+  if (st == AIWC_OK && mode == AIWC_SIZING_LEARNED) st = aiwc_sizer_predict(ctx, feat, m, s, pred);
+  std::vector<float> hf(m * NF), hp(m * NT);
   if (st == AIWC_OK) {
-    hipMemcpy(hf.data(), feat, 4 * n * NF, hipMemcpyDeviceToHost);
-    if (mode == AIWC_SIZING_LEARNED) hipMemcpy(hp.data(), pred, 4 * n * NT, hipMemcpyDeviceToHost);
+    hipMemcpy(hf.data(), feat, 4 * m * NF, hipMemcpyDeviceToHost);
+    if (mode == AIWC_SIZING_LEARNED) hipMemcpy(hp.data(), pred, 4 * m * NT, hipMemcpyDeviceToHost);
   }
   hipFree(feat);
   hipFree(pred);
   if (st != AIWC_OK) return st;
-  for (size_t i = 0; i < n; ++i) {
-    const float *f = &hf[i * NF];
+  for (size_t k = 0; k < m; ++k) {
+    const size_t i = idx[k];
+    const float *f = &hf[k * NF];
     const double nmem = (double)traces[i]->d.n_mem;
     const double npref = std::exp2((double)f[34]) - 1.0;
     const double scale = npref > 0 ? nmem / npref : 1.0;
@@ -712,7 +727,7 @@ aiwc_status sizer_plan_pbits(aiwc_ctx *ctx, const aiwc_trace *const *traces, siz
     const double loc = std::min(nmem, (std::exp2((double)f[29]) - 1.0) * scale);
     double glob;
     if (mode == AIWC_SIZING_LEARNED)
-      glob = std::exp2((double)hp[i * NT + 10] + ctx->sizer->margin) - 1.0;
+      glob = std::exp2((double)hp[k * NT + 10] + ctx->sizer->margin) - 1.0;
     else
       glob = (std::exp2((double)f[18]) - 1.0) * scale;
     glob = std::min(glob, nmem);
