@@ -1,6 +1,7 @@
 """Learned sizing: prefix features vs a numpy restatement, MLP gradients vs
 the FP64 reference, training on exact-path labels, and the gain of LEARNED
-over BOUND sizing with identical metrics (run with -m gpu)."""
+over BOUND sizing with identical metrics, and of the shipped network over
+the heuristic (run with -m gpu)."""
 import numpy as np
 import pytest
 
@@ -93,3 +94,19 @@ def test_train_and_learned_sizing_gain(tmp_path):
     print("bound", sb, "learned", sl, flush=True)
     assert sl["total_partitions"] < sb["total_partitions"]
     assert sl["reserved_bytes"] <= sb["reserved_bytes"]
+
+
+def test_shipped_network_beats_the_heuristic():
+    # the shipped weights on held-out traces of the family they were trained
+    # on (another seed): fewer partitions than the heuristic (the sizing
+    # without the network) and than the bound, identical metrics under all
+    # three policies
+    from paper_1805_04207_amd.train_sizer import DEFAULT_WEIGHTS, evaluate
+    from gpu_util import ctx
+    c = ctx()
+    c.sizer_load(DEFAULT_WEIGHTS)
+    out = evaluate(c, 48, 5, 12.0, 16.0)
+    print({k: out[k]["partitions"] for k in ("bound", "heuristic", "learned")}, flush=True)
+    for k in ("bound", "heuristic", "learned"):
+        assert out[k]["identical_metrics"], k
+    assert out["learned"]["partitions"] < out["heuristic"]["partitions"] < out["bound"]["partitions"]
