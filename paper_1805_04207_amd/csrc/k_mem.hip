@@ -415,7 +415,13 @@ __global__ void __launch_bounds__(SC_BLOCK, 8) k_mem_scatter_b(TraceArgs A0, con
   for (u32 c = tid; c <= NC; c += SC_BLOCK) S.tst[c] = tst_g[c];
   __syncthreads();
   const u32 ntiles = S.tst[NC];
-  for (u32 t = blockIdx.x; t < ntiles; t += gridDim.x) {
+  // blocks are dealt to the 8 XCDs in turn; the blocks of one XCD take one
+  // contiguous eighth of the tiles, so that a coarse bucket's cursors and
+  // its partitions' write runs stay with one XCD's L2
+  const u32 X = (gridDim.x % 8u == 0) ? 8u : 1u;
+  const u32 xcd = blockIdx.x % X, per = gridDim.x / X;
+  const u32 t_lo = (u32)((u64)ntiles * xcd / X), t_hi = (u32)((u64)ntiles * (xcd + 1) / X);
+  for (u32 t = t_lo + blockIdx.x / X; t < t_hi; t += per) {
     // the coarse bucket of tile t: the last c with tst[c] <= t
     u32 lo = 0, hi = NC;
     while (hi - lo > 1) {
