@@ -360,7 +360,12 @@ __global__ void __launch_bounds__(SC_BLOCK, 8) k_mem_scatter_a(TraceArgs A0, con
   const u32 P = 1u << A.pbits, NC = P >> FINE_BITS;
   u32 *ccur = A.part_cur + P;
   const u64 ntiles = (A.n_mem + SC_T - 1) / SC_T;
-  for (u64 t = blockIdx.x; t < ntiles; t += gridDim.x) {
+  // the blocks of one XCD take one contiguous eighth of the tiles (as in
+  // pass B)
+  const u32 X = (gridDim.x % 8u == 0) ? 8u : 1u;
+  const u32 xcd = blockIdx.x % X, per = gridDim.x / X;
+  const u64 t_lo = ntiles * xcd / X, t_hi = ntiles * (xcd + 1) / X;
+  for (u64 t = t_lo + blockIdx.x / X; t < t_hi; t += per) {
     const u64 t0 = t * SC_T;
     const u32 n = (u32)((A.n_mem - t0) < SC_T ? (A.n_mem - t0) : SC_T);
     if (tid < 256) S.cnt[tid] = 0;
